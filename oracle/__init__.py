@@ -1,0 +1,233 @@
+"""FP64 CPU oracle for the cell-centred multigrid (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+(``paper_1306_6883_amd``) and never imports it.
+
+Two parts:
+
+* the multigrid algorithm itself, step by step, in plain C
+  (``mg_oracle.c``; pyro paper Sec. 3.3), wrapped here with ctypes;
+* exact discrete solutions (``oracle.exact``): dense direct solves and
+  fast-transform solves of the same 5-point operator.
+
+Fields are numpy float64 arrays of shape (n+2, n+2): row index j+1, column
+index i+1 for valid cell (i, j), x contiguous, one ghost layer.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mg_oracle.c")
+_LIB = os.path.join(_HERE, "libmg_oracle.so")
+
+DIRICHLET, NEUMANN, PERIODIC = 0, 1, 2
+_BC_CODES = {"D": DIRICHLET, "N": NEUMANN, "P": PERIODIC,
+             DIRICHLET: DIRICHLET, NEUMANN: NEUMANN, PERIODIC: PERIODIC}
+OK, NOT_CONVERGED, EINVAL = 0, 1, -1
+HISTORY = 256
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (FP contraction off, OpenMP on)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("h", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("bc", ctypes.c_int * 4), ("nu1", ctypes.c_int),
+                ("nu2", ctypes.c_int), ("nu_bottom", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("rtol", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("rel_resid0", ctypes.c_double), ("rel_resid", ctypes.c_double),
+                ("history", ctypes.c_double * HISTORY)]
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.og_fill.argtypes = [ctypes.c_int, ip, dp]
+        lib.og_smooth.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ip, dp, dp, ctypes.c_int]
+        lib.og_residual.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ip, dp, dp, dp]
+        lib.og_restrict.argtypes = [ctypes.c_int, dp, dp]
+        lib.og_prolong_add.argtypes = [ctypes.c_int, ip, dp, dp]
+        lib.og_norm.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        lib.og_norm.restype = ctypes.c_double
+        lib.og_mean.argtypes = [ctypes.c_int, dp]
+        lib.og_mean.restype = ctypes.c_double
+        lib.og_vcycle.argtypes = [ctypes.POINTER(_Params), dp, dp]
+        lib.og_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
+                                 ctypes.POINTER(_Result)]
+        lib.og_smooth_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
+                                        ctypes.POINTER(_Result)]
+        _lib_handle = lib
+    return _lib_handle
+
+
+def bc_codes(bc) -> tuple:
+    """Normalise a BC spec: a 4-tuple (xlo, xhi, ylo, yhi) of 'D'/'N'/'P' or ints,
+    or a single letter for all sides."""
+    if isinstance(bc, str) and len(bc) == 1:
+        bc = (bc,) * 4
+    out = tuple(_BC_CODES[b] for b in bc)
+    if len(out) != 4:
+        raise ValueError("bc needs four sides")
+    if (out[0] == PERIODIC) != (out[1] == PERIODIC) or (out[2] == PERIODIC) != (out[3] == PERIODIC):
+        raise ValueError("periodic must pair opposite sides")
+    return out
+
+
+@dataclass
+class Problem:
+    """(alpha - beta Lap) phi = f on an n x n grid of square cells of width h."""
+    n: int
+    h: float
+    alpha: float = 0.0
+    beta: float = -1.0
+    bc: tuple = ("D", "D", "D", "D")
+    nu1: int = 2
+    nu2: int = 2
+    nu_bottom: int = 50
+    max_cycles: int = 100
+    rtol: float = 1e-10
+
+    def _c(self) -> _Params:
+        p = _Params()
+        p.n, p.h, p.alpha, p.beta = self.n, self.h, self.alpha, self.beta
+        p.bc[:] = list(bc_codes(self.bc))
+        p.nu1, p.nu2, p.nu_bottom = self.nu1, self.nu2, self.nu_bottom
+        p.max_cycles, p.rtol = self.max_cycles, self.rtol
+        return p
+
+    @property
+    def singular(self) -> bool:
+        return self.alpha == 0.0 and DIRICHLET not in bc_codes(self.bc)
+
+
+@dataclass
+class Result:
+    status: int
+    cycles: int
+    rel_resid0: float
+    rel_resid: float
+    history: list = field(default_factory=list)
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _bcp(bc):
+    arr = (ctypes.c_int * 4)(*bc_codes(bc))
+    return arr
+
+
+def field_zeros(n: int) -> np.ndarray:
+    return np.zeros((n + 2, n + 2), dtype=np.float64)
+
+
+def embed(valid: np.ndarray) -> np.ndarray:
+    """Place an (n, n) array of valid cells (index [j, i]) into a ghosted field."""
+    n = valid.shape[0]
+    a = field_zeros(n)
+    a[1:n + 1, 1:n + 1] = valid
+    return a
+
+
+def interior(a: np.ndarray) -> np.ndarray:
+    n = a.shape[0] - 2
+    return a[1:n + 1, 1:n + 1]
+
+
+def fill(a: np.ndarray, bc) -> np.ndarray:
+    _lib().og_fill(a.shape[0] - 2, _bcp(bc), _ptr(a))
+    return a
+
+
+def smooth(p: Problem, phi: np.ndarray, f: np.ndarray, iters: int, level: int = 0) -> np.ndarray:
+    n, h = p.n >> level, p.h * (1 << level)
+    assert phi.shape == (n + 2, n + 2) and f.shape == phi.shape
+    _lib().og_smooth(n, h, p.alpha, p.beta, _bcp(p.bc), _ptr(phi), _ptr(f), iters)
+    return phi
+
+
+def residual(p: Problem, phi: np.ndarray, f: np.ndarray, level: int = 0) -> np.ndarray:
+    n, h = p.n >> level, p.h * (1 << level)
+    r = field_zeros(n)
+    _lib().og_residual(n, h, p.alpha, p.beta, _bcp(p.bc), _ptr(phi), _ptr(f), _ptr(r))
+    return r
+
+
+def restrict(fine: np.ndarray) -> np.ndarray:
+    n = fine.shape[0] - 2
+    c = field_zeros(n // 2)
+    _lib().og_restrict(n, _ptr(fine), _ptr(c))
+    return c
+
+
+def prolong_add(coarse: np.ndarray, fine: np.ndarray, bc) -> np.ndarray:
+    _lib().og_prolong_add(coarse.shape[0] - 2, _bcp(bc), _ptr(coarse), _ptr(fine))
+    return fine
+
+
+def norm(a: np.ndarray, h: float) -> float:
+    return _lib().og_norm(a.shape[0] - 2, h, _ptr(a))
+
+
+def mean(a: np.ndarray) -> float:
+    return _lib().og_mean(a.shape[0] - 2, _ptr(a))
+
+
+def vcycle(p: Problem, phi: np.ndarray, f: np.ndarray) -> np.ndarray:
+    st = _lib().og_vcycle(ctypes.byref(p._c()), _ptr(phi), _ptr(f))
+    if st != OK:
+        raise ValueError("oracle vcycle: bad problem")
+    return phi
+
+
+def _result(r: _Result) -> Result:
+    hist = [r.history[i] for i in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist)
+
+
+def solve(p: Problem, f: np.ndarray, phi: np.ndarray | None = None):
+    """V-cycles until ||r||/||f|| <= rtol.  Returns (phi, Result)."""
+    use_guess = phi is not None
+    phi = field_zeros(p.n) if phi is None else phi
+    res = _Result()
+    st = _lib().og_solve(ctypes.byref(p._c()), _ptr(phi), _ptr(f), int(use_guess), ctypes.byref(res))
+    if st == EINVAL:
+        raise ValueError("oracle solve: bad problem")
+    return phi, _result(res)
+
+
+def smooth_solve(p: Problem, f: np.ndarray, max_iters: int, phi: np.ndarray | None = None):
+    """Relaxation only (no coarse grids) until the same stopping rule holds."""
+    phi = field_zeros(p.n) if phi is None else phi
+    res = _Result()
+    _lib().og_smooth_solve(ctypes.byref(p._c()), _ptr(phi), _ptr(f), max_iters, ctypes.byref(res))
+    return phi, _result(res)

@@ -1,0 +1,311 @@
+/*
+ * mg_oracle.c -- plain FP64 CPU multigrid for the cell-centred
+ * constant-coefficient Helmholtz problem  (alpha - beta Lap) phi = f.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * judged against.  Only tests/, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code, header, table or constant
+ * with the GPU library and includes nothing from it.
+ *
+ * What it follows (pyro paper, Sec. 3.3 "Multigrid"):
+ *   - the operator of Eq. (helmholtz); Poisson is (alpha, beta) = (0, -1);
+ *   - the second difference of Sec. 2 ("Design"), applied along x and y with
+ *     the same spacing (square cells);
+ *   - red-black Gauss-Seidel relaxation; restriction = mean of the four fine
+ *     cells; prolongation = centred slopes in x and y of each coarse cell,
+ *     bilinear without the xy cross term;
+ *   - homogeneous ghost cells: Dirichlet  phi[lo-1] = -phi[lo],
+ *     Neumann phi[lo-1] = +phi[lo] (the two ghost-cell equations of Sec. 3.3);
+ *     periodic (not in the paper; needed by the periodic workloads) wraps;
+ *   - pure V-cycles down to a 2x2 grid, solved there by relaxation only
+ *     (50 sweeps by default);
+ *   - stop when ||r||_2 / ||f||_2 falls to the tolerance (Poisson test
+ *     problem, Sec. 3.3.1).
+ * Where the paper is silent the readings are: red = (i+j) even (0-based),
+ * red first; ghosts refreshed before each colour; V(nu1, nu2) with the counts
+ * given by the caller; coarse operators re-discretised with h_l = 2^l h and
+ * the same alpha, beta; coarse levels use the homogeneous version of the
+ * finest BC types; L2 norms are sqrt(h^2 sum v^2) over valid cells; the stop
+ * test runs before every cycle and uses "<="; zero initial guess unless one
+ * is given.  Singular problems (alpha == 0 and no Dirichlet side): the mean of
+ * each restricted coarse right-hand side is removed and the mean of phi is
+ * pinned to zero after each cycle.
+ *
+ * Storage: every field is (n+2) x (n+2) doubles, row-major, x contiguous,
+ * one ghost layer; valid cell (i, j) (0 <= i, j < n) lives at
+ * a[(j+1)*(n+2) + (i+1)].  Corner ghosts are never read or written.
+ *
+ * Parallelism: the only OpenMP use is over rows inside one colour of a
+ * sweep (cells of one colour are independent) and over rows of pointwise
+ * passes.  Sums are formed per row and then added in row order, so every
+ * result is independent of the thread count.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "mg_oracle.h"
+
+#define IDX(n, i, j) ((size_t)((j) + 1) * (size_t)((n) + 2) + (size_t)((i) + 1))
+
+static int is_singular(double alpha, const int bc[4]) {
+    if (alpha != 0.0) return 0;
+    for (int s = 0; s < 4; ++s)
+        if (bc[s] == OG_DIRICHLET) return 0;
+    return 1;
+}
+
+/* Ghost cells of one side-type: Dirichlet -> minus the adjacent valid cell,
+ * Neumann -> plus it, periodic -> the valid cell on the opposite side. */
+void og_fill(int n, const int bc[4], double *a) {
+    for (int j = 0; j < n; ++j) {
+        /* x-lo ghost (i = -1) and x-hi ghost (i = n) */
+        double lo = a[IDX(n, 0, j)], hi = a[IDX(n, n - 1, j)];
+        a[IDX(n, -1, j)] = bc[OG_XLO] == OG_PERIODIC ? hi : (bc[OG_XLO] == OG_DIRICHLET ? -lo : lo);
+        a[IDX(n, n, j)] = bc[OG_XHI] == OG_PERIODIC ? lo : (bc[OG_XHI] == OG_DIRICHLET ? -hi : hi);
+    }
+    for (int i = 0; i < n; ++i) {
+        double lo = a[IDX(n, i, 0)], hi = a[IDX(n, i, n - 1)];
+        a[IDX(n, i, -1)] = bc[OG_YLO] == OG_PERIODIC ? hi : (bc[OG_YLO] == OG_DIRICHLET ? -lo : lo);
+        a[IDX(n, i, n)] = bc[OG_YHI] == OG_PERIODIC ? lo : (bc[OG_YHI] == OG_DIRICHLET ? -hi : hi);
+    }
+}
+
+/* One colour of Gauss-Seidel: every cell with (i+j)%2 == colour solves its
+ * own row of (alpha - beta Lap) phi = f for phi_ij with the neighbours held:
+ *   phi_ij = (f_ij + (beta/h^2)(phiE + phiW + phiN + phiS)) / (alpha + 4 beta/h^2) */
+static void relax_colour(int n, double h, double alpha, double beta, const int bc[4],
+                         double *phi, const double *f, int colour) {
+    og_fill(n, bc, phi);
+    const double c = beta / (h * h);
+    const double diag = alpha + 4.0 * c;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        for (int i = (j + colour) & 1; i < n; i += 2) {
+            double nb = phi[IDX(n, i + 1, j)] + phi[IDX(n, i - 1, j)] + phi[IDX(n, i, j + 1)] +
+                        phi[IDX(n, i, j - 1)];
+            phi[IDX(n, i, j)] = (f[IDX(n, i, j)] + c * nb) / diag;
+        }
+    }
+}
+
+void og_smooth(int n, double h, double alpha, double beta, const int bc[4], double *phi,
+               const double *f, int iters) {
+    for (int it = 0; it < iters; ++it) {
+        relax_colour(n, h, alpha, beta, bc, phi, f, 0); /* red   */
+        relax_colour(n, h, alpha, beta, bc, phi, f, 1); /* black */
+    }
+}
+
+/* r = f - (alpha phi - beta Lap phi), Lap written as differences from the
+ * centre to limit cancellation. */
+void og_residual(int n, double h, double alpha, double beta, const int bc[4], double *phi,
+                 const double *f, double *r) {
+    og_fill(n, bc, phi);
+    const double ih2 = 1.0 / (h * h);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            double p = phi[IDX(n, i, j)];
+            double lap = ((phi[IDX(n, i + 1, j)] - p) + (phi[IDX(n, i - 1, j)] - p) +
+                          (phi[IDX(n, i, j + 1)] - p) + (phi[IDX(n, i, j - 1)] - p)) * ih2;
+            r[IDX(n, i, j)] = f[IDX(n, i, j)] - (alpha * p - beta * lap);
+        }
+    }
+}
+
+/* coarse(I, J) = mean of fine (2I..2I+1, 2J..2J+1); fine has n cells/side. */
+void og_restrict(int n, const double *fine, double *coarse) {
+    int nc = n / 2;
+#pragma omp parallel for schedule(static)
+    for (int J = 0; J < nc; ++J)
+        for (int I = 0; I < nc; ++I)
+            coarse[IDX(nc, I, J)] =
+                0.25 * (fine[IDX(n, 2 * I, 2 * J)] + fine[IDX(n, 2 * I + 1, 2 * J)] +
+                        fine[IDX(n, 2 * I, 2 * J + 1)] + fine[IDX(n, 2 * I + 1, 2 * J + 1)]);
+}
+
+/* fine += P coarse.  Centred slopes of each coarse cell (ghosts from the
+ * homogeneous BCs), then each of the four fine cells, which sit a quarter
+ * coarse width from the coarse centre, gets e + dx*mx + dy*my with
+ * dx, dy = -1/4 or +1/4 and mx, my the centred differences per coarse cell. */
+void og_prolong_add(int nc, const int bc[4], double *coarse, double *fine) {
+    int n = 2 * nc;
+    og_fill(nc, bc, coarse);
+#pragma omp parallel for schedule(static)
+    for (int J = 0; J < nc; ++J) {
+        for (int I = 0; I < nc; ++I) {
+            double e = coarse[IDX(nc, I, J)];
+            double mx = 0.5 * (coarse[IDX(nc, I + 1, J)] - coarse[IDX(nc, I - 1, J)]);
+            double my = 0.5 * (coarse[IDX(nc, I, J + 1)] - coarse[IDX(nc, I, J - 1)]);
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    double dx = a ? 0.25 : -0.25, dy = b ? 0.25 : -0.25;
+                    fine[IDX(n, 2 * I + a, 2 * J + b)] += e + dx * mx + dy * my;
+                }
+        }
+    }
+}
+
+/* Sum over valid cells, formed per row then over rows in order. */
+static double valid_sum(int n, const double *a, int squares) {
+    double *row = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double v = a[IDX(n, i, j)];
+            s += squares ? v * v : v;
+        }
+        row[j] = s;
+    }
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += row[j];
+    free(row);
+    return s;
+}
+
+double og_norm(int n, double h, const double *a) { return sqrt(h * h * valid_sum(n, a, 1)); }
+
+double og_mean(int n, const double *a) { return valid_sum(n, a, 0) / ((double)n * (double)n); }
+
+static void add_const(int n, double *a, double c) {
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) a[IDX(n, i, j)] += c;
+}
+
+size_t og_field_len(int n) { return (size_t)(n + 2) * (size_t)(n + 2); }
+
+/* Recursive V(nu1, nu2) cycle on level `lev` of the hierarchy.  phi[l] and
+ * f[l] hold the level-l fields; r is scratch of the finest size. */
+static void vcycle(const og_params *p, int lev, double **phi, double **f, double *r, int singular) {
+    int n = p->n >> lev;
+    double h = p->h * (double)(1 << lev);
+    if (n == 2) {
+        og_smooth(n, h, p->alpha, p->beta, p->bc, phi[lev], f[lev], p->nu_bottom);
+        return;
+    }
+    og_smooth(n, h, p->alpha, p->beta, p->bc, phi[lev], f[lev], p->nu1);
+    og_residual(n, h, p->alpha, p->beta, p->bc, phi[lev], f[lev], r);
+    og_restrict(n, r, f[lev + 1]);
+    if (singular) add_const(n / 2, f[lev + 1], -og_mean(n / 2, f[lev + 1]));
+    memset(phi[lev + 1], 0, sizeof(double) * og_field_len(n / 2));
+    vcycle(p, lev + 1, phi, f, r, singular);
+    og_prolong_add(n / 2, p->bc, phi[lev + 1], phi[lev]);
+    og_smooth(n, h, p->alpha, p->beta, p->bc, phi[lev], f[lev], p->nu2);
+}
+
+static int num_levels(int n) {
+    int L = 0;
+    while ((n >> L) >= 2) ++L;
+    return L; /* n, n/2, ..., 2 */
+}
+
+static int valid_n(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+/* Hierarchy helpers: level 0 aliases the caller's arrays. */
+static int alloc_levels(const og_params *p, double *phi0, const double *f0, double ***phi,
+                        double ***f, double **r) {
+    int L = num_levels(p->n);
+    *phi = (double **)calloc((size_t)L, sizeof(double *));
+    *f = (double **)calloc((size_t)L, sizeof(double *));
+    *r = (double *)calloc(og_field_len(p->n), sizeof(double));
+    (*phi)[0] = phi0;
+    (*f)[0] = (double *)f0;
+    for (int l = 1; l < L; ++l) {
+        (*phi)[l] = (double *)calloc(og_field_len(p->n >> l), sizeof(double));
+        (*f)[l] = (double *)calloc(og_field_len(p->n >> l), sizeof(double));
+    }
+    return L;
+}
+
+static void free_levels(int L, double **phi, double **f, double *r) {
+    for (int l = 1; l < L; ++l) {
+        free(phi[l]);
+        free(f[l]);
+    }
+    free(phi);
+    free(f);
+    free(r);
+}
+
+int og_vcycle(const og_params *p, double *phi, const double *f) {
+    if (!valid_n(p->n)) return OG_EINVAL;
+    double **P, **F, *r;
+    int L = alloc_levels(p, phi, f, &P, &F, &r);
+    vcycle(p, 0, P, F, r, is_singular(p->alpha, p->bc));
+    free_levels(L, P, F, r);
+    return OG_OK;
+}
+
+int og_solve(const og_params *p, double *phi, const double *f, int use_guess, og_result *out) {
+    if (!valid_n(p->n)) return OG_EINVAL;
+    int n = p->n;
+    int singular = is_singular(p->alpha, p->bc);
+    if (!use_guess) memset(phi, 0, sizeof(double) * og_field_len(n));
+    memset(out, 0, sizeof(*out));
+
+    double fnorm = og_norm(n, p->h, f);
+    if (fnorm == 0.0) {
+        memset(phi, 0, sizeof(double) * og_field_len(n));
+        out->status = OG_OK;
+        return OG_OK;
+    }
+    if (singular) add_const(n, phi, -og_mean(n, phi));
+
+    double **P, **F, *r;
+    int L = alloc_levels(p, phi, f, &P, &F, &r);
+    int status = OG_NOT_CONVERGED;
+    int cycles = 0;
+    for (;;) {
+        og_residual(n, p->h, p->alpha, p->beta, p->bc, phi, f, r);
+        double rho = og_norm(n, p->h, r) / fnorm;
+        if (cycles < OG_HISTORY) out->history[cycles] = rho;
+        if (cycles == 0) out->rel_resid0 = rho;
+        out->rel_resid = rho;
+        if (rho <= p->rtol) {
+            status = OG_OK;
+            break;
+        }
+        if (cycles >= p->max_cycles) break;
+        vcycle(p, 0, P, F, r, singular);
+        if (singular) add_const(n, phi, -og_mean(n, phi));
+        ++cycles;
+    }
+    og_fill(n, p->bc, phi);
+    out->cycles = cycles;
+    out->status = status;
+    free_levels(L, P, F, r);
+    return status;
+}
+
+/* Relaxation alone (no coarse grids), the paper's first suggested exercise:
+ * whole red-black iterations until the same stopping rule holds. */
+int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_iters,
+                    og_result *out) {
+    if (!valid_n(p->n)) return OG_EINVAL;
+    int n = p->n;
+    int singular = is_singular(p->alpha, p->bc);
+    memset(out, 0, sizeof(*out));
+    double *r = (double *)calloc(og_field_len(n), sizeof(double));
+    double fnorm = og_norm(n, p->h, f);
+    int it = 0, status = OG_NOT_CONVERGED;
+    for (;;) {
+        og_residual(n, p->h, p->alpha, p->beta, p->bc, phi, f, r);
+        double rho = fnorm > 0 ? og_norm(n, p->h, r) / fnorm : 0.0;
+        out->rel_resid = rho;
+        if (rho <= p->rtol) {
+            status = OG_OK;
+            break;
+        }
+        if (it >= max_iters) break;
+        og_smooth(n, p->h, p->alpha, p->beta, p->bc, phi, f, 1);
+        if (singular) add_const(n, phi, -og_mean(n, phi));
+        ++it;
+    }
+    out->cycles = it;
+    out->status = status;
+    free(r);
+    return status;
+}
