@@ -1,0 +1,148 @@
+/*
+ * ccmg.h -- C ABI of the MI355X (gfx950) cell-centred multigrid library.
+ *
+ * Problem (pyro paper, Sec. 3.3, Eq. (helmholtz)):
+ *     (alpha - beta Lap) phi = f     on a square grid of n x n square cells,
+ * Poisson is (alpha, beta) = (0, -1).  The method: pure V-cycles of red-black
+ * Gauss-Seidel relaxation, restriction by averaging the four fine cells,
+ * prolongation by centred slopes per coarse cell (bilinear without the xy
+ * term), coarsening down to a 2 x 2 grid that is solved by relaxation alone
+ * (50 sweeps by default), stopping when ||r||_2 / ||f||_2 <= rtol
+ * (Sec. 3.3 and its Poisson test problem, Sec. 3.3.1).  Ghost cells follow
+ * the paper's homogeneous rules: Dirichlet phi[lo-1] = -phi[lo], Neumann
+ * phi[lo-1] = +phi[lo]; periodic sides wrap.
+ *
+ * Conventions for every entry point:
+ *   - Device arrays hold one grid level *with* one ghost layer: (n+2) rows of
+ *     `pitch` elements (pitch >= n+2), row-major, x contiguous; valid cell
+ *     (i, j) is element (j+1)*pitch + (i+1).  Pitches are in elements.
+ *   - Arrays are owned by the caller; the library never allocates device
+ *     memory.  Plans work inside a caller-provided workspace.
+ *   - All GPU work is enqueued on the plan's stream (a hipStream_t passed as
+ *     void*; NULL = the default stream).
+ *   - Functions return a ccmg status; none aborts or throws.  Arguments are
+ *     validated before any device work is enqueued.
+ *   - A plan is not re-entrant: one call at a time per plan.  Distinct plans
+ *     (with distinct workspaces) may run on distinct streams concurrently.
+ */
+#ifndef CCMG_H
+#define CCMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Side types (Sec. 3.3; periodic is an addition for doubly periodic work). */
+enum { CCMG_BC_DIRICHLET = 0, CCMG_BC_NEUMANN = 1, CCMG_BC_PERIODIC = 2 };
+/* Side order inside ccmg_problem.bc */
+enum { CCMG_XLO = 0, CCMG_XHI = 1, CCMG_YLO = 2, CCMG_YHI = 3 };
+/* Precision forms.
+ *   CCMG_FP64 : every level relaxed, restricted and prolonged in FP64.
+ *   CCMG_MIXED: iterative refinement -- the FP64 residual of the FP64 iterate
+ *               is rounded to FP32, FP32 V-cycles solve for the correction
+ *               (2x2 bottom solve in FP64), the correction is added in FP64,
+ *               and the stop test always uses the FP64 residual. */
+enum { CCMG_FP64 = 0, CCMG_MIXED = 1 };
+
+/* Status codes */
+enum {
+    CCMG_OK = 0,
+    CCMG_NOT_CONVERGED = 1, /* max_cycles reached; last iterate and history kept */
+    CCMG_EINVAL = -1,       /* NULL pointer, bad count, bad pitch, bad level     */
+    CCMG_ESIZE = -2,        /* n not a power of two in [2, 16384]                */
+    CCMG_EBC = -3,          /* unknown side type, or periodic not paired         */
+    CCMG_EINCOMPAT = -4,    /* singular problem with |sum f| > 1e-12 sum |f|     */
+    CCMG_ENONFINITE = -5,   /* NaN / Inf in f, or a residual norm went NaN / Inf */
+    CCMG_EHIP = -6,         /* a HIP runtime call failed                         */
+    CCMG_EWORKSPACE = -7    /* workspace NULL, too small or misaligned (256 B)   */
+};
+
+#define CCMG_HISTORY 128
+
+typedef struct {
+    int n;                 /* cells per side: power of two, 2 <= n <= 16384     */
+    int ng;                /* ghost layers: must be 1                           */
+    double xmin, xmax;     /* domain; cells must be square:                     */
+    double ymin, ymax;     /*   xmax - xmin == ymax - ymin > 0                  */
+    int bc[4];             /* side types, order CCMG_XLO, XHI, YLO, YHI         */
+    double alpha, beta;    /* (alpha - beta Lap) phi = f                        */
+    int nu1, nu2;          /* relaxations before / after the coarse correction, 0..8 */
+    int nu_bottom;         /* relaxations on the 2 x 2 grid (paper: 50)         */
+    int max_cycles;        /* >= 0, at most CCMG_HISTORY - 1                    */
+    double rtol;           /* stop when ||r|| / ||f|| <= rtol                   */
+    int prec;              /* CCMG_FP64 or CCMG_MIXED                           */
+} ccmg_problem;
+
+typedef struct {
+    int status;            /* same value the call returned                      */
+    int cycles;            /* V-cycles (MIXED: refinement steps) performed      */
+    double rel_resid0;     /* ||f - A phi0|| / ||f|| of the starting iterate    */
+    double rel_resid;      /* ... of the returned iterate                       */
+    double history[CCMG_HISTORY]; /* history[k] after k cycles, k <= cycles     */
+    float ms;              /* device time of the call (HIP events)              */
+    int inner_cycles;      /* MIXED: FP32 V-cycles performed in total           */
+} ccmg_result;
+
+typedef struct ccmg_plan ccmg_plan;
+
+/* Text for a status code (static storage). */
+const char *ccmg_status_str(int status);
+
+/* Fill *p with the defaults: unit square, all sides Dirichlet, Poisson,
+ * V(2,2), 50 bottom relaxations, 100 cycles, rtol 1e-10, FP64. */
+int ccmg_problem_init(ccmg_problem *p, int n);
+
+/* Validate a problem without touching the GPU. */
+int ccmg_problem_check(const ccmg_problem *p);
+
+/* Bytes of device workspace ccmg_plan_create needs for *p (0 if invalid). */
+size_t ccmg_workspace_bytes(const ccmg_problem *p);
+
+/* Create a plan in a caller-owned device workspace of >= ccmg_workspace_bytes
+ * bytes, 256-byte aligned.  The workspace must outlive the plan and must not
+ * be shared with another live plan.  `stream` is a hipStream_t (or NULL). */
+int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *stream,
+                     ccmg_plan **out);
+int ccmg_plan_destroy(ccmg_plan *plan);
+
+/* Solve (alpha - beta Lap) phi = f.  d_f, d_phi: device arrays of the finest
+ * level, same pitch.  f's ghosts are ignored.  On entry d_phi holds the
+ * starting iterate if use_guess != 0 (else it is ignored and zero is used);
+ * on return it holds the last iterate with its ghost cells filled.  Blocks
+ * until the result is known (the stop test needs it).  Singular problems
+ * (alpha == 0, no Dirichlet side) are checked for compatibility and return
+ * the zero-mean solution.  ||f|| == 0 gives phi = 0 and CCMG_OK.
+ * `out` may be NULL. */
+int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+               ccmg_result *out);
+
+/* Exactly one V-cycle (FP64 plans) or one refinement step (MIXED plans) on
+ * the finest level, in place on d_phi, without a stop test.  Asynchronous. */
+int ccmg_vcycle(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
+
+/* ---- single steps at one level, for checking each kernel (asynchronous).
+ * `level` l has n >> l cells per side and spacing h * 2^l; every level uses
+ * the homogeneous version of the plan's side types and the plan's
+ * alpha, beta.  Out-of-place: input and output arrays must not overlap. */
+
+/* Fill the ghost cells of d_a (level l) from its valid cells. */
+int ccmg_fill_ghosts(ccmg_plan *plan, int level, double *d_a, ptrdiff_t pitch);
+/* phi_out = `iters` (1 or 2) red-black Gauss-Seidel iterations applied to phi_in. */
+int ccmg_smooth(ccmg_plan *plan, int level, int iters, const double *d_f, const double *d_phi_in,
+                double *d_phi_out, ptrdiff_t pitch);
+/* r = f - (alpha phi - beta Lap phi) on valid cells of level l. */
+int ccmg_residual(ccmg_plan *plan, int level, const double *d_f, const double *d_phi, double *d_r,
+                  ptrdiff_t pitch);
+/* d_fc (level l+1) = four-cell average of r = f - A phi (level l). */
+int ccmg_restrict_residual(ccmg_plan *plan, int level, const double *d_f, const double *d_phi,
+                           ptrdiff_t pitch, double *d_fc, ptrdiff_t pitch_c);
+/* phi_out = phi_in + P e  with e on level l+1 (its ghosts are not read). */
+int ccmg_prolong_add(ccmg_plan *plan, int level, const double *d_ec, ptrdiff_t pitch_c,
+                     const double *d_phi_in, double *d_phi_out, ptrdiff_t pitch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,288 @@
+"""Python binding of the ccmg HIP library (include/ccmg.h).
+
+Argument marshalling only: every step of a solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (fields and workspaces are torch
+tensors on a ROCm device) and the stream (torch's current HIP stream).  The
+library must be built (``python -m paper_1306_6883_amd.build``); importing
+this module does not fall back to anything when it is missing.
+
+Fields are torch tensors of shape (n+2, pitch) with pitch >= n+2 (row stride
+in elements), one ghost layer, x contiguous: valid cell (i, j) is
+``t[j+1, i+1]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccmg.so")
+
+BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC = 0, 1, 2
+FP64, MIXED = 0, 1
+OK, NOT_CONVERGED, EINVAL, ESIZE, EBC, EINCOMPAT, ENONFINITE, EHIP, EWORKSPACE = 0, 1, -1, -2, -3, -4, -5, -6, -7
+HISTORY = 128
+_BC = {"D": BC_DIRICHLET, "N": BC_NEUMANN, "P": BC_PERIODIC,
+       BC_DIRICHLET: BC_DIRICHLET, BC_NEUMANN: BC_NEUMANN, BC_PERIODIC: BC_PERIODIC}
+
+
+class CcmgError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {ccmg_status_str(status)} ({status})" if what else ccmg_status_str(status))
+
+
+class ccmg_problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("ng", ctypes.c_int),
+                ("xmin", ctypes.c_double), ("xmax", ctypes.c_double),
+                ("ymin", ctypes.c_double), ("ymax", ctypes.c_double),
+                ("bc", ctypes.c_int * 4), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("nu_bottom", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("rtol", ctypes.c_double), ("prec", ctypes.c_int)]
+
+
+class ccmg_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("rel_resid0", ctypes.c_double), ("rel_resid", ctypes.c_double),
+                ("history", ctypes.c_double * HISTORY), ("ms", ctypes.c_float),
+                ("inner_cycles", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no other path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1306_6883_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, sz, pd, i = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_ssize_t, ctypes.c_int
+        P = ctypes.POINTER(ccmg_problem)
+        L.ccmg_status_str.restype = ctypes.c_char_p
+        L.ccmg_status_str.argtypes = [i]
+        L.ccmg_problem_init.argtypes = [P, i]
+        L.ccmg_problem_check.argtypes = [P]
+        L.ccmg_workspace_bytes.restype = sz
+        L.ccmg_workspace_bytes.argtypes = [P]
+        L.ccmg_plan_create.argtypes = [P, vp, sz, vp, ctypes.POINTER(vp)]
+        L.ccmg_plan_destroy.argtypes = [vp]
+        L.ccmg_solve.argtypes = [vp, dp, dp, pd, i, ctypes.POINTER(ccmg_result)]
+        L.ccmg_vcycle.argtypes = [vp, dp, dp, pd]
+        L.ccmg_fill_ghosts.argtypes = [vp, i, dp, pd]
+        L.ccmg_smooth.argtypes = [vp, i, i, dp, dp, dp, pd]
+        L.ccmg_residual.argtypes = [vp, i, dp, dp, dp, pd]
+        L.ccmg_restrict_residual.argtypes = [vp, i, dp, dp, pd, dp, pd]
+        L.ccmg_prolong_add.argtypes = [vp, i, dp, pd, dp, dp, pd]
+        _lib = L
+    return _lib
+
+
+def ccmg_status_str(status: int) -> str:
+    return lib().ccmg_status_str(status).decode()
+
+
+def _check(status: int, what: str, allow=(OK,)):
+    if status not in allow:
+        raise CcmgError(status, what)
+    return status
+
+
+@dataclass
+class Problem:
+    """Mirror of ccmg_problem.  bc: 4 sides (xlo, xhi, ylo, yhi) as 'D'/'N'/'P' or
+    codes, or one letter for all sides."""
+    n: int
+    bc: object = "D"
+    alpha: float = 0.0
+    beta: float = -1.0
+    xmin: float = 0.0
+    xmax: float = 1.0
+    ymin: float = 0.0
+    ymax: float = 1.0
+    nu1: int = 2
+    nu2: int = 2
+    nu_bottom: int = 50
+    max_cycles: int = 100
+    rtol: float = 1e-10
+    prec: int = FP64
+
+    def bc_codes(self):
+        b = self.bc
+        if isinstance(b, str) and len(b) == 1:
+            b = (b,) * 4
+        return tuple(x if isinstance(x, int) else _BC[x] for x in b)
+
+    def to_c(self) -> ccmg_problem:
+        p = ccmg_problem()
+        p.n, p.ng = self.n, 1
+        p.xmin, p.xmax, p.ymin, p.ymax = self.xmin, self.xmax, self.ymin, self.ymax
+        p.bc[:] = list(self.bc_codes())
+        p.alpha, p.beta = self.alpha, self.beta
+        p.nu1, p.nu2, p.nu_bottom = self.nu1, self.nu2, self.nu_bottom
+        p.max_cycles, p.rtol, p.prec = self.max_cycles, self.rtol, self.prec
+        return p
+
+    @property
+    def h(self) -> float:
+        return (self.xmax - self.xmin) / self.n
+
+
+@dataclass
+class Result:
+    status: int
+    cycles: int
+    rel_resid0: float
+    rel_resid: float
+    history: list = field(default_factory=list)
+    ms: float = 0.0
+    inner_cycles: int = 0
+
+
+def ccmg_problem_check(prob: Problem) -> int:
+    return lib().ccmg_problem_check(ctypes.byref(prob.to_c()))
+
+
+def ccmg_workspace_bytes(prob: Problem) -> int:
+    return lib().ccmg_workspace_bytes(ctypes.byref(prob.to_c()))
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _field_args(t: torch.Tensor, n: int, dtype=torch.float64):
+    if not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.shape[0] != n + 2 or t.shape[1] < n + 2:
+        raise ValueError(f"expected a {dtype} device tensor of shape ({n + 2}, >= {n + 2})")
+    if t.stride(1) != 1 or t.stride(0) < n + 2:
+        raise ValueError("field must be x-contiguous with row stride >= n+2")
+    return t.data_ptr(), t.stride(0)
+
+
+class Plan:
+    """A ccmg plan with its own workspace tensor (caller-owned device memory)."""
+
+    def __init__(self, prob: Problem, device=None, stream=None):
+        self.prob = prob
+        self._c = prob.to_c()
+        st = lib().ccmg_problem_check(ctypes.byref(self._c))
+        _check(st, "problem")
+        nbytes = lib().ccmg_workspace_bytes(ctypes.byref(self._c))
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        _check(lib().ccmg_plan_create(ctypes.byref(self._c), ctypes.c_void_p(aligned), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "plan_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ccmg_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def n(self):
+        return self.prob.n
+
+    def level_n(self, level: int) -> int:
+        return self.prob.n >> level
+
+
+def ccmg_solve(plan: Plan, f: torch.Tensor, phi: torch.Tensor, use_guess: bool = False) -> Result:
+    n = plan.n
+    fp, pitch = _field_args(f, n)
+    pp, pitch2 = _field_args(phi, n)
+    if pitch != pitch2:
+        raise ValueError("f and phi must share one pitch")
+    r = ccmg_result()
+    st = lib().ccmg_solve(plan.handle, fp, pp, pitch, int(use_guess), ctypes.byref(r))
+    _check(st, "ccmg_solve", allow=(OK, NOT_CONVERGED))
+    hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
+
+
+def ccmg_vcycle(plan: Plan, f: torch.Tensor, phi: torch.Tensor) -> None:
+    fp, pitch = _field_args(f, plan.n)
+    pp, pitch2 = _field_args(phi, plan.n)
+    if pitch != pitch2:
+        raise ValueError("f and phi must share one pitch")
+    _check(lib().ccmg_vcycle(plan.handle, fp, pp, pitch), "ccmg_vcycle")
+
+
+def ccmg_fill_ghosts(plan: Plan, level: int, a: torch.Tensor) -> None:
+    ap, pitch = _field_args(a, plan.level_n(level))
+    _check(lib().ccmg_fill_ghosts(plan.handle, level, ap, pitch), "ccmg_fill_ghosts")
+
+
+def ccmg_smooth(plan: Plan, level: int, iters: int, f, phi_in, phi_out) -> None:
+    n = plan.level_n(level)
+    fp, pitch = _field_args(f, n)
+    ip, p2 = _field_args(phi_in, n)
+    op, p3 = _field_args(phi_out, n)
+    if not (pitch == p2 == p3):
+        raise ValueError("f, phi_in and phi_out must share one pitch")
+    _check(lib().ccmg_smooth(plan.handle, level, iters, fp, ip, op, pitch), "ccmg_smooth")
+
+
+def ccmg_residual(plan: Plan, level: int, f, phi, r) -> None:
+    n = plan.level_n(level)
+    fp, pitch = _field_args(f, n)
+    pp, p2 = _field_args(phi, n)
+    rp, p3 = _field_args(r, n)
+    if not (pitch == p2 == p3):
+        raise ValueError("f, phi and r must share one pitch")
+    _check(lib().ccmg_residual(plan.handle, level, fp, pp, rp, pitch), "ccmg_residual")
+
+
+def ccmg_restrict_residual(plan: Plan, level: int, f, phi, fc) -> None:
+    n = plan.level_n(level)
+    fp, pitch = _field_args(f, n)
+    pp, p2 = _field_args(phi, n)
+    cp, pc = _field_args(fc, n // 2)
+    if pitch != p2:
+        raise ValueError("f and phi must share one pitch")
+    _check(lib().ccmg_restrict_residual(plan.handle, level, fp, pp, pitch, cp, pc), "ccmg_restrict_residual")
+
+
+def ccmg_prolong_add(plan: Plan, level: int, ec, phi_in, phi_out) -> None:
+    n = plan.level_n(level)
+    ep, pc = _field_args(ec, n // 2)
+    ip, pitch = _field_args(phi_in, n)
+    op, p2 = _field_args(phi_out, n)
+    if pitch != p2:
+        raise ValueError("phi_in and phi_out must share one pitch")
+    _check(lib().ccmg_prolong_add(plan.handle, level, ep, pc, ip, op, pitch), "ccmg_prolong_add")
+
+
+def field(n: int, dtype=torch.float64, device="cuda", pitch: int | None = None) -> torch.Tensor:
+    """A zeroed (n+2, pitch) field on the device (a view when pitch > n+2)."""
+    p = pitch or (n + 2)
+    return torch.zeros((n + 2, p), dtype=dtype, device=device)
+
+
+def to_field(valid, device="cuda", pitch: int | None = None) -> torch.Tensor:
+    """Upload an (n, n) host array of valid cells into a zero-ghost device field."""
+    v = torch.as_tensor(valid, dtype=torch.float64)
+    n = v.shape[0]
+    t = field(n, device=device, pitch=pitch)
+    t[1:n + 1, 1:n + 1] = v.to(device)
+    return t
+
+
+def solve(prob: Problem, f_valid, guess=None):
+    """Convenience: solve on the current device from host arrays; returns (phi field, Result)."""
+    plan = Plan(prob)
+    f = to_field(f_valid)
+    phi = to_field(guess) if guess is not None else field(prob.n)
+    res = ccmg_solve(plan, f, phi, use_guess=guess is not None)
+    return phi, res

@@ -1,0 +1,91 @@
+// internal.h -- shared declarations of the ccmg HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ccmg.h"
+
+namespace ccmg {
+
+enum Post { POST_NONE = 0, POST_RESTRICT = 1, POST_NORM = 2, POST_RESID = 3 };
+
+// Arguments of one row-march launch over one grid level (see march.hip).
+template <typename T>
+struct MarchArgs {
+    const T *f;          // right-hand side, ghosted, pitch pf
+    long pf;
+    const T *phi_in;     // starting iterate (ignored when the launch assumes zero)
+    long pin;
+    T *phi_out;          // relaxed iterate (valid cells only)
+    long pout;
+    const T *ec;         // coarse correction e (level l+1) for the prolongation
+    long pc;
+    T *aux;              // POST_RESTRICT: coarse rhs (level l+1); POST_RESID: r
+    long paux;
+    double *partial;     // per-tile sums: RESTRICT -> sum of coarse rhs; NORM -> sum r^2, sum phi
+    const double *fmean_part;  // partial sums whose total / (n*n) is subtracted from f (or null)
+    int fmean_count;
+    const double *phi_shift;   // device scalar subtracted from loaded phi (or null)
+    const int *skip;     // device flag: when set (solve converged) the launch does nothing
+    int n;               // cells per side of this level
+    int bc[4];
+    T cc, invd;          // relaxation: phi = (f + cc * sum of neighbours) * invd
+    T alpha, beta, ih2;  // residual: r = f - (alpha phi - beta ih2 * lap)
+    int strips, chunks, ty, outw, ntiles, groups_per_xcd;
+};
+
+// Launch description chosen by the host for one level.
+struct MarchShape {
+    int ty;       // rows per tile (even)
+    int wpb;      // waves per workgroup
+};
+
+// Host launchers (march.hip).  nu in {0,1,2}; load_phi=false means phi starts at 0.
+// *ntiles_out receives the number of tiles (= partial-sum slots) of the launch.
+template <typename T>
+hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post,
+                        MarchShape shape, hipStream_t s, int *ntiles_out);
+int march_outw(int nu, bool prolong, int post);
+int march_halo_y(int nu, int post);
+
+// Coarse tail: a whole V-cycle from level `n_top` (<= kCoarseMax) down to 2x2 and
+// back, one workgroup, all levels resident in LDS (coarse.hip).
+constexpr int kCoarseMax = 32;
+template <typename T>
+struct CoarseArgs {
+    const T *f;          // rhs at the top level, ghosted
+    long pf;
+    const T *phi_in;     // starting iterate at the top level (if load_phi)
+    long pin;
+    T *phi_out;          // result at the top level (valid cells)
+    long pout;
+    const double *phi_shift;  // subtracted from loaded phi (or null)
+    const int *skip;          // device flag: when set the launch does nothing
+    int n_top;
+    int bc[4];
+    double alpha, beta, h_top;
+    int nu1, nu2, nu_bottom;
+    int load_phi;        // 1: top level starts from phi_in; 0: from zero
+    int sub_top_mean;    // 1: remove the mean of the top-level rhs (singular, not finest)
+    int singular;        // remove the mean of every restricted rhs below the top
+};
+template <typename T>
+hipError_t launch_coarse(const CoarseArgs<T> &a, hipStream_t s);
+
+// util.hip
+hipError_t launch_fill_ghosts_f64(double *a, long pitch, int n, const int bc[4], const double *shift,
+                                  hipStream_t s);
+// End of a cycle: sum the (sum r^2, sum phi) tile pairs in a fixed order, then
+//   *rho_out = sqrt(sum r^2) / sqrt(*f2),  *phi_mean = sum phi / n^2 (singular) or 0,
+//   *done = 1 if rho <= rtol or rho is not finite.
+// Does nothing if *done is already set.  One workgroup.
+hipError_t launch_cycle_end(const double *partial, int count, int n, int singular, const double *f2,
+                            double rtol, double *rho_out, double *phi_mean, int *done, hipStream_t s);
+// Statistics of f (sum, sum |f|, sum f^2, non-finite count) -> out4; `blocks` partials.
+hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
+                         hipStream_t s);
+hipError_t launch_set(double *p, int count, double v, hipStream_t s);
+hipError_t launch_set_int(int *p, int count, int v, hipStream_t s);
+
+}  // namespace ccmg

@@ -1,0 +1,662 @@
+// plan.cpp -- host side of the ccmg C ABI: validation, workspace layout, the
+// V-cycle schedule (which kernel runs on which level) and the solve loop.
+//
+// Schedule of one V(nu1, nu2) cycle (pyro paper, Sec. 3.3):
+//   for each level l from the finest while it has more than kCoarseMax cells per side:
+//     row-march: nu1 red-black iterations, residual, four-cell restriction into
+//     the rhs of level l+1 (plus that rhs's partial sums, for singular problems)
+//   one workgroup: the whole rest of the cycle (coarse.hip), down to 2x2 and back
+//   for each of those levels back up:
+//     row-march: prolongation of the level-(l+1) correction, nu2 iterations,
+//     and on the finest level the residual norm and the sum of phi
+//   one workgroup: residual norm -> relative residual, mean of phi, done flag
+// The stop test reads the relative residual back after each cycle while the
+// next cycle is already queued; the device "done" flag turns that queued cycle
+// into no-ops once the tolerance is met, so the GPU never waits on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ccmg;
+
+namespace {
+
+constexpr int kMinTy = 8;       // smallest rows-per-tile the shape picker uses
+constexpr int kMinOutw = 112;   // narrowest output width of any march variant
+constexpr int kStatBlocks = 512;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+long pitch_for(int n) { return (long)((n + 2 + 31) & ~31); }
+bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+enum { S_FSUM = 0, S_FABS = 1, S_F2 = 2, S_FBAD = 3, S_PHIMEAN = 4, S_RHO0 = 5, kScal = 16 };
+
+int max_tiles(int n) {
+    const int strips = (n + kMinOutw - 1) / kMinOutw;
+    const int chunks = (n + kMinTy - 1) / kMinTy;
+    return strips * chunks;
+}
+
+struct LevelLay {
+    int n = 0;
+    double h = 0;
+    long pitch = 0;        // pitch of the workspace arrays of this level
+    size_t a = 0, b = 0, f = 0;  // byte offsets (level 0 has only b)
+    size_t fpart = 0;      // partial sums of this level's rhs
+    int fpart_cap = 0;
+};
+
+struct Layout {
+    int L = 0;             // levels n, n/2, ..., 2
+    int lt = 0;            // first level handled by the one-workgroup tail
+    std::vector<LevelLay> lev;
+    size_t normpart = 0;
+    int normpart_cap = 0;
+    size_t fstats = 0;
+    size_t scal = 0, hist = 0, flags = 0;
+    size_t total = 0;
+};
+
+bool build_layout(const ccmg_problem &p, Layout &lay) {
+    const int n = p.n;
+    lay.L = 0;
+    while ((n >> lay.L) >= 2) ++lay.L;
+    lay.lev.assign(lay.L, LevelLay());
+    const double h0 = (p.xmax - p.xmin) / n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    lay.lt = lay.L - 1;
+    for (int l = 0; l < lay.L; ++l) {
+        if ((n >> l) <= kCoarseMax) {
+            lay.lt = l;
+            break;
+        }
+    }
+    for (int l = 0; l < lay.L; ++l) {
+        LevelLay &v = lay.lev[l];
+        v.n = n >> l;
+        v.h = h0 * (double)(1 << l);
+        v.pitch = pitch_for(v.n);
+        const size_t bytes = sizeof(double) * (size_t)(v.n + 2) * (size_t)v.pitch;
+        if (l == 0) {
+            v.b = take(bytes);
+        } else if (l <= lay.lt) {
+            v.a = take(bytes);
+            v.b = take(bytes);
+            v.f = take(bytes);
+            v.fpart_cap = max_tiles(v.n * 2);
+            v.fpart = take(sizeof(double) * v.fpart_cap);
+        }
+    }
+    lay.normpart_cap = max_tiles(n);
+    lay.normpart = take(sizeof(double) * 2 * lay.normpart_cap);
+    lay.fstats = take(sizeof(double) * 4 * kStatBlocks);
+    lay.scal = take(sizeof(double) * kScal);
+    lay.hist = take(sizeof(double) * CCMG_HISTORY);
+    lay.flags = take(sizeof(int) * 16);
+    lay.total = off;
+    return true;
+}
+
+// Rows per tile: aim for ~2048 tiles (8 waves per CU) without going below kMinTy.
+MarchShape shape_for(int n) {
+    static int env_ty = -1, env_wpb = -1;
+    if (env_ty < 0) {
+        const char *e = getenv("CCMG_TY");
+        env_ty = e ? atoi(e) : 0;
+        const char *w = getenv("CCMG_WPB");
+        env_wpb = w ? atoi(w) : 0;
+    }
+    MarchShape s;
+    s.wpb = env_wpb > 0 ? env_wpb : 4;
+    if (env_ty >= kMinTy && (env_ty & 1) == 0) {
+        s.ty = env_ty < n ? env_ty : n;
+        return s;
+    }
+    const int strips = (n + 115) / 116;
+    int ty = 128;
+    while (ty > kMinTy && (long)strips * ((n + ty - 1) / ty) < 2048) ty >>= 1;
+    s.ty = ty < n ? ty : n;
+    if (s.ty < 2) s.ty = 2;
+    return s;
+}
+
+}  // namespace
+
+struct ccmg_plan {
+    ccmg_problem p;
+    Layout lay;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool singular = false;
+    double *hpin = nullptr;  // pinned host: relative residual per cycle
+    hipEvent_t ev_sync[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    double *scal() const { return at<double>(lay.scal); }
+    double *hist() const { return at<double>(lay.hist); }
+    int *done() const { return at<int>(lay.flags); }
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? CCMG_OK : CCMG_EHIP; }
+
+// Constants of the level-l operator: relaxation phi = (f + cc*sum) * invd and
+// residual r = f - (alpha phi - beta ih2 lap).
+template <typename T>
+void level_consts(const ccmg_plan *P, int l, MarchArgs<T> &a) {
+    const double h = P->lay.lev[l].h;
+    const double c = P->p.beta / (h * h);
+    a.cc = (T)c;
+    a.invd = (T)(1.0 / (P->p.alpha + 4.0 * c));
+    a.alpha = (T)P->p.alpha;
+    a.beta = (T)P->p.beta;
+    a.ih2 = (T)(1.0 / (h * h));
+    a.n = P->lay.lev[l].n;
+    for (int s = 0; s < 4; ++s) a.bc[s] = P->p.bc[s];
+}
+
+// Split nu relaxations into launches of at most two iterations.
+std::vector<int> split_nu(int nu) {
+    std::vector<int> v;
+    if (nu == 0) {
+        v.push_back(0);
+        return v;
+    }
+    if (nu & 1) v.push_back(1);
+    for (int i = 0; i < nu / 2; ++i) v.push_back(2);
+    return v;
+}
+
+struct Buf {
+    double *p;
+    long pitch;
+};
+
+// Enqueue one FP64 V-cycle.  phi0 (pitch pp0) holds the iterate and receives
+// the result.  first_zero: the iterate is zero (not read).  phi_shift: device
+// scalar subtracted from phi0 as it is read (singular problems), or null.
+// with_norm: also produce the relative residual of the result into hist[slot]
+// and the mean of phi into scal[S_PHIMEAN], and set the done flag.
+hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *phi0, long pp0,
+                            bool first_zero, const double *phi_shift, bool with_norm, int slot) {
+    const Layout &lay = P->lay;
+    const MarchShape *dummy = nullptr;
+    (void)dummy;
+    hipStream_t s = P->stream;
+    hipError_t e;
+    std::vector<Buf> cur(lay.L), other(lay.L);
+    std::vector<int> fpart_count(lay.L, 0);
+    const int *skip = with_norm ? P->done() : nullptr;
+
+    auto fptr = [&](int l) -> Buf {
+        if (l == 0) return Buf{const_cast<double *>(f0), pf0};
+        return Buf{P->at<double>(lay.lev[l].f), lay.lev[l].pitch};
+    };
+    auto setup_bufs = [&](int l) {
+        if (l == 0) {
+            cur[0] = Buf{phi0, pp0};
+            other[0] = Buf{P->at<double>(lay.lev[0].b), lay.lev[0].pitch};
+        } else {
+            cur[l] = Buf{P->at<double>(lay.lev[l].a), lay.lev[l].pitch};
+            other[l] = Buf{P->at<double>(lay.lev[l].b), lay.lev[l].pitch};
+        }
+    };
+    auto fmean = [&](int l, MarchArgs<double> &a) {
+        a.fmean_part = nullptr;
+        a.fmean_count = 0;
+        if (P->singular && l > 0) {
+            a.fmean_part = P->at<double>(lay.lev[l].fpart);
+            a.fmean_count = fpart_count[l];
+        }
+    };
+
+    // down
+    for (int l = 0; l < lay.lt; ++l) {
+        setup_bufs(l);
+        const MarchShape sh = shape_for(lay.lev[l].n);
+        const std::vector<int> chain = split_nu(P->p.nu1);
+        bool zero = (l > 0) || first_zero;
+        for (size_t i = 0; i < chain.size(); ++i) {
+            const bool last = i + 1 == chain.size();
+            MarchArgs<double> a{};
+            level_consts(P, l, a);
+            const Buf fb = fptr(l);
+            a.f = fb.p;
+            a.pf = fb.pitch;
+            fmean(l, a);
+            a.phi_in = cur[l].p;
+            a.pin = cur[l].pitch;
+            a.phi_out = other[l].p;
+            a.pout = other[l].pitch;
+            a.phi_shift = (l == 0 && i == 0 && !zero) ? phi_shift : nullptr;
+            a.skip = skip;
+            int post = POST_NONE;
+            if (last) {
+                post = POST_RESTRICT;
+                a.aux = P->at<double>(lay.lev[l + 1].f);
+                a.paux = lay.lev[l + 1].pitch;
+                a.partial = P->at<double>(lay.lev[l + 1].fpart);
+            }
+            int nt = 0;
+            e = launch_march<double>(a, chain[i], !zero, false, post, sh, s, &nt);
+            if (e != hipSuccess) return e;
+            if (last) fpart_count[l + 1] = nt;
+            std::swap(cur[l], other[l]);
+            zero = false;
+        }
+    }
+    // bottom part in one workgroup
+    {
+        const int l = lay.lt;
+        setup_bufs(l);
+        CoarseArgs<double> c{};
+        const Buf fb = fptr(l);
+        c.f = fb.p;
+        c.pf = fb.pitch;
+        c.load_phi = (l == 0 && !first_zero) ? 1 : 0;
+        c.phi_in = cur[l].p;
+        c.pin = cur[l].pitch;
+        c.phi_out = cur[l].p;  // the tail reads everything into LDS first
+        c.pout = cur[l].pitch;
+        c.phi_shift = (l == 0) ? phi_shift : nullptr;
+        c.skip = skip;
+        c.n_top = lay.lev[l].n;
+        for (int q = 0; q < 4; ++q) c.bc[q] = P->p.bc[q];
+        c.alpha = P->p.alpha;
+        c.beta = P->p.beta;
+        c.h_top = lay.lev[l].h;
+        c.nu1 = P->p.nu1;
+        c.nu2 = P->p.nu2;
+        c.nu_bottom = P->p.nu_bottom;
+        c.sub_top_mean = (P->singular && l > 0) ? 1 : 0;
+        c.singular = P->singular ? 1 : 0;
+        e = launch_coarse<double>(c, s);
+        if (e != hipSuccess) return e;
+    }
+    // up
+    int last_nt = 0;
+    for (int l = lay.lt - 1; l >= 0; --l) {
+        const MarchShape sh = shape_for(lay.lev[l].n);
+        const std::vector<int> chain = split_nu(P->p.nu2);
+        for (size_t i = 0; i < chain.size(); ++i) {
+            const bool last = i + 1 == chain.size();
+            MarchArgs<double> a{};
+            level_consts(P, l, a);
+            const Buf fb = fptr(l);
+            a.f = fb.p;
+            a.pf = fb.pitch;
+            fmean(l, a);
+            a.phi_in = cur[l].p;
+            a.pin = cur[l].pitch;
+            a.phi_out = other[l].p;
+            a.pout = other[l].pitch;
+            a.skip = skip;
+            const bool prolong = i == 0;
+            if (prolong) {
+                a.ec = cur[l + 1].p;
+                a.pc = cur[l + 1].pitch;
+            }
+            int post = POST_NONE;
+            if (last && l == 0 && with_norm) {
+                post = POST_NORM;
+                a.partial = P->at<double>(lay.normpart);
+            }
+            int nt = 0;
+            e = launch_march<double>(a, chain[i], true, prolong, post, sh, s, &nt);
+            if (e != hipSuccess) return e;
+            if (post == POST_NORM) last_nt = nt;
+            std::swap(cur[l], other[l]);
+        }
+    }
+    // the result must end in phi0
+    if (lay.lt > 0 && cur[0].p != phi0) {
+        e = hipMemcpy2DAsync(phi0 + pp0 + 1, sizeof(double) * pp0, cur[0].p + cur[0].pitch + 1,
+                             sizeof(double) * cur[0].pitch, sizeof(double) * lay.lev[0].n, lay.lev[0].n,
+                             hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    if (with_norm) {
+        if (lay.lt == 0) {
+            // the whole cycle ran in the tail: one residual pass for the norm
+            MarchArgs<double> a{};
+            level_consts(P, 0, a);
+            a.f = f0;
+            a.pf = pf0;
+            a.phi_in = phi0;
+            a.pin = pp0;
+            a.partial = P->at<double>(lay.normpart);
+            a.skip = skip;
+            e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(lay.lev[0].n), s, &last_nt);
+            if (e != hipSuccess) return e;
+        }
+        e = launch_cycle_end(P->at<double>(lay.normpart), last_nt, lay.lev[0].n, P->singular ? 1 : 0,
+                             P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN,
+                             P->done(), s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int check_pitch(const ccmg_plan *P, int level, ptrdiff_t pitch) {
+    if (level < 0 || level >= P->lay.L) return CCMG_EINVAL;
+    if (pitch < (ptrdiff_t)(P->lay.lev[level].n + 2)) return CCMG_EINVAL;
+    return CCMG_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char *ccmg_status_str(int s) {
+    switch (s) {
+        case CCMG_OK: return "ok";
+        case CCMG_NOT_CONVERGED: return "not converged within max_cycles";
+        case CCMG_EINVAL: return "invalid argument";
+        case CCMG_ESIZE: return "n must be a power of two in [2, 16384]";
+        case CCMG_EBC: return "bad boundary condition (unknown type or unpaired periodic side)";
+        case CCMG_EINCOMPAT: return "singular problem with a right-hand side of nonzero mean";
+        case CCMG_ENONFINITE: return "non-finite value in f or in a residual norm";
+        case CCMG_EHIP: return "HIP runtime error";
+        case CCMG_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    }
+    return "unknown status";
+}
+
+int ccmg_problem_init(ccmg_problem *p, int n) {
+    if (!p) return CCMG_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->n = n;
+    p->ng = 1;
+    p->xmin = 0.0;
+    p->xmax = 1.0;
+    p->ymin = 0.0;
+    p->ymax = 1.0;
+    for (int s = 0; s < 4; ++s) p->bc[s] = CCMG_BC_DIRICHLET;
+    p->alpha = 0.0;
+    p->beta = -1.0;
+    p->nu1 = 2;
+    p->nu2 = 2;
+    p->nu_bottom = 50;
+    p->max_cycles = 100;
+    p->rtol = 1e-10;
+    p->prec = CCMG_FP64;
+    return ccmg_problem_check(p);
+}
+
+int ccmg_problem_check(const ccmg_problem *p) {
+    if (!p) return CCMG_EINVAL;
+    if (!pow2(p->n) || p->n > 16384) return CCMG_ESIZE;
+    if (p->ng != 1) return CCMG_EINVAL;
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] < CCMG_BC_DIRICHLET || p->bc[s] > CCMG_BC_PERIODIC) return CCMG_EBC;
+    if ((p->bc[0] == CCMG_BC_PERIODIC) != (p->bc[1] == CCMG_BC_PERIODIC)) return CCMG_EBC;
+    if ((p->bc[2] == CCMG_BC_PERIODIC) != (p->bc[3] == CCMG_BC_PERIODIC)) return CCMG_EBC;
+    const double lx = p->xmax - p->xmin, ly = p->ymax - p->ymin;
+    if (!(lx > 0) || !(ly > 0) || !std::isfinite(lx) || !std::isfinite(ly)) return CCMG_EINVAL;
+    if (std::fabs(lx - ly) > 1e-12 * lx) return CCMG_EINVAL;
+    if (!std::isfinite(p->alpha) || !std::isfinite(p->beta)) return CCMG_EINVAL;
+    if (p->nu1 < 0 || p->nu1 > 8 || p->nu2 < 0 || p->nu2 > 8) return CCMG_EINVAL;
+    if (p->nu_bottom < 0 || p->nu_bottom > 100000) return CCMG_EINVAL;
+    if (p->max_cycles < 0 || p->max_cycles >= CCMG_HISTORY) return CCMG_EINVAL;
+    if (!(p->rtol >= 0) || !std::isfinite(p->rtol)) return CCMG_EINVAL;
+    if (p->prec != CCMG_FP64 && p->prec != CCMG_MIXED) return CCMG_EINVAL;
+    // every level's relaxation divides by alpha + 4 beta / h^2
+    const double h0 = lx / p->n;
+    for (int l = 0; (p->n >> l) >= 2; ++l) {
+        const double h = h0 * (double)(1 << l);
+        const double d = p->alpha + 4.0 * p->beta / (h * h);
+        if (d == 0.0 || !std::isfinite(d)) return CCMG_EINVAL;
+    }
+    return CCMG_OK;
+}
+
+size_t ccmg_workspace_bytes(const ccmg_problem *p) {
+    if (ccmg_problem_check(p) != CCMG_OK) return 0;
+    Layout lay;
+    build_layout(*p, lay);
+    return lay.total;
+}
+
+int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *stream, ccmg_plan **out) {
+    if (!out) return CCMG_EINVAL;
+    *out = nullptr;
+    int st = ccmg_problem_check(p);
+    if (st != CCMG_OK) return st;
+    if (p->prec != CCMG_FP64) return CCMG_EINVAL;  // set up below once the mixed form exists
+    ccmg_plan *P = new (std::nothrow) ccmg_plan();
+    if (!P) return CCMG_EINVAL;
+    P->p = *p;
+    build_layout(*p, P->lay);
+    if (!d_ws || ws_bytes < P->lay.total || (reinterpret_cast<uintptr_t>(d_ws) & 255)) {
+        delete P;
+        return CCMG_EWORKSPACE;
+    }
+    P->ws = static_cast<char *>(d_ws);
+    P->stream = static_cast<hipStream_t>(stream);
+    P->singular = p->alpha == 0.0 && p->bc[0] != CCMG_BC_DIRICHLET && p->bc[1] != CCMG_BC_DIRICHLET &&
+                  p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
+    if (e == hipSuccess) e = hipEventCreate(&P->ev_t1);
+    if (e != hipSuccess) {
+        ccmg_plan_destroy(P);
+        return CCMG_EHIP;
+    }
+    *out = P;
+    return CCMG_OK;
+}
+
+int ccmg_plan_destroy(ccmg_plan *P) {
+    if (!P) return CCMG_EINVAL;
+    if (P->hpin) hipHostFree(P->hpin);
+    for (int i = 0; i < 2; ++i)
+        if (P->ev_sync[i]) hipEventDestroy(P->ev_sync[i]);
+    if (P->ev_t0) hipEventDestroy(P->ev_t0);
+    if (P->ev_t1) hipEventDestroy(P->ev_t1);
+    delete P;
+    return CCMG_OK;
+}
+
+int ccmg_vcycle(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
+    if (!P || !d_f || !d_phi) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    return hip_status(enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, false, nullptr, false, 0));
+}
+
+int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+               ccmg_result *out) {
+    ccmg_result local;
+    ccmg_result *R = out ? out : &local;
+    std::memset(R, 0, sizeof(*R));
+    if (!P || !d_f || !d_phi) return R->status = CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return R->status = CCMG_EINVAL;
+    hipStream_t s = P->stream;
+    const Layout &lay = P->lay;
+    const int n = lay.lev[0].n;
+    double *scal = P->scal();
+    hipError_t e = hipEventRecord(P->ev_t0, s);
+
+    // statistics of f, reset of the flags, and the starting residual
+    if (e == hipSuccess) e = launch_set_int(P->done(), 1, 0, s);
+    if (e == hipSuccess) e = launch_set(scal, kScal, 0.0, s);
+    if (e == hipSuccess)
+        e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
+    if (e == hipSuccess && use_guess) {
+        MarchArgs<double> a{};
+        level_consts(P, 0, a);
+        a.f = d_f;
+        a.pf = pitch;
+        a.phi_in = d_phi;
+        a.pin = pitch;
+        a.partial = P->at<double>(lay.normpart);
+        int nt = 0;
+        e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(n), s, &nt);
+        if (e == hipSuccess)
+            e = launch_cycle_end(P->at<double>(lay.normpart), nt, n, P->singular ? 1 : 0, scal + S_F2,
+                                 P->p.rtol, P->hist(), scal + S_PHIMEAN, P->done(), s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P->hpin + CCMG_HISTORY, scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->hpin, P->hist(), sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return R->status = CCMG_EHIP;
+    const double *hs = P->hpin + CCMG_HISTORY;
+    if (hs[S_FBAD] > 0 || !std::isfinite(hs[S_F2])) return R->status = CCMG_ENONFINITE;
+    if (hs[S_F2] == 0.0) {
+        // phi = 0 exactly (valid and ghost cells)
+        e = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        R->status = e == hipSuccess ? CCMG_OK : CCMG_EHIP;
+        return R->status;
+    }
+    if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
+
+    const double rho0 = use_guess ? P->hpin[0] : 1.0;
+    R->rel_resid0 = rho0;
+    R->history[0] = rho0;
+    if (use_guess && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
+    int status = CCMG_NOT_CONVERGED;
+    int cycles = 0;
+    double rho = rho0;
+    if (rho0 <= P->p.rtol) {
+        status = CCMG_OK;
+    } else if (P->p.max_cycles > 0) {
+        const double *shift = P->singular ? scal + S_PHIMEAN : nullptr;
+        auto enqueue = [&](int k) -> hipError_t {  // cycle k (1-based) -> hist[k]
+            hipError_t x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
+            if (x == hipSuccess)
+                x = hipMemcpyAsync(P->hpin + k, P->hist() + k, sizeof(double), hipMemcpyDeviceToHost, s);
+            if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
+            return x;
+        };
+        e = enqueue(1);
+        for (int k = 1; e == hipSuccess; ++k) {
+            if (k < P->p.max_cycles) e = enqueue(k + 1);  // runs as no-ops if cycle k converges
+            if (e != hipSuccess) break;
+            e = hipEventSynchronize(P->ev_sync[k & 1]);
+            if (e != hipSuccess) break;
+            rho = P->hpin[k];
+            R->history[k] = rho;
+            cycles = k;
+            if (!std::isfinite(rho)) {
+                status = CCMG_ENONFINITE;
+                break;
+            }
+            if (rho <= P->p.rtol) {
+                status = CCMG_OK;
+                break;
+            }
+            if (k >= P->p.max_cycles) break;
+        }
+        if (e != hipSuccess) return R->status = CCMG_EHIP;
+    }
+    // output: zero-mean representative for singular problems, ghost cells filled
+    e = launch_fill_ghosts_f64(d_phi, pitch, n, P->p.bc, P->singular ? scal + S_PHIMEAN : nullptr, s);
+    if (e == hipSuccess) e = hipEventRecord(P->ev_t1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(P->ev_t1);
+    if (e != hipSuccess) return R->status = CCMG_EHIP;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, P->ev_t0, P->ev_t1);
+    R->ms = ms;
+    R->cycles = cycles;
+    R->rel_resid = rho;
+    R->status = status;
+    return status;
+}
+
+// ---- single steps -----------------------------------------------------------
+int ccmg_fill_ghosts(ccmg_plan *P, int level, double *d_a, ptrdiff_t pitch) {
+    if (!P || !d_a) return CCMG_EINVAL;
+    if (check_pitch(P, level, pitch) != CCMG_OK) return CCMG_EINVAL;
+    return hip_status(launch_fill_ghosts_f64(d_a, pitch, P->lay.lev[level].n, P->p.bc, nullptr, P->stream));
+}
+
+int ccmg_smooth(ccmg_plan *P, int level, int iters, const double *d_f, const double *d_phi_in,
+                double *d_phi_out, ptrdiff_t pitch) {
+    if (!P || !d_f || !d_phi_in || !d_phi_out || d_phi_in == d_phi_out) return CCMG_EINVAL;
+    if (iters < 1 || iters > 2 || check_pitch(P, level, pitch) != CCMG_OK) return CCMG_EINVAL;
+    MarchArgs<double> a{};
+    level_consts(P, level, a);
+    a.f = d_f;
+    a.pf = pitch;
+    a.phi_in = d_phi_in;
+    a.pin = pitch;
+    a.phi_out = d_phi_out;
+    a.pout = pitch;
+    int nt;
+    return hip_status(launch_march<double>(a, iters, true, false, POST_NONE, shape_for(a.n), P->stream, &nt));
+}
+
+int ccmg_residual(ccmg_plan *P, int level, const double *d_f, const double *d_phi, double *d_r,
+                  ptrdiff_t pitch) {
+    if (!P || !d_f || !d_phi || !d_r) return CCMG_EINVAL;
+    if (check_pitch(P, level, pitch) != CCMG_OK) return CCMG_EINVAL;
+    MarchArgs<double> a{};
+    level_consts(P, level, a);
+    a.f = d_f;
+    a.pf = pitch;
+    a.phi_in = d_phi;
+    a.pin = pitch;
+    a.aux = d_r;
+    a.paux = pitch;
+    int nt;
+    return hip_status(launch_march<double>(a, 0, true, false, POST_RESID, shape_for(a.n), P->stream, &nt));
+}
+
+int ccmg_restrict_residual(ccmg_plan *P, int level, const double *d_f, const double *d_phi, ptrdiff_t pitch,
+                           double *d_fc, ptrdiff_t pitch_c) {
+    if (!P || !d_f || !d_phi || !d_fc) return CCMG_EINVAL;
+    if (check_pitch(P, level, pitch) != CCMG_OK || check_pitch(P, level + 1, pitch_c) != CCMG_OK)
+        return CCMG_EINVAL;
+    MarchArgs<double> a{};
+    level_consts(P, level, a);
+    a.f = d_f;
+    a.pf = pitch;
+    a.phi_in = d_phi;
+    a.pin = pitch;
+    a.aux = d_fc;
+    a.paux = pitch_c;
+    a.partial = P->at<double>(P->lay.normpart);
+    int nt;
+    return hip_status(
+        launch_march<double>(a, 0, true, false, POST_RESTRICT, shape_for(a.n), P->stream, &nt));
+}
+
+int ccmg_prolong_add(ccmg_plan *P, int level, const double *d_ec, ptrdiff_t pitch_c, const double *d_phi_in,
+                     double *d_phi_out, ptrdiff_t pitch) {
+    if (!P || !d_ec || !d_phi_in || !d_phi_out || d_phi_in == d_phi_out) return CCMG_EINVAL;
+    if (check_pitch(P, level, pitch) != CCMG_OK || check_pitch(P, level + 1, pitch_c) != CCMG_OK)
+        return CCMG_EINVAL;
+    MarchArgs<double> a{};
+    level_consts(P, level, a);
+    a.f = d_phi_in;  // f is read but unused by a pure prolongation
+    a.pf = pitch;
+    a.phi_in = d_phi_in;
+    a.pin = pitch;
+    a.phi_out = d_phi_out;
+    a.pout = pitch;
+    a.ec = d_ec;
+    a.pc = pitch_c;
+    int nt;
+    return hip_status(launch_march<double>(a, 0, true, true, POST_NONE, shape_for(a.n), P->stream, &nt));
+}
+
+}  // extern "C"
