@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the cell-centred multigrid hot path on one MI355X.
+
+A step is one whole solve to tolerance (V(2,2) cycles of red-black
+Gauss-Seidel, four-cell restriction, centred-slope prolongation, 2x2 bottom
+solve, FP64 stop test) of the headline workload:
+
+  Poisson on 4096 x 4096 cells, periodic sides, f = sum of 64 seeded Fourier
+  modes (|k| <= 32, N(0,1) amplitudes), zero mean, relative residual 1e-10.
+
+Inputs are generated on the host, uploaded once, and resident in HBM when the
+timed region starts.  The printed JSON line reports grid-points x V-cycles per
+second over the K timed solves, the roofline of the dominant kernel (measured
+with HIP events in a separate pass of the same K solves), the same workload on
+8192^2 with Dirichlet sides, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def upload(cc, torch, fv):
+    n = fv.shape[0]
+    f = cc.field(n)
+    f[1:n + 1, 1:n + 1] = torch.from_numpy(fv).cuda()
+    return f
+
+
+def run_solves(cc, torch, plan, f, phi, steps, profile=False):
+    """Time `steps` solves; returns (seconds, results)."""
+    if profile:
+        cc.ccmg_plan_profile(plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [cc.ccmg_solve(plan, f, phi) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = None
+    if profile:
+        stats = cc.ccmg_plan_kernel_stats(plan)
+        cc.ccmg_plan_profile(plan, False)
+    return dt, res, stats
+
+
+def measure(cc, torch, n, bc, fv, steps, warmup):
+    prob = cc.Problem(n=n, bc=bc, rtol=1e-10)
+    plan = cc.Plan(prob)
+    f = upload(cc, torch, fv)
+    phi = cc.field(n)
+    cc.ccmg_plan_autotune(plan, f, phi)  # launch shapes per level, before any timing
+    shapes = cc.ccmg_plan_shapes(plan)
+    for _ in range(warmup):
+        r = cc.ccmg_solve(plan, f, phi)
+        assert r.status == cc.OK, r
+    dt, res, _ = run_solves(cc, torch, plan, f, phi, steps)
+    cycles = sum(r.cycles for r in res)
+    assert all(r.status == cc.OK and r.rel_resid <= 1e-10 for r in res)
+    # kernel durations: a second pass of the same solves with HIP events around
+    # the finest-level launches
+    _, _, stats = run_solves(cc, torch, plan, f, phi, steps, profile=True)
+    out = dict(n=n, bc=bc, seconds=dt, solves=steps, cycles=cycles,
+               cycles_per_solve=cycles / steps, ms_per_solve=1e3 * dt / steps,
+               pts_cycles_per_s=n * n * cycles / dt, rel_resid=res[-1].rel_resid,
+               history=res[-1].history, kernels=stats, shapes=shapes)
+    del plan, f, phi
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(meas):
+    ks = [k for k in meas["kernels"] if k["launches"] > 0]
+    dom = max(ks, key=lambda k: k["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom["name"],
+                avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_per_launch,
+                all_kernels=[dict(name=k["name"], launches=k["launches"],
+                                  avg_ms=round(k["ms"] / k["launches"], 5),
+                                  gbs=round(k["bytes"] / k["launches"] / (k["ms"] / k["launches"] * 1e-3) / 1e9, 1))
+                             for k in ks])
+
+
+def cpu_baseline(fv, n, bc, budget_s=10.0):
+    """The FP64 CPU oracle on a bounded sample of the same workload: whole
+    solves to 1e-10 repeated until about `budget_s` seconds have passed."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    p = oracle.Problem(n=n, h=1.0 / n, bc=bc, rtol=1e-10)
+    f = oracle.embed(fv)
+    solves = cycles = 0
+    t0 = time.perf_counter()
+    while True:
+        _, r = oracle.solve(p, f)
+        solves += 1
+        cycles += r.cycles
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or solves >= 50:
+            break
+    return {"value": n * n * cycles / dt, "unit": "grid-pts*V-cycles/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{solves} whole {n}^2 periodic solves to 1e-10 ({cycles} V(2,2) cycles), "
+                      f"plain C + OpenMP, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of it"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1306_6883_amd as cc
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    n = 4096
+    log("generating inputs")
+    f4096 = W.fourier_modes(n, seed=0, count=64, kmax=32)
+
+    if args.probe_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written")
+        del a, b
+
+    log(f"{n}^2 periodic: {args.warmup} warmup + {args.steps} timed solves")
+    m = measure(cc, torch, n, "P", f4096, args.steps, args.warmup)
+    log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
+        f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
+    rl = roofline_of(m)
+    log(f"dominant kernel {rl['kernel']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s ({rl['frac']:.3f})")
+
+    also = {}
+    if not args.quick:
+        n8 = 8192
+        f8 = W.fourier_modes(n8, seed=0, count=64, kmax=32)
+        log(f"{n8}^2 Dirichlet: 1 warmup + {max(args.steps // 4, 2)} timed solves")
+        m8 = measure(cc, torch, n8, "D", f8, max(args.steps // 4, 2), 1)
+        rl8 = roofline_of(m8)
+        also["dirichlet_8192"] = dict(ms_per_solve=round(m8["ms_per_solve"], 3),
+                                      cycles_per_solve=m8["cycles_per_solve"],
+                                      value=m8["pts_cycles_per_s"], rel_resid=m8["rel_resid"],
+                                      roofline=rl8)
+        log(f"8192^2: {m8['ms_per_solve']:.3f} ms/solve, {m8['pts_cycles_per_s'] / 1e9:.2f} G; "
+            f"{rl8['kernel']} {rl8['achieved']} GB/s")
+        del f8
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle sample")
+        cpu = cpu_baseline(f4096, n, "PPPP")
+        log(f"oracle: {cpu['value'] / 1e9:.3f} G pts*cycles/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": "time-to-1e-10 residual & grid-pts*V-cycles/s (HBM % peak), plain vs mixed/batched/learned",
+        "value": m["pts_cycles_per_s"],
+        "unit": "grid-pts*V-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain FP64 V(2,2) Poisson 4096^2 periodic, 64 Fourier modes |k|<=32, "
+                               "zero mean, seed 0, to relative residual 1e-10",
+                   "n": n, "bc": "periodic", "rtol": 1e-10, "cycles_per_solve": m["cycles_per_solve"],
+                   "time_to_tol_ms": m["ms_per_solve"]},
+        "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "all_kernels")},
+        "launch_shapes": {"levels": "finest first; (rows per band, waves per workgroup) of the nu1 and nu2 launches",
+                          "value": m["shapes"]},
+        "cpu_baseline": cpu,
+        "also": also,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

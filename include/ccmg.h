@@ -142,6 +142,42 @@ int ccmg_restrict_residual(ccmg_plan *plan, int level, const double *d_f, const 
 int ccmg_prolong_add(ccmg_plan *plan, int level, const double *d_ec, ptrdiff_t pitch_c,
                      const double *d_phi_in, double *d_phi_out, ptrdiff_t pitch);
 
+/* ---- launch-shape autotuning.
+ * Times every candidate tile shape (rows per wavefront band x wavefronts per
+ * workgroup) of the two row-march launches of each level on the given data and
+ * keeps the fastest for this plan.  d_f and d_phi are only read (finest level,
+ * same layout as ccmg_solve); blocks until done.  Optional: untuned plans use
+ * a fixed size-based choice. */
+int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
+/* Set one launch shape by hand: kind 0 = the nu1 (restricting) launch of
+ * `level`, 1 = the nu2 (prolongating) launch; ty even, >= 8 unless it covers
+ * the level; 1 <= wpb <= 4.  Results do not depend on the shape. */
+int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
+/* The plan's launch shapes per level (arrays of max_levels entries). */
+int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, int *wpb_post,
+                     int max_levels);
+
+/* ---- kernel timing (diagnostics).
+ * While profiling is on, the plan brackets each launch of the two
+ * finest-level row-march kernels of a V-cycle with HIP events on its stream:
+ *   "finest_pre":  nu1 relaxations + residual + four-cell restriction,
+ *   "finest_post": prolongation + nu2 relaxations (+ residual norm).
+ * `bytes` is the algorithmic traffic of one launch: each valid cell of each
+ * array the launch reads or writes, counted once (ghost cells and halo
+ * re-reads excluded). */
+typedef struct {
+    char name[32];
+    int launches;          /* launches timed since profiling was (re)enabled */
+    double ms;             /* their summed device time                       */
+    double bytes;          /* their summed algorithmic bytes                 */
+} ccmg_kernel_stat;
+
+/* Enable (1) or disable (0) kernel timing; either way the counters restart. */
+int ccmg_plan_profile(ccmg_plan *plan, int enable);
+/* Copy up to `max` kernel records into out; *count receives how many exist.
+ * Call after the timed work has completed (e.g. after ccmg_solve returned). */
+int ccmg_plan_kernel_stats(ccmg_plan *plan, ccmg_kernel_stat *out, int max, int *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,11 @@ class ccmg_result(ctypes.Structure):
                 ("inner_cycles", ctypes.c_int)]
 
 
+class ccmg_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -78,6 +83,12 @@ def lib():
         L.ccmg_residual.argtypes = [vp, i, dp, dp, dp, pd]
         L.ccmg_restrict_residual.argtypes = [vp, i, dp, dp, pd, dp, pd]
         L.ccmg_prolong_add.argtypes = [vp, i, dp, pd, dp, dp, pd]
+        L.ccmg_plan_profile.argtypes = [vp, i]
+        L.ccmg_plan_autotune.argtypes = [vp, dp, dp, pd]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.ccmg_plan_shapes.argtypes = [vp, ip, ip, ip, ip, i]
+        L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
+        L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
         _lib = L
     return _lib
 
@@ -262,6 +273,40 @@ def ccmg_prolong_add(plan: Plan, level: int, ec, phi_in, phi_out) -> None:
     if pitch != p2:
         raise ValueError("phi_in and phi_out must share one pitch")
     _check(lib().ccmg_prolong_add(plan.handle, level, ep, pc, ip, op, pitch), "ccmg_prolong_add")
+
+
+def ccmg_plan_autotune(plan: Plan, f: torch.Tensor, phi: torch.Tensor) -> None:
+    fp, pitch = _field_args(f, plan.n)
+    pp, pitch2 = _field_args(phi, plan.n)
+    if pitch != pitch2:
+        raise ValueError("f and phi must share one pitch")
+    _check(lib().ccmg_plan_autotune(plan.handle, fp, pp, pitch), "ccmg_plan_autotune")
+
+
+def ccmg_plan_set_shape(plan: Plan, level: int, kind: int, ty: int, wpb: int) -> None:
+    _check(lib().ccmg_plan_set_shape(plan.handle, level, kind, ty, wpb), "ccmg_plan_set_shape")
+
+
+def ccmg_plan_shapes(plan: Plan) -> list:
+    """[(ty_pre, wpb_pre, ty_post, wpb_post)] per level."""
+    L = 16
+    a, b, c, d = [(ctypes.c_int * L)() for _ in range(4)]
+    _check(lib().ccmg_plan_shapes(plan.handle, a, b, c, d, L), "ccmg_plan_shapes")
+    levels = plan.n.bit_length() - 1
+    return [(a[k], b[k], c[k], d[k]) for k in range(min(levels, L))]
+
+
+def ccmg_plan_profile(plan: Plan, enable: bool) -> None:
+    _check(lib().ccmg_plan_profile(plan.handle, int(enable)), "ccmg_plan_profile")
+
+
+def ccmg_plan_kernel_stats(plan: Plan) -> list:
+    """[{name, launches, ms, bytes}] summed since profiling was enabled."""
+    arr = (ccmg_kernel_stat * 8)()
+    cnt = ctypes.c_int()
+    _check(lib().ccmg_plan_kernel_stats(plan.handle, arr, 8, ctypes.byref(cnt)), "ccmg_plan_kernel_stats")
+    return [dict(name=arr[k].name.decode(), launches=arr[k].launches, ms=arr[k].ms, bytes=arr[k].bytes)
+            for k in range(min(cnt.value, 8))]
 
 
 def field(n: int, dtype=torch.float64, device="cuda", pitch: int | None = None) -> torch.Tensor:

@@ -14,22 +14,41 @@ namespace ccmg {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;  // one thread per cell of a colour on the 32 x 32 level
 
-// Neighbour values of cell (x, y) of an n x n level stored row-major in A.
+// Side rules, held in scalar registers for the whole kernel.
+struct Sides {
+    bool px, py;          // periodic in x / y
+    float sxl, sxh, syl, syh;  // ghost sign of a Dirichlet (-1) / Neumann (+1) side
+};
+
+// Neighbour values of cell (x, y) of an n x n level (n = 1 << lg) stored
+// row-major in A.  Branch-free: every neighbour is one LDS read at a wrapped
+// (periodic) or clamped (own cell) index, times the ghost sign (-1 Dirichlet,
+// +1 Neumann) where the neighbour is a ghost; times 1 (exact) elsewhere.
 template <typename T>
-__device__ __forceinline__ void neighbours(const T *A, int n, int x, int y, const int *bc, T self,
+__device__ __forceinline__ void neighbours(const T *A, int lg, int x, int y, const Sides &sd, T self,
                                            T &e, T &w, T &nn, T &s) {
-    const int nm = n - 1;
-    auto sgn = [](int b) { return b == CCMG_BC_DIRICHLET ? T(-1) : T(1); };
-    e = x < nm ? A[y * n + x + 1] : (bc[CCMG_XHI] == CCMG_BC_PERIODIC ? A[y * n] : sgn(bc[CCMG_XHI]) * self);
-    w = x > 0 ? A[y * n + x - 1] : (bc[CCMG_XLO] == CCMG_BC_PERIODIC ? A[y * n + nm] : sgn(bc[CCMG_XLO]) * self);
-    nn = y < nm ? A[(y + 1) * n + x] : (bc[CCMG_YHI] == CCMG_BC_PERIODIC ? A[x] : sgn(bc[CCMG_YHI]) * self);
-    s = y > 0 ? A[(y - 1) * n + x] : (bc[CCMG_YLO] == CCMG_BC_PERIODIC ? A[nm * n + x] : sgn(bc[CCMG_YLO]) * self);
+    (void)self;
+    const int nm = (1 << lg) - 1;
+    const bool xh = x == nm, xl = x == 0, yh = y == nm, yl = y == 0;
+    const int xe = xh ? (sd.px ? 0 : x) : x + 1;
+    const int xw = xl ? (sd.px ? nm : x) : x - 1;
+    const int yn = yh ? (sd.py ? 0 : y) : y + 1;
+    const int yS = yl ? (sd.py ? nm : y) : y - 1;
+    const T ge = (xh && !sd.px) ? T(sd.sxh) : T(1);
+    const T gw = (xl && !sd.px) ? T(sd.sxl) : T(1);
+    const T gn = (yh && !sd.py) ? T(sd.syh) : T(1);
+    const T gs = (yl && !sd.py) ? T(sd.syl) : T(1);
+    const int row = y << lg;
+    e = ge * A[row + xe];
+    w = gw * A[row + xw];
+    nn = gn * A[(yn << lg) + x];
+    s = gs * A[(yS << lg) + x];
 }
 
 // Block-wide sum in a fixed order (per-thread strided sums, per-wave butterfly,
-// then the four wave totals in order).  All threads get the result.
+// then the wave totals in order).  All threads get the result.
 __device__ double block_sum(double v, double *red) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -37,45 +56,46 @@ __device__ double block_sum(double v, double *red) {
     if ((threadIdx.x & 63) == 0) red[wave] = v;
     __syncthreads();
     double t = 0.0;
+#pragma unroll
     for (int i = 0; i < kThreads / 64; ++i) t += red[i];
     __syncthreads();
     return t;
 }
 
 template <typename T>
-__device__ void relax(T *P, const T *F, int n, const int *bc, T cc, T invd, int iters) {
-    const int half = (n * n) >> 1, hn = n >> 1;
+__device__ void relax(T *P, const T *F, int lg, const Sides &sd, T cc, T invd, int iters) {
+    const int n = 1 << lg, half = (n * n) >> 1, lgh = lg - 1;
     for (int it = 0; it < iters; ++it) {
         for (int colour = 0; colour < 2; ++colour) {
             for (int i = threadIdx.x; i < half; i += kThreads) {
-                const int y = i / hn;
-                const int x = 2 * (i - y * hn) + ((y + colour) & 1);
-                const T self = P[y * n + x];
+                const int y = i >> lgh;
+                const int x = 2 * (i - (y << lgh)) + ((y + colour) & 1);
+                const T self = P[(y << lg) + x];
                 T e, w, nn, s;
-                neighbours(P, n, x, y, bc, self, e, w, nn, s);
-                P[y * n + x] = (F[y * n + x] + cc * (((e + w) + nn) + s)) * invd;
+                neighbours(P, lg, x, y, sd, self, e, w, nn, s);
+                P[(y << lg) + x] = (F[(y << lg) + x] + cc * (((e + w) + nn) + s)) * invd;
             }
             __syncthreads();
         }
     }
 }
 
-// Fc = four-cell average of r = F - A P (fine level of n cells per side).
+// Fc = four-cell average of r = F - A P (fine level of n = 1 << lg cells per side).
 template <typename T>
-__device__ void restrict_residual(const T *P, const T *F, T *Fc, int n, const int *bc, T alpha, T beta,
+__device__ void restrict_residual(const T *P, const T *F, T *Fc, int lg, const Sides &sd, T alpha, T beta,
                                   T ih2) {
-    const int nc = n >> 1;
+    const int lgc = lg - 1, nc = 1 << lgc;
     for (int i = threadIdx.x; i < nc * nc; i += kThreads) {
-        const int J = i / nc, I = i - J * nc;
+        const int J = i >> lgc, I = i - (J << lgc);
         T r[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int x = 2 * I + (q & 1), y = 2 * J + (q >> 1);
-            const T p = P[y * n + x];
+            const T p = P[(y << lg) + x];
             T e, w, nn, s;
-            neighbours(P, n, x, y, bc, p, e, w, nn, s);
+            neighbours(P, lg, x, y, sd, p, e, w, nn, s);
             const T lap = ((((e - p) + (w - p)) + (nn - p)) + (s - p)) * ih2;
-            r[q] = F[y * n + x] - (alpha * p - beta * lap);
+            r[q] = F[(y << lg) + x] - (alpha * p - beta * lap);
         }
         Fc[i] = T(0.25) * (((r[0] + r[1]) + r[2]) + r[3]);
     }
@@ -83,24 +103,25 @@ __device__ void restrict_residual(const T *P, const T *F, T *Fc, int n, const in
 }
 
 template <typename T>
-__device__ void remove_mean(T *A, int n, double *red) {
+__device__ void remove_mean(T *A, int lg, double *red) {
+    const int nn = 1 << (2 * lg);
     double s = 0.0;
-    for (int i = threadIdx.x; i < n * n; i += kThreads) s += (double)A[i];
-    const T m = T(block_sum(s, red) / ((double)n * (double)n));
-    for (int i = threadIdx.x; i < n * n; i += kThreads) A[i] -= m;
+    for (int i = threadIdx.x; i < nn; i += kThreads) s += (double)A[i];
+    const T m = T(block_sum(s, red) / (double)nn);
+    for (int i = threadIdx.x; i < nn; i += kThreads) A[i] -= m;
     __syncthreads();
 }
 
-// P (fine, n per side) += prolongation of E (coarse, n/2 per side).
+// P (fine, n = 1 << lg per side) += prolongation of E (coarse, n/2 per side).
 template <typename T>
-__device__ void prolong_add(const T *E, T *P, int n, const int *bc) {
-    const int nc = n >> 1;
+__device__ void prolong_add(const T *E, T *P, int lg, const Sides &sd) {
+    const int n = 1 << lg, lgc = lg - 1;
     for (int i = threadIdx.x; i < n * n; i += kThreads) {
-        const int y = i / n, x = i - y * n;
+        const int y = i >> lg, x = i - (y << lg);
         const int I = x >> 1, J = y >> 1;
-        const T e = E[J * nc + I];
+        const T e = E[(J << lgc) + I];
         T ee, ew, en, es;
-        neighbours(E, nc, I, J, bc, e, ee, ew, en, es);
+        neighbours(E, lgc, I, J, sd, e, ee, ew, en, es);
         const T mx = T(0.5) * (ee - ew), my = T(0.5) * (en - es);
         const T dx = (x & 1) ? T(0.25) : T(-0.25), dy = (y & 1) ? T(0.25) : T(-0.25);
         P[i] = P[i] + ((e + dx * mx) + dy * my);
@@ -115,97 +136,98 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const CoarseArgs<T> a) {
     __shared__ T sP[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ T sF[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ double red[kThreads / 64];
-    __shared__ int bc[4];
     if (a.skip && *a.skip) return;  // uniform over the workgroup
-    if (threadIdx.x < 4) bc[threadIdx.x] = a.bc[threadIdx.x];
-    __syncthreads();
+
+    Sides sd;
+    sd.px = a.bc[CCMG_XLO] == CCMG_BC_PERIODIC;
+    sd.py = a.bc[CCMG_YLO] == CCMG_BC_PERIODIC;
+    sd.sxl = a.bc[CCMG_XLO] == CCMG_BC_DIRICHLET ? -1.f : 1.f;
+    sd.sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? -1.f : 1.f;
+    sd.syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? -1.f : 1.f;
+    sd.syh = a.bc[CCMG_YHI] == CCMG_BC_DIRICHLET ? -1.f : 1.f;
 
     const int n0 = a.n_top;
-    int L = 0;
-    while ((n0 >> L) >= 2) ++L;  // levels n0, n0/2, ..., 2
-    int off[16];
+    const int lg0 = 31 - __clz(n0);
+    const int L = lg0;  // levels n0, n0/2, ..., 2
+    int off[8];
     off[0] = 0;
-    for (int l = 1; l < L; ++l) off[l] = off[l - 1] + (n0 >> (l - 1)) * (n0 >> (l - 1));
+    for (int l = 1; l < L; ++l) off[l] = off[l - 1] + (1 << (2 * (lg0 - l + 1)));
 
     // top level in
     const T shift = (a.load_phi && a.phi_shift) ? T(*a.phi_shift) : T(0);
     for (int i = threadIdx.x; i < n0 * n0; i += kThreads) {
-        const int y = i / n0, x = i - y * n0;
+        const int y = i >> lg0, x = i - (y << lg0);
         sF[i] = a.f[(long)(y + 1) * a.pf + 1 + x];
         sP[i] = a.load_phi ? a.phi_in[(long)(y + 1) * a.pin + 1 + x] - shift : T(0);
     }
     __syncthreads();
-    if (a.sub_top_mean) remove_mean(sF, n0, red);
-
-    auto consts = [&](int l, T &cc, T &invd, T &ih2) {
-        const double h = a.h_top * (double)(1 << l);
-        const double c = a.beta / (h * h);
-        cc = T(c);
-        invd = T(1.0 / (a.alpha + 4.0 * c));
-        ih2 = T(1.0 / (h * h));
-    };
+    if (a.sub_top_mean) remove_mean(sF, lg0, red);
 
     // down
     for (int l = 0; l + 1 < L; ++l) {
-        const int n = n0 >> l;
-        T cc, invd, ih2;
-        consts(l, cc, invd, ih2);
-        relax(sP + off[l], sF + off[l], n, bc, cc, invd, a.nu1);
-        restrict_residual(sP + off[l], sF + off[l], sF + off[l + 1], n, bc, T(a.alpha), T(a.beta), ih2);
-        if (a.singular) remove_mean(sF + off[l + 1], n >> 1, red);
-        for (int i = threadIdx.x; i < (n >> 1) * (n >> 1); i += kThreads) sP[off[l + 1] + i] = T(0);
+        const int lg = lg0 - l;
+        relax(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu1);
+        restrict_residual(sP + off[l], sF + off[l], sF + off[l + 1], lg, sd, T(a.alpha), T(a.beta),
+                          T(a.ih2[l]));
+        if (a.singular) remove_mean(sF + off[l + 1], lg - 1, red);
+        for (int i = threadIdx.x; i < (1 << (2 * (lg - 1))); i += kThreads) sP[off[l + 1] + i] = T(0);
         __syncthreads();
     }
-    // bottom: 2 x 2 grid, relaxation only, in FP64 registers of one thread
+    // bottom: 2 x 2 grid, relaxation only, in FP64 registers of one thread.
+    // Cell q = 2y + x; its x-neighbour is q^1 and its y-neighbour q^2.  On a
+    // 2 x 2 grid the periodic image of that neighbour is the same cell, and a
+    // Dirichlet / Neumann ghost is -/+ the cell itself.
     if (threadIdx.x == 0) {
         const int l = L - 1;
-        const double h = a.h_top * (double)(1 << l);
-        const double c = a.beta / (h * h), invd = 1.0 / (a.alpha + 4.0 * c);
-        double p[4], f[4];
-        for (int q = 0; q < 4; ++q) {
-            p[q] = (double)sP[off[l] + q];
-            f[q] = (double)sF[off[l] + q];
-        }
-        auto sgn = [](int b) { return b == CCMG_BC_DIRICHLET ? -1.0 : 1.0; };
-        // cell q = y*2 + x; its x-neighbour is q^1, its y-neighbour q^2.  On a
-        // 2 x 2 grid the periodic image of that neighbour is the same cell, and a
-        // D / N ghost is -/+ the cell itself.
+        const double c = a.cc[l], invd = a.invd[l];
+        double p0 = sP[off[l] + 0], p1 = sP[off[l] + 1], p2 = sP[off[l] + 2], p3 = sP[off[l] + 3];
+        const double f0 = sF[off[l] + 0], f1 = sF[off[l] + 1], f2 = sF[off[l] + 2], f3 = sF[off[l] + 3];
+        const double xl = sd.px ? 1.0 : (double)sd.sxl, xh = sd.px ? 1.0 : (double)sd.sxh;
+        const double yl = sd.py ? 1.0 : (double)sd.syl, yh = sd.py ? 1.0 : (double)sd.syh;
+        // x-ghost of a cell at x = 0 is its west side (x-lo), at x = 1 its east side (x-hi)
+        auto upd = [&](double self, double ex, double ey, double f, bool x0, bool y0) {
+            const double e = x0 ? ex : (sd.px ? ex : xh * self);
+            const double w = x0 ? (sd.px ? ex : xl * self) : ex;
+            const double nn = y0 ? ey : (sd.py ? ey : yh * self);
+            const double s = y0 ? (sd.py ? ey : yl * self) : ey;
+            return (f + c * (((e + w) + nn) + s)) * invd;
+        };
         for (int it = 0; it < a.nu_bottom; ++it) {
-            for (int colour = 0; colour < 2; ++colour) {
-                for (int q = 0; q < 4; ++q) {
-                    const int x = q & 1, y = q >> 1;
-                    if (((x + y) & 1) != colour) continue;
-                    const double self = p[q];
-                    const double ex = p[q ^ 1], ey = p[q ^ 2];
-                    const double e = x == 0 ? ex : (bc[CCMG_XHI] == CCMG_BC_PERIODIC ? ex : sgn(bc[CCMG_XHI]) * self);
-                    const double w = x == 1 ? ex : (bc[CCMG_XLO] == CCMG_BC_PERIODIC ? ex : sgn(bc[CCMG_XLO]) * self);
-                    const double nn = y == 0 ? ey : (bc[CCMG_YHI] == CCMG_BC_PERIODIC ? ey : sgn(bc[CCMG_YHI]) * self);
-                    const double s = y == 1 ? ey : (bc[CCMG_YLO] == CCMG_BC_PERIODIC ? ey : sgn(bc[CCMG_YLO]) * self);
-                    p[q] = (f[q] + c * (((e + w) + nn) + s)) * invd;
-                }
-            }
+            p0 = upd(p0, p1, p2, f0, true, true);    // red (0,0)
+            p3 = upd(p3, p2, p1, f3, false, false);  // red (1,1)
+            p1 = upd(p1, p0, p3, f1, false, true);   // black (1,0)
+            p2 = upd(p2, p3, p0, f2, true, false);   // black (0,1)
         }
-        for (int q = 0; q < 4; ++q) sP[off[l] + q] = T(p[q]);
+        sP[off[l] + 0] = T(p0);
+        sP[off[l] + 1] = T(p1);
+        sP[off[l] + 2] = T(p2);
+        sP[off[l] + 3] = T(p3);
     }
     __syncthreads();
     // up
     for (int l = L - 2; l >= 0; --l) {
-        const int n = n0 >> l;
-        T cc, invd, ih2;
-        consts(l, cc, invd, ih2);
-        prolong_add(sP + off[l + 1], sP + off[l], n, bc);
-        relax(sP + off[l], sF + off[l], n, bc, cc, invd, a.nu2);
+        const int lg = lg0 - l;
+        prolong_add(sP + off[l + 1], sP + off[l], lg, sd);
+        relax(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu2);
     }
     // top level out
     for (int i = threadIdx.x; i < n0 * n0; i += kThreads) {
-        const int y = i / n0, x = i - y * n0;
+        const int y = i >> lg0, x = i - (y << lg0);
         a.phi_out[(long)(y + 1) * a.pout + 1 + x] = sP[i];
     }
 }
 
 template <typename T>
-hipError_t launch_coarse(const CoarseArgs<T> &a, hipStream_t s) {
-    if (a.n_top < 2 || a.n_top > kCoarseMax || (a.n_top & (a.n_top - 1))) return hipErrorInvalidValue;
+hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
+    if (a0.n_top < 2 || a0.n_top > kCoarseMax || (a0.n_top & (a0.n_top - 1))) return hipErrorInvalidValue;
+    CoarseArgs<T> a = a0;
+    for (int l = 0; (a.n_top >> l) >= 2 && l < 8; ++l) {
+        const double h = a.h_top * (double)(1 << l);
+        const double c = a.beta / (h * h);
+        a.cc[l] = c;
+        a.invd[l] = 1.0 / (a.alpha + 4.0 * c);
+        a.ih2[l] = 1.0 / (h * h);
+    }
     hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }

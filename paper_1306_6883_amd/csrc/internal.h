@@ -46,8 +46,11 @@ struct MarchShape {
 template <typename T>
 hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post,
                         MarchShape shape, hipStream_t s, int *ntiles_out);
-int march_outw(int nu, bool prolong, int post);
-int march_halo_y(int nu, int post);
+// One march variant family with NU fused iterations; defined in march_impl.h and
+// instantiated per (T, NU) in the march_*.hip files.
+template <typename T, int NU>
+hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int post, MarchShape sh,
+                       hipStream_t s, int *nt);
 
 // Coarse tail: a whole V-cycle from level `n_top` (<= kCoarseMax) down to 2x2 and
 // back, one workgroup, all levels resident in LDS (coarse.hip).
@@ -65,6 +68,9 @@ struct CoarseArgs {
     int n_top;
     int bc[4];
     double alpha, beta, h_top;
+    // per level l below the top (n_top >> l cells): relaxation phi = (f + cc*sum) * invd,
+    // residual r = f - (alpha phi - beta ih2 lap); filled by launch_coarse
+    double cc[8], invd[8], ih2[8];
     int nu1, nu2, nu_bottom;
     int load_phi;        // 1: top level starts from phi_in; 0: from zero
     int sub_top_mean;    // 1: remove the mean of the top-level rhs (singular, not finest)
@@ -80,8 +86,10 @@ hipError_t launch_fill_ghosts_f64(double *a, long pitch, int n, const int bc[4],
 //   *rho_out = sqrt(sum r^2) / sqrt(*f2),  *phi_mean = sum phi / n^2 (singular) or 0,
 //   *done = 1 if rho <= rtol or rho is not finite.
 // Does nothing if *done is already set.  One workgroup.
+// host_rho (optional): host-mapped address that also receives rho.
 hipError_t launch_cycle_end(const double *partial, int count, int n, int singular, const double *f2,
-                            double rtol, double *rho_out, double *phi_mean, int *done, hipStream_t s);
+                            double rtol, double *rho_out, double *phi_mean, int *done, double *host_rho,
+                            hipStream_t s);
 // Statistics of f (sum, sum |f|, sum f^2, non-finite count) -> out4; `blocks` partials.
 hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
                          hipStream_t s);

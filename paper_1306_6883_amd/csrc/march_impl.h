@@ -1,0 +1,444 @@
+// march_impl.h -- fused row-march kernel: the hot path of every V-cycle level.
+// (Included by the march_*.hip files, each of which instantiates a subset.)
+//
+// One wavefront owns a tile of the level: 128 consecutive columns (two per
+// lane: x = X0 + 2*lane and X0 + 2*lane + 1) and a band of rows.  It walks
+// the band one row at a time, keeping a short window of rows in registers,
+// and runs a skewed pipeline over that window:
+//
+//     load row t  ->  [prolongation of the coarse correction into row t]
+//     red sweep of iteration 1 on row t-1, black sweep on row t-2,
+//     red sweep of iteration 2 on row t-3, black sweep on row t-4, ...
+//     -> store the relaxed row t-2*NU
+//     -> residual of row t-2*NU-1 -> four-cell restriction / norm / residual store
+//
+// Each stage only needs the previous stage's values on the rows directly
+// above and below, so this is exactly red-black Gauss-Seidel (pyro paper,
+// Sec. 3.3): the red cells of a row see the old black neighbours, the black
+// cells see the new red ones.  The tile's outer columns and rows are a halo
+// that is recomputed redundantly by the neighbouring tile; what a tile writes
+// is independent of how the level is cut into tiles.
+//
+// Boundary conditions are applied where a neighbour is read: for a Dirichlet
+// or Neumann side the ghost is -/+ the cell's own current value (the paper's
+// homogeneous ghost rules, refreshed before each colour); periodic tiles load
+// the wrapped rows and columns, so the halo *is* the periodic image.
+//
+// Bytes per cell and launch: read f, read phi (unless it starts at zero),
+// write phi, plus a quarter cell of coarse rhs (restriction) or coarse
+// correction (prolongation).  Every other intermediate lives in registers.
+//
+// The output never aliases the input (phi_in != phi_out): a neighbour tile may
+// still read the old values of rows this tile has finished.
+#pragma once
+#include <type_traits>
+
+#include "internal.h"
+
+namespace ccmg {
+
+// ---- cross-lane moves (DPP wavefront shifts) --------------------------------
+// from_left: lane l receives lane l-1's value; from_right: lane l+1's.
+// The edge lanes (0 for from_left, 63 for from_right) receive 0; they are
+// halo lanes by construction.
+__device__ __forceinline__ double from_left(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// Sum over the 64 lanes with a fixed butterfly: every lane gets the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Total of `count` partial sums, formed in a fixed order (deterministic).
+__device__ __forceinline__ double sum_partials(const double *p, int count) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int i = lane; i < count; i += 64) s += p[i];
+    return wave_sum(s);
+}
+
+// Compile-time loop: f(integral_constant<int, B>), ..., f(integral_constant<int, E-1>).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// ---- compile-time shape of a march variant ----------------------------------
+template <int NU, bool PROLONG, int POST>
+struct Cfg {
+    static constexpr int LAGR = POST ? 2 * NU + 1 : 0;  // residual stage
+    static constexpr int LAST = POST ? LAGR : 2 * NU;   // last stage
+    // halo columns: one per stage, two (one lane) for the prolongation slope
+    static constexpr int HXC = 2 * NU + (POST ? 1 : 0) + (PROLONG ? 2 : 0);
+    static constexpr int HX = (HXC + 1) & ~1;
+    static constexpr int HY = (LAST + 1) & ~1;  // halo rows (even: rows start on red parity)
+    static constexpr int W = 10;                // register window (rows), even
+    static constexpr int D = W - LAST - 2;      // prefetch distance (rows)
+    static constexpr int WC = W / 2;            // coarse-row window
+    static constexpr int DC = WC - 3;           // coarse prefetch distance
+    static constexpr int OUTW = 128 - 2 * HX;   // output columns per tile
+    static_assert(D >= 1 && DC >= 0, "window too small");
+};
+
+// Per-wave description of the tile, computed once by the kernel entry.
+struct Tile {
+    int n, nm, nc;
+    int xo0, x0, xl, I, Il;   // output column start; lane columns; loads; coarse column
+    bool px, py, wedge, eedge, cwedge, ceedge, outl;
+    int y0, y1, ys, ye;       // output rows [y0, y1); march rows [ys, ye)
+};
+
+// The row march of one tile.  XB / YB: the tile touches a Dirichlet or Neumann
+// side in x / y, so neighbour reads there must apply the ghost rule; interior
+// tiles (most of them) skip every boundary select.
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST, bool XB, bool YB>
+__device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl, const int tile) {
+    using C = Cfg<NU, PROLONG, POST>;
+    constexpr int W = C::W, D = C::D, WC = C::WC, DC = C::DC;
+    const int lane = threadIdx.x & 63;
+    const int nm = tl.nm, nc = tl.nc;
+    const bool py = tl.py;
+    const int ys = tl.ys, ye = tl.ye, y0 = tl.y0, y1 = tl.y1;
+    const T sxl = a.bc[CCMG_XLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
+    const T sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
+    const T syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
+    const T syh = a.bc[CCMG_YHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
+    const T cc = a.cc, invd = a.invd;
+
+    const bool subf = a.fmean_part != nullptr;
+    const bool subp = LOADPHI && a.phi_shift != nullptr;
+    T fsub = T(0), psub = T(0);
+    if (subf) fsub = T(sum_partials(a.fmean_part, a.fmean_count) / ((double)tl.n * (double)tl.n));
+    if (subp) psub = T(*a.phi_shift);
+
+    const int lo = 1 + tl.xl;        // element offset of this lane's first column in a row
+    const int co = 1 + tl.Il;        // ... of its coarse column
+
+    T P0[W], P1[W], F0[W], F1[W], Cw[WC];
+#pragma unroll
+    for (int k = 0; k < W; ++k) P0[k] = P1[k] = F0[k] = F1[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < WC; ++k) Cw[k] = T(0);
+
+    // Loads are unconditional (a conditional load into the window would force
+    // the compiler to wait for it): rows past the end of the band re-read the
+    // band's last row, whose values only ever reach halo rows.
+    auto load_row = [&](int y, T &p0, T &p1, T &f0, T &f1) {
+        y = min(y, ye - 1);
+        const int yy = py ? (y & nm) : y;
+        const T *fr = a.f + (long)(yy + 1) * a.pf;
+        f0 = fr[lo];
+        f1 = fr[lo + 1];
+        if (LOADPHI) {
+            const T *pr = a.phi_in + (long)(yy + 1) * a.pin;
+            p0 = pr[lo];
+            p1 = pr[lo + 1];
+        }
+    };
+    auto load_coarse = [&](int J, T &c) {
+        const int Jl = py ? (J & (nc - 1)) : (J < 0 ? 0 : (J >= nc ? nc - 1 : J));
+        c = (a.ec + (long)(Jl + 1) * a.pc)[co];
+    };
+
+    double acc0 = 0.0, acc1 = 0.0;
+    T rprev0 = T(0), rprev1 = T(0);
+
+    static_for<0, D>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        load_row(ys + k, P0[k], P1[k], F0[k], F1[k]);
+    });
+    if constexpr (PROLONG) {
+        static_for<0, DC + 2>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            load_coarse((ys >> 1) - 1 + q, Cw[q]);
+        });
+    }
+
+    const int tend = ye + C::LAST;
+    for (int tb = ys; tb < tend; tb += W) {
+        static_for<0, W>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int t = tb + k;
+            // 1. prefetch
+            {
+                constexpr int kd = (k + D) % W;
+                load_row(t + D, P0[kd], P1[kd], F0[kd], F1[kd]);
+            }
+            if constexpr (PROLONG) {
+                if constexpr ((k & 1) == 0) load_coarse((t >> 1) + 1 + DC, Cw[((k >> 1) + 2 + DC) % WC]);
+            }
+            // 2. finish the load of row t: mean shifts, prolongation (done for
+            // every step: past the band it only touches halo slots)
+            if (subf) {
+                F0[k] -= fsub;
+                F1[k] -= fsub;
+            }
+            if (LOADPHI) {
+                if (subp) {
+                    P0[k] -= psub;
+                    P1[k] -= psub;
+                }
+            } else {
+                P0[k] = T(0);
+                P1[k] = T(0);
+            }
+            if constexpr (PROLONG) {
+                const int J = t >> 1;
+                T cm = Cw[((k >> 1) + 0) % WC];
+                const T c0 = Cw[((k >> 1) + 1) % WC];
+                T cp = Cw[((k >> 1) + 2) % WC];
+                if constexpr (YB) {
+                    if (J - 1 < 0) cm = syl * cm;    // coarse ghost row below
+                    if (J + 1 >= nc) cp = syh * cp;  // coarse ghost row above
+                }
+                T ew = from_left(c0), ee = from_right(c0);
+                if constexpr (XB) {
+                    if (tl.cwedge) ew = sxl * c0;
+                    if (tl.ceedge) ee = sxh * c0;
+                }
+                const T mx = T(0.5) * (ee - ew);
+                const T my = T(0.5) * (cp - cm);
+                const T dy = (k & 1) ? T(0.25) : T(-0.25);
+                P0[k] = P0[k] + ((c0 + T(-0.25) * mx) + dy * my);
+                P1[k] = P1[k] + ((c0 + T(0.25) * mx) + dy * my);
+            }
+            // 3. relaxation stages: stage s works on row t - s; odd s = red, even s = black.
+            // Unconditional: a stage on a row outside [ys, ye) writes a slot that
+            // either is reloaded before it is read again (rows below ys) or only
+            // feeds halo rows (rows at or past ye).
+            static_for<1, 2 * NU + 1>([&](auto sc) {
+                constexpr int s = decltype(sc)::value;
+                const int y = t - s;
+                constexpr int kk = (k - s + 2 * W) % W;
+                constexpr int km = (k - s - 1 + 2 * W) % W;
+                constexpr int kp = (k - s + 1 + 2 * W) % W;
+                // red cells: (x + y) even; column 0 has x even; row parity = (k - s) & 1
+                constexpr int col = ((s & 1) ? ((k - s) & 1) : (1 - ((k - s) & 1)));
+                if constexpr (col == 0) {
+                    const T self = P0[kk];
+                    const T e = P1[kk];
+                    T w = from_left(P1[kk]);
+                    if constexpr (XB) {
+                        if (tl.wedge) w = sxl * self;
+                    }
+                    T nn = P0[kp], ss = P0[km];
+                    if constexpr (YB) {
+                        if (y == nm) nn = syh * self;
+                        if (y == 0) ss = syl * self;
+                    }
+                    P0[kk] = (F0[kk] + cc * (((e + w) + nn) + ss)) * invd;
+                } else {
+                    const T self = P1[kk];
+                    const T w = P0[kk];
+                    T e = from_right(P0[kk]);
+                    if constexpr (XB) {
+                        if (tl.eedge) e = sxh * self;
+                    }
+                    T nn = P1[kp], ss = P1[km];
+                    if constexpr (YB) {
+                        if (y == nm) nn = syh * self;
+                        if (y == 0) ss = syl * self;
+                    }
+                    P1[kk] = (F1[kk] + cc * (((e + w) + nn) + ss)) * invd;
+                }
+            });
+            // 4. store the finished row
+            {
+                const int y = t - 2 * NU;
+                constexpr int kk = (k - 2 * NU + 2 * W) % W;
+                if (a.phi_out && y >= y0 && y < y1 && tl.outl) {
+                    T *o = a.phi_out + (long)(y + 1) * a.pout;
+                    o[1 + tl.x0] = P0[kk];
+                    o[2 + tl.x0] = P1[kk];
+                }
+            }
+            // 5. residual of the finished rows and what is made from it
+            if constexpr (POST != POST_NONE) {
+                const int y = t - C::LAGR;
+                if (y >= y0 && y < y1) {
+                    constexpr int kk = (k - C::LAGR + 2 * W) % W;
+                    constexpr int km = (k - C::LAGR - 1 + 2 * W) % W;
+                    constexpr int kp = (k - C::LAGR + 1 + 2 * W) % W;
+                    const T p0 = P0[kk], p1 = P1[kk];
+                    T w0 = from_left(P1[kk]);
+                    T e1 = from_right(P0[kk]);
+                    if constexpr (XB) {
+                        if (tl.wedge) w0 = sxl * p0;
+                        if (tl.eedge) e1 = sxh * p1;
+                    }
+                    T n0 = P0[kp], n1 = P1[kp], s0 = P0[km], s1 = P1[km];
+                    if constexpr (YB) {
+                        if (y == nm) {
+                            n0 = syh * p0;
+                            n1 = syh * p1;
+                        }
+                        if (y == 0) {
+                            s0 = syl * p0;
+                            s1 = syl * p1;
+                        }
+                    }
+                    const T ih2 = a.ih2;
+                    const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                    const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                    const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
+                    const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
+                    if constexpr (POST == POST_RESTRICT) {
+                        if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
+                            const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
+                            if (tl.outl) {
+                                (a.aux + (long)((y >> 1) + 1) * a.paux)[1 + (tl.x0 >> 1)] = v;
+                                acc0 += (double)v;
+                            }
+                        } else {
+                            rprev0 = r0;
+                            rprev1 = r1;
+                        }
+                    } else if constexpr (POST == POST_NORM) {
+                        if (tl.outl) {
+                            acc0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                            acc1 += (double)p0 + (double)p1;
+                        }
+                    } else {  // POST_RESID
+                        if (tl.outl) {
+                            T *o = a.aux + (long)(y + 1) * a.paux;
+                            o[1 + tl.x0] = r0;
+                            o[2 + tl.x0] = r1;
+                        }
+                    }
+                }
+            }
+        });
+    }
+
+    if constexpr (POST == POST_RESTRICT) {
+        const double s = wave_sum(acc0);
+        if (lane == 0) a.partial[tile] = s;
+    } else if constexpr (POST == POST_NORM) {
+        const double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
+        if (lane == 0) {
+            a.partial[2 * tile] = s0;
+            a.partial[2 * tile + 1] = s1;
+        }
+    }
+}
+
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
+__global__ __launch_bounds__(256) void k_march(const MarchArgs<T> a) {
+    using C = Cfg<NU, PROLONG, POST>;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    // The wave index is uniform across the wavefront; saying so keeps every row
+    // decision in scalar registers and scalar branches.
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware order: consecutive workgroup ids go to different XCDs, so give
+    // each XCD a contiguous run of tiles (neighbouring tiles share halo rows in L2).
+    const int lb = (blockIdx.x & 7) * a.groups_per_xcd + (blockIdx.x >> 3);
+    const int tile = lb * wpb + wib;
+    if (tile >= a.ntiles) return;  // whole wavefront leaves; no barriers anywhere
+    if (a.skip && *a.skip) return;
+    const int strip = tile % a.strips, chunk = tile / a.strips;
+
+    Tile tl;
+    tl.n = a.n;
+    tl.nm = a.n - 1;
+    tl.nc = a.n >> 1;
+    tl.px = a.bc[CCMG_XLO] == CCMG_BC_PERIODIC;
+    tl.py = a.bc[CCMG_YLO] == CCMG_BC_PERIODIC;
+    // columns: lane owns x0, x0 + 1 (x0 even)
+    tl.xo0 = strip * a.outw;
+    const int X0 = tl.xo0 - C::HX;
+    tl.x0 = X0 + 2 * lane;
+    const bool inx = tl.px || (tl.x0 >= 0 && tl.x0 < tl.n);
+    tl.xl = tl.px ? (tl.x0 & tl.nm) : (inx ? tl.x0 : 0);  // out-of-domain lanes read column 0
+    tl.wedge = !tl.px && tl.x0 == 0;
+    tl.eedge = !tl.px && tl.x0 + 1 == tl.nm;
+    tl.outl = tl.x0 >= tl.xo0 && tl.x0 < tl.xo0 + a.outw && tl.x0 >= 0 && tl.x0 < tl.n;
+    tl.I = tl.x0 >> 1;
+    tl.Il = PROLONG ? (tl.px ? (tl.I & (tl.nc - 1)) : min(max(tl.I, 0), tl.nc - 1)) : 0;
+    tl.cwedge = !tl.px && tl.I == 0;
+    tl.ceedge = !tl.px && tl.I == tl.nc - 1;
+    // rows
+    tl.y0 = chunk * a.ty;
+    tl.y1 = min(tl.y0 + a.ty, tl.n);
+    tl.ys = tl.py ? tl.y0 - C::HY : max(tl.y0 - C::HY, 0);
+    tl.ye = tl.py ? tl.y1 + C::HY : min(tl.y1 + C::HY, tl.n);
+
+    // does any lane / row of the tile meet a Dirichlet or Neumann side?
+    const bool xb = !tl.px && (X0 <= 0 || X0 + 128 >= tl.n - 1);
+    const bool yb = !tl.py && (tl.ys == 0 || tl.ye == tl.n);
+    if (xb) {
+        if (yb) march_tile<T, NU, LOADPHI, PROLONG, POST, true, true>(a, tl, tile);
+        else march_tile<T, NU, LOADPHI, PROLONG, POST, true, false>(a, tl, tile);
+    } else {
+        if (yb) march_tile<T, NU, LOADPHI, PROLONG, POST, false, true>(a, tl, tile);
+        else march_tile<T, NU, LOADPHI, PROLONG, POST, false, false>(a, tl, tile);
+    }
+}
+
+// ---- host side ---------------------------------------------------------------
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
+static hipError_t go(const MarchArgs<T> &a0, MarchShape sh, hipStream_t s, int *nt) {
+    MarchArgs<T> a = a0;
+    a.outw = Cfg<NU, PROLONG, POST>::OUTW;
+    a.ty = sh.ty;
+    a.strips = (a.n + a.outw - 1) / a.outw;
+    a.chunks = (a.n + a.ty - 1) / a.ty;
+    a.ntiles = a.strips * a.chunks;
+    if (nt) *nt = a.ntiles;
+    const int wpb = sh.wpb;
+    const int blocks = (a.ntiles + wpb - 1) / wpb;
+    a.groups_per_xcd = (blocks + 7) / 8;
+    const int grid = 8 * a.groups_per_xcd;
+    hipLaunchKernelGGL((k_march<T, NU, LOADPHI, PROLONG, POST>), dim3(grid), dim3(64 * wpb), 0, s, a);
+    return hipGetLastError();
+}
+
+// Launch one march variant with NU fused iterations (instantiated per NU and T
+// in the march_*.hip files).
+template <typename T, int NU>
+hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int post,
+                              MarchShape sh, hipStream_t s, int *nt) {
+    if (prolong) {
+        if (!load_phi) return hipErrorInvalidValue;
+        if (post == POST_NONE) return go<T, NU, true, true, POST_NONE>(a, sh, s, nt);
+        if (post == POST_NORM) return go<T, NU, true, true, POST_NORM>(a, sh, s, nt);
+        return hipErrorInvalidValue;
+    }
+    if (load_phi) {
+        switch (post) {
+            case POST_NONE: return go<T, NU, true, false, POST_NONE>(a, sh, s, nt);
+            case POST_RESTRICT: return go<T, NU, true, false, POST_RESTRICT>(a, sh, s, nt);
+            case POST_NORM: return go<T, NU, true, false, POST_NORM>(a, sh, s, nt);
+            case POST_RESID: return go<T, NU, true, false, POST_RESID>(a, sh, s, nt);
+        }
+    } else {
+        switch (post) {
+            case POST_NONE: return go<T, NU, false, false, POST_NONE>(a, sh, s, nt);
+            case POST_RESTRICT: return go<T, NU, false, false, POST_RESTRICT>(a, sh, s, nt);
+            case POST_NORM: return go<T, NU, false, false, POST_NORM>(a, sh, s, nt);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ccmg

@@ -108,7 +108,9 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     return true;
 }
 
-// Rows per tile: aim for ~2048 tiles (8 waves per CU) without going below kMinTy.
+// Default rows per tile (before / without autotuning): long bands on the big
+// levels keep the redundant halo rows (2 x 6 per band) small; small levels
+// need short bands so that enough wavefronts run and each finishes quickly.
 MarchShape shape_for(int n) {
     static int env_ty = -1, env_wpb = -1;
     if (env_ty < 0) {
@@ -118,14 +120,13 @@ MarchShape shape_for(int n) {
         env_wpb = w ? atoi(w) : 0;
     }
     MarchShape s;
-    s.wpb = env_wpb > 0 ? env_wpb : 4;
-    if (env_ty >= kMinTy && (env_ty & 1) == 0) {
-        s.ty = env_ty < n ? env_ty : n;
-        return s;
-    }
-    const int strips = (n + 115) / 116;
-    int ty = 128;
-    while (ty > kMinTy && (long)strips * ((n + ty - 1) / ty) < 2048) ty >>= 1;
+    s.wpb = env_wpb > 0 ? env_wpb : 1;
+    int ty;
+    if (env_ty >= kMinTy && (env_ty & 1) == 0) ty = env_ty;
+    else if (n >= 4096) ty = 64;
+    else if (n >= 2048) ty = 32;
+    else if (n >= 512) ty = 16;
+    else ty = 8;
     s.ty = ty < n ? ty : n;
     if (s.ty < 2) s.ty = 2;
     return s;
@@ -133,8 +134,27 @@ MarchShape shape_for(int n) {
 
 }  // namespace
 
+// Events bracketing finest-level launches while profiling is on.
+struct KernelTimer {
+    static constexpr int kKinds = 2;
+    static constexpr int kPairs = 1024;
+    bool on = false;
+    std::vector<hipEvent_t> ev;          // 2 * kPairs
+    int used = 0;
+    int kind[kPairs];
+    double bytes[kPairs];
+    int launches[kKinds] = {0, 0};
+    double ms[kKinds] = {0, 0}, tbytes[kKinds] = {0, 0};
+};
+
+constexpr int kMaxLevels = 16;
+
 struct ccmg_plan {
     ccmg_problem p;
+    KernelTimer timer;
+    MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
+    double *hrho = nullptr;   // host-mapped: relative residual of each cycle
+    double *drho = nullptr;   // ... its device address
     Layout lay;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
@@ -146,6 +166,31 @@ struct ccmg_plan {
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     double *scal() const { return at<double>(lay.scal); }
+
+    // Record the start event of a timed launch (returns the pair index or -1).
+    int tstart(int kind, double bytes) {
+        if (!timer.on || timer.used >= KernelTimer::kPairs) return -1;
+        const int i = timer.used++;
+        timer.kind[i] = kind;
+        timer.bytes[i] = bytes;
+        hipEventRecord(timer.ev[2 * i], stream);
+        return i;
+    }
+    void tstop(int i) {
+        if (i >= 0) hipEventRecord(timer.ev[2 * i + 1], stream);
+    }
+    // Fold finished pairs into the per-kind totals.
+    void tcollect() {
+        for (int i = 0; i < timer.used; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess) {
+                timer.launches[timer.kind[i]] += 1;
+                timer.ms[timer.kind[i]] += ms;
+                timer.tbytes[timer.kind[i]] += timer.bytes[i];
+            }
+        }
+        timer.used = 0;
+    }
     double *hist() const { return at<double>(lay.hist); }
     int *done() const { return at<int>(lay.flags); }
 };
@@ -227,7 +272,7 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
     // down
     for (int l = 0; l < lay.lt; ++l) {
         setup_bufs(l);
-        const MarchShape sh = shape_for(lay.lev[l].n);
+        const MarchShape sh = P->shp_pre[l];
         const std::vector<int> chain = split_nu(P->p.nu1);
         bool zero = (l > 0) || first_zero;
         for (size_t i = 0; i < chain.size(); ++i) {
@@ -252,7 +297,11 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
                 a.partial = P->at<double>(lay.lev[l + 1].fpart);
             }
             int nt = 0;
+            const double nn = (double)lay.lev[l].n * lay.lev[l].n;
+            const int ti = l == 0 ? P->tstart(0, sizeof(double) * nn * ((zero ? 2.0 : 3.0) + (last ? 0.25 : 0.0)))
+                                  : -1;
             e = launch_march<double>(a, chain[i], !zero, false, post, sh, s, &nt);
+            P->tstop(ti);
             if (e != hipSuccess) return e;
             if (last) fpart_count[l + 1] = nt;
             std::swap(cur[l], other[l]);
@@ -290,7 +339,7 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
     // up
     int last_nt = 0;
     for (int l = lay.lt - 1; l >= 0; --l) {
-        const MarchShape sh = shape_for(lay.lev[l].n);
+        const MarchShape sh = P->shp_post[l];
         const std::vector<int> chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
@@ -316,7 +365,10 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
                 a.partial = P->at<double>(lay.normpart);
             }
             int nt = 0;
+            const double nn = (double)lay.lev[l].n * lay.lev[l].n;
+            const int ti = l == 0 ? P->tstart(1, sizeof(double) * nn * (3.0 + (prolong ? 0.25 : 0.0))) : -1;
             e = launch_march<double>(a, chain[i], true, prolong, post, sh, s, &nt);
+            P->tstop(ti);
             if (e != hipSuccess) return e;
             if (post == POST_NORM) last_nt = nt;
             std::swap(cur[l], other[l]);
@@ -345,7 +397,7 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
         }
         e = launch_cycle_end(P->at<double>(lay.normpart), last_nt, lay.lev[0].n, P->singular ? 1 : 0,
                              P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN,
-                             P->done(), s);
+                             P->done(), P->drho + slot, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -450,8 +502,13 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     P->stream = static_cast<hipStream_t>(stream);
     P->singular = p->alpha == 0.0 && p->bc[0] != CCMG_BC_DIRICHLET && p->bc[1] != CCMG_BC_DIRICHLET &&
                   p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
+    for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&P->hrho), sizeof(double) * CCMG_HISTORY,
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&P->drho), P->hrho, 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[1], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
@@ -464,9 +521,159 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     return CCMG_OK;
 }
 
+// Time every candidate launch shape of each row-march level (the nu1 half and
+// the nu2 half of the cycle separately) on the caller's data and keep the
+// fastest.  Inputs are only read; outputs go to workspace buffers.
+int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
+    if (!P || !d_f || !d_phi) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    const Layout &lay = P->lay;
+    hipStream_t s = P->stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return CCMG_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return CCMG_EHIP;
+    }
+    // the workspace is scratch between calls: start from zeros (values do not
+    // change the timing, but keep them finite)
+    hipError_t err = hipMemsetAsync(P->ws, 0, lay.total, s);
+    const int tys[] = {8, 16, 32, 64, 128, 256};
+    const int wpbs[] = {1, 2, 4};
+    const int reps = 4;
+    for (int l = 0; l < lay.lt && err == hipSuccess; ++l) {
+        const int n = lay.lev[l].n;
+        for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
+            MarchArgs<double> a{};
+            level_consts(P, l, a);
+            if (l == 0) {
+                a.f = d_f;
+                a.pf = pitch;
+            } else {
+                a.f = P->at<double>(lay.lev[l].f);
+                a.pf = lay.lev[l].pitch;
+            }
+            int nu, post;
+            bool load_phi, prolong;
+            if (kind == 0) {  // the restricting launch of the nu1 half
+                nu = split_nu(P->p.nu1).back();
+                load_phi = l == 0;
+                prolong = false;
+                post = POST_RESTRICT;
+                a.phi_in = l == 0 ? d_phi : P->at<double>(lay.lev[l].a);
+                a.pin = l == 0 ? pitch : lay.lev[l].pitch;
+                a.phi_out = P->at<double>(lay.lev[l].b);
+                a.pout = lay.lev[l].pitch;
+                a.aux = P->at<double>(lay.lev[l + 1].f);
+                a.paux = lay.lev[l + 1].pitch;
+                a.partial = P->at<double>(lay.lev[l + 1].fpart);
+            } else {  // the prolongating launch of the nu2 half
+                nu = split_nu(P->p.nu2).front();
+                load_phi = true;
+                prolong = true;
+                post = (l == 0 && split_nu(P->p.nu2).size() == 1) ? POST_NORM : POST_NONE;
+                a.phi_in = l == 0 ? d_phi : P->at<double>(lay.lev[l].a);
+                a.pin = l == 0 ? pitch : lay.lev[l].pitch;
+                a.phi_out = P->at<double>(lay.lev[l].b);
+                a.pout = lay.lev[l].pitch;
+                a.ec = P->at<double>(lay.lev[l + 1].a);
+                a.pc = lay.lev[l + 1].pitch;
+                a.partial = P->at<double>(lay.normpart);
+            }
+            float best = 1e30f;
+            MarchShape bs = kind == 0 ? P->shp_pre[l] : P->shp_post[l];
+            for (int ty : tys) {
+                if (ty > n && ty != tys[0]) continue;
+                for (int wpb : wpbs) {
+                    MarchShape sh{ty < n ? ty : n, wpb};
+                    int nt;
+                    err = launch_march<double>(a, nu, load_phi, prolong, post, sh, s, &nt);  // warm-up
+                    if (err == hipSuccess) err = hipEventRecord(e0, s);
+                    for (int r = 0; r < reps && err == hipSuccess; ++r)
+                        err = launch_march<double>(a, nu, load_phi, prolong, post, sh, s, &nt);
+                    if (err == hipSuccess) err = hipEventRecord(e1, s);
+                    if (err == hipSuccess) err = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                    if (err != hipSuccess) break;
+                    if (ms < best) {
+                        best = ms;
+                        bs = sh;
+                    }
+                }
+                if (err != hipSuccess) break;
+            }
+            if (kind == 0) P->shp_pre[l] = bs;
+            else P->shp_post[l] = bs;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return hip_status(err);
+}
+
+int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
+    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || (kind != 0 && kind != 1)) return CCMG_EINVAL;
+    if (ty < 2 || (ty & 1) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
+    // the partial-sum buffers are sized for bands of at least kMinTy rows
+    const int n = P->lay.lev[level].n;
+    if (ty < kMinTy && ty < n) return CCMG_EINVAL;
+    MarchShape sh{ty < n ? ty : n, wpb};
+    if (kind == 0) P->shp_pre[level] = sh;
+    else P->shp_post[level] = sh;
+    return CCMG_OK;
+}
+
+int ccmg_plan_shapes(ccmg_plan *P, int *ty_pre, int *wpb_pre, int *ty_post, int *wpb_post, int max_levels) {
+    if (!P || !ty_pre || !wpb_pre || !ty_post || !wpb_post) return CCMG_EINVAL;
+    for (int l = 0; l < max_levels && l < P->lay.L && l < kMaxLevels; ++l) {
+        ty_pre[l] = P->shp_pre[l].ty;
+        wpb_pre[l] = P->shp_pre[l].wpb;
+        ty_post[l] = P->shp_post[l].ty;
+        wpb_post[l] = P->shp_post[l].wpb;
+    }
+    return CCMG_OK;
+}
+
+int ccmg_plan_profile(ccmg_plan *P, int enable) {
+    if (!P) return CCMG_EINVAL;
+    if (enable && P->timer.ev.empty()) {
+        P->timer.ev.assign(2 * KernelTimer::kPairs, nullptr);
+        for (auto &e : P->timer.ev)
+            if (hipEventCreate(&e) != hipSuccess) return CCMG_EHIP;
+    }
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return CCMG_EHIP;
+    P->timer.used = 0;
+    for (int k = 0; k < KernelTimer::kKinds; ++k) {
+        P->timer.launches[k] = 0;
+        P->timer.ms[k] = P->timer.tbytes[k] = 0.0;
+    }
+    P->timer.on = enable != 0;
+    return CCMG_OK;
+}
+
+int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *count) {
+    if (!P || !count || (max > 0 && !out)) return CCMG_EINVAL;
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return CCMG_EHIP;
+    P->tcollect();
+    static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post"};
+    *count = KernelTimer::kKinds;
+    for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
+        std::memset(&out[k], 0, sizeof(out[k]));
+        std::strncpy(out[k].name, names[k], sizeof(out[k].name) - 1);
+        out[k].launches = P->timer.launches[k];
+        out[k].ms = P->timer.ms[k];
+        out[k].bytes = P->timer.tbytes[k];
+    }
+    return CCMG_OK;
+}
+
 int ccmg_plan_destroy(ccmg_plan *P) {
     if (!P) return CCMG_EINVAL;
+    for (auto &e : P->timer.ev)
+        if (e) hipEventDestroy(e);
     if (P->hpin) hipHostFree(P->hpin);
+    if (P->hrho) hipHostFree(P->hrho);
     for (int i = 0; i < 2; ++i)
         if (P->ev_sync[i]) hipEventDestroy(P->ev_sync[i]);
     if (P->ev_t0) hipEventDestroy(P->ev_t0);
@@ -511,11 +718,10 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
         e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(n), s, &nt);
         if (e == hipSuccess)
             e = launch_cycle_end(P->at<double>(lay.normpart), nt, n, P->singular ? 1 : 0, scal + S_F2,
-                                 P->p.rtol, P->hist(), scal + S_PHIMEAN, P->done(), s);
+                                 P->p.rtol, P->hist(), scal + S_PHIMEAN, P->done(), P->drho, s);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->hpin + CCMG_HISTORY, scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(P->hpin, P->hist(), sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return R->status = CCMG_EHIP;
     const double *hs = P->hpin + CCMG_HISTORY;
@@ -529,7 +735,7 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     }
     if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
 
-    const double rho0 = use_guess ? P->hpin[0] : 1.0;
+    const double rho0 = use_guess ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
     if (use_guess && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
@@ -542,8 +748,6 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
         const double *shift = P->singular ? scal + S_PHIMEAN : nullptr;
         auto enqueue = [&](int k) -> hipError_t {  // cycle k (1-based) -> hist[k]
             hipError_t x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
-            if (x == hipSuccess)
-                x = hipMemcpyAsync(P->hpin + k, P->hist() + k, sizeof(double), hipMemcpyDeviceToHost, s);
             if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
             return x;
         };
@@ -553,7 +757,7 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
             if (e != hipSuccess) break;
             e = hipEventSynchronize(P->ev_sync[k & 1]);
             if (e != hipSuccess) break;
-            rho = P->hpin[k];
+            rho = P->hrho[k];  // written by the cycle's last kernel (host-mapped)
             R->history[k] = rho;
             cycles = k;
             if (!std::isfinite(rho)) {

@@ -63,7 +63,7 @@ hipError_t launch_fill_ghosts_f64(double *a, long pitch, int n, const int bc[4],
 // End of a cycle (see internal.h).
 __global__ __launch_bounds__(kRed) void k_cycle_end(const double *p, int count, int n, int singular,
                                                     const double *f2, double rtol, double *rho_out,
-                                                    double *phi_mean, int *done) {
+                                                    double *phi_mean, int *done, double *host_rho) {
     __shared__ double red[4];
     if (*done) return;  // uniform
     double s0 = 0.0, s1 = 0.0;
@@ -76,15 +76,17 @@ __global__ __launch_bounds__(kRed) void k_cycle_end(const double *p, int count, 
     if (threadIdx.x == 0) {
         const double rho = sqrt(s0) / sqrt(*f2);
         *rho_out = rho;
+        if (host_rho) *host_rho = rho;  // host-mapped: read by the host after the cycle's event
         *phi_mean = singular ? s1 / ((double)n * (double)n) : 0.0;
         if (rho <= rtol || !isfinite(rho)) *done = 1;
     }
 }
 
 hipError_t launch_cycle_end(const double *partial, int count, int n, int singular, const double *f2,
-                            double rtol, double *rho_out, double *phi_mean, int *done, hipStream_t s) {
+                            double rtol, double *rho_out, double *phi_mean, int *done, double *host_rho,
+                            hipStream_t s) {
     hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(kRed), 0, s, partial, count, n, singular, f2, rtol,
-                       rho_out, phi_mean, done);
+                       rho_out, phi_mean, done, host_rho);
     return hipGetLastError();
 }
 
