@@ -161,7 +161,10 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  * While profiling is on, the plan brackets each launch of the two
  * finest-level row-march kernels of a V-cycle with HIP events on its stream:
  *   "finest_pre":  nu1 relaxations + residual + four-cell restriction,
- *   "finest_post": prolongation + nu2 relaxations (+ residual norm).
+ *   "finest_post": prolongation + nu2 relaxations (+ residual norm);
+ * MIXED plans: "mixed_finest_pre" (the same in FP32) and "mixed_finest_post_ir"
+ * (FP32 prolongation + relaxations, then the FP64 update of the iterate and
+ * its FP64 residual, rounded to FP32 for the next step).
  * `bytes` is the algorithmic traffic of one launch: each valid cell of each
  * array the launch reads or writes, counted once (ghost cells and halo
  * re-reads excluded). */

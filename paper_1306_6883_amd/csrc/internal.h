@@ -8,7 +8,15 @@
 
 namespace ccmg {
 
-enum Post { POST_NONE = 0, POST_RESTRICT = 1, POST_NORM = 2, POST_RESID = 3 };
+enum Post {
+    POST_NONE = 0,
+    POST_RESTRICT = 1,  // residual -> four-cell restriction into aux (+ partial sums)
+    POST_NORM = 2,      // residual -> sum r^2, sum phi per tile
+    POST_RESID = 3,     // residual -> aux
+    POST_IR = 4,        // (float launches) relaxed e -> phi64_out = phi64_in + e, FP64 residual
+                        // of phi64_out -> r32 (+ sum r^2, sum phi64, sum r32 per tile)
+    POST_R32 = 5        // (double launches) residual -> r32 (+ the same three sums)
+};
 
 // Arguments of one row-march launch over one grid level (see march.hip).
 template <typename T>
@@ -33,6 +41,18 @@ struct MarchArgs {
     T cc, invd;          // relaxation: phi = (f + cc * sum of neighbours) * invd
     T alpha, beta, ih2;  // residual: r = f - (alpha phi - beta ih2 * lap)
     int strips, chunks, ty, outw, ntiles, groups_per_xcd;
+    // mixed precision (POST_IR / POST_R32)
+    const double *q_in;  // FP64 iterate, read (POST_IR)
+    long pq_in;
+    double *q_out;       // FP64 iterate + e, written (POST_IR)
+    long pq_out;
+    const double *g;     // FP64 right-hand side (POST_IR)
+    long pg;
+    float *r_out;        // FP32 copy of the FP64 residual
+    long pr;
+    double *partial3;    // per tile: sum of the FP32 residual (mean removal of singular problems)
+    double alpha64, beta64, ih2_64;
+    int q_zero;          // POST_IR: the FP64 iterate is zero (q_in is not used)
 };
 
 // Launch description chosen by the host for one level.

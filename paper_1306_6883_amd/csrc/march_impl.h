@@ -127,8 +127,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     const bool subf = a.fmean_part != nullptr;
     const bool subp = LOADPHI && a.phi_shift != nullptr;
     T fsub = T(0), psub = T(0);
+    double psub64 = 0.0;  // POST_IR: the shift applies to the FP64 iterate, in FP64
     if (subf) fsub = T(sum_partials(a.fmean_part, a.fmean_count) / ((double)tl.n * (double)tl.n));
-    if (subp) psub = T(*a.phi_shift);
+    if (subp) {
+        psub64 = *a.phi_shift;
+        psub = T(psub64);
+    }
 
     const int lo = 1 + tl.xl;        // element offset of this lane's first column in a row
     const int co = 1 + tl.Il;        // ... of its coarse column
@@ -138,6 +142,13 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     for (int k = 0; k < W; ++k) P0[k] = P1[k] = F0[k] = F1[k] = T(0);
 #pragma unroll
     for (int k = 0; k < WC; ++k) Cw[k] = T(0);
+    // POST_IR: FP64 iterate (Q) and right-hand side (G) rows, same slots as P / F
+    constexpr bool IR = POST == POST_IR;
+    constexpr int WQ = IR ? W : 1;
+    double Q0[WQ], Q1[WQ], G0[WQ], G1[WQ];
+#pragma unroll
+    for (int k = 0; k < WQ; ++k) Q0[k] = Q1[k] = G0[k] = G1[k] = 0.0;
+    double acc2 = 0.0;
 
     // Loads are unconditional (a conditional load into the window would force
     // the compiler to wait for it): rows past the end of the band re-read the
@@ -154,6 +165,16 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             p1 = pr[lo + 1];
         }
     };
+    auto load_row64 = [&](int y, double &q0, double &q1, double &g0, double &g1) {
+        y = min(y, ye - 1);
+        const int yy = py ? (y & nm) : y;
+        const double *qr = a.q_in + (long)(yy + 1) * a.pq_in;
+        const double *gr = a.g + (long)(yy + 1) * a.pg;
+        q0 = qr[lo];
+        q1 = qr[lo + 1];
+        g0 = gr[lo];
+        g1 = gr[lo + 1];
+    };
     auto load_coarse = [&](int J, T &c) {
         const int Jl = py ? (J & (nc - 1)) : (J < 0 ? 0 : (J >= nc ? nc - 1 : J));
         c = (a.ec + (long)(Jl + 1) * a.pc)[co];
@@ -165,6 +186,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     static_for<0, D>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         load_row(ys + k, P0[k], P1[k], F0[k], F1[k]);
+        if constexpr (IR) load_row64(ys + k, Q0[k], Q1[k], G0[k], G1[k]);
     });
     if constexpr (PROLONG) {
         static_for<0, DC + 2>([&](auto qc) {
@@ -182,6 +204,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             {
                 constexpr int kd = (k + D) % W;
                 load_row(t + D, P0[kd], P1[kd], F0[kd], F1[kd]);
+                if constexpr (IR) load_row64(t + D, Q0[kd], Q1[kd], G0[kd], G1[kd]);
             }
             if constexpr (PROLONG) {
                 if constexpr ((k & 1) == 0) load_coarse((t >> 1) + 1 + DC, Cw[((k >> 1) + 2 + DC) % WC]);
@@ -192,8 +215,17 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 F0[k] -= fsub;
                 F1[k] -= fsub;
             }
+            if constexpr (IR) {
+                if (a.q_zero) {
+                    Q0[k] = 0.0;
+                    Q1[k] = 0.0;
+                } else if (subp) {
+                    Q0[k] -= psub64;
+                    Q1[k] -= psub64;
+                }
+            }
             if (LOADPHI) {
-                if (subp) {
+                if (subp && !IR) {
                     P0[k] -= psub;
                     P1[k] -= psub;
                 }
@@ -261,18 +293,65 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     P1[kk] = (F1[kk] + cc * (((e + w) + nn) + ss)) * invd;
                 }
             });
-            // 4. store the finished row
+            // 4. store the finished row (POST_IR: add it to the FP64 iterate and store that)
             {
                 const int y = t - 2 * NU;
                 constexpr int kk = (k - 2 * NU + 2 * W) % W;
-                if (a.phi_out && y >= y0 && y < y1 && tl.outl) {
+                if constexpr (IR) {
+                    Q0[kk] += (double)P0[kk];
+                    Q1[kk] += (double)P1[kk];
+                    if (y >= y0 && y < y1 && tl.outl) {
+                        double *o = a.q_out + (long)(y + 1) * a.pq_out;
+                        o[1 + tl.x0] = Q0[kk];
+                        o[2 + tl.x0] = Q1[kk];
+                    }
+                } else if (a.phi_out && y >= y0 && y < y1 && tl.outl) {
                     T *o = a.phi_out + (long)(y + 1) * a.pout;
                     o[1 + tl.x0] = P0[kk];
                     o[2 + tl.x0] = P1[kk];
                 }
             }
             // 5. residual of the finished rows and what is made from it
-            if constexpr (POST != POST_NONE) {
+            if constexpr (IR) {
+                const int y = t - C::LAGR;
+                if (y >= y0 && y < y1) {
+                    constexpr int kk = (k - C::LAGR + 2 * W) % W;
+                    constexpr int km = (k - C::LAGR - 1 + 2 * W) % W;
+                    constexpr int kp = (k - C::LAGR + 1 + 2 * W) % W;
+                    const double p0 = Q0[kk], p1 = Q1[kk];
+                    double w0 = from_left(Q1[kk]);
+                    double e1 = from_right(Q0[kk]);
+                    if constexpr (XB) {
+                        if (tl.wedge) w0 = (double)sxl * p0;
+                        if (tl.eedge) e1 = (double)sxh * p1;
+                    }
+                    double n0 = Q0[kp], n1 = Q1[kp], s0 = Q0[km], s1 = Q1[km];
+                    if constexpr (YB) {
+                        if (y == nm) {
+                            n0 = (double)syh * p0;
+                            n1 = (double)syh * p1;
+                        }
+                        if (y == 0) {
+                            s0 = (double)syl * p0;
+                            s1 = (double)syl * p1;
+                        }
+                    }
+                    const double ih2 = a.ih2_64;
+                    const double lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                    const double lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                    const double r0 = G0[kk] - (a.alpha64 * p0 - a.beta64 * lap0);
+                    const double r1 = G1[kk] - (a.alpha64 * p1 - a.beta64 * lap1);
+                    if (tl.outl) {
+                        const float q0 = (float)r0, q1 = (float)r1;
+                        float *o = a.r_out + (long)(y + 1) * a.pr;
+                        o[1 + tl.x0] = q0;
+                        o[2 + tl.x0] = q1;
+                        acc0 += r0 * r0 + r1 * r1;
+                        acc1 += p0 + p1;
+                        acc2 += (double)q0 + (double)q1;
+                    }
+                }
+            } else if constexpr (POST != POST_NONE) {
                 const int y = t - C::LAGR;
                 if (y >= y0 && y < y1) {
                     constexpr int kk = (k - C::LAGR + 2 * W) % W;
@@ -317,6 +396,16 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             acc0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
                             acc1 += (double)p0 + (double)p1;
                         }
+                    } else if constexpr (POST == POST_R32) {
+                        if (tl.outl) {
+                            const float q0 = (float)r0, q1 = (float)r1;
+                            float *o = a.r_out + (long)(y + 1) * a.pr;
+                            o[1 + tl.x0] = q0;
+                            o[2 + tl.x0] = q1;
+                            acc0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                            acc1 += (double)p0 + (double)p1;
+                            acc2 += (double)q0 + (double)q1;
+                        }
                     } else {  // POST_RESID
                         if (tl.outl) {
                             T *o = a.aux + (long)(y + 1) * a.paux;
@@ -332,11 +421,14 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     if constexpr (POST == POST_RESTRICT) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
-    } else if constexpr (POST == POST_NORM) {
+    } else if constexpr (POST == POST_NORM || POST == POST_IR || POST == POST_R32) {
         const double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
+        double s2 = 0.0;
+        if constexpr (POST != POST_NORM) s2 = wave_sum(acc2);
         if (lane == 0) {
             a.partial[2 * tile] = s0;
             a.partial[2 * tile + 1] = s1;
+            if constexpr (POST != POST_NORM) a.partial3[tile] = s2;
         }
     }
 }
@@ -421,7 +513,20 @@ hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int p
         if (!load_phi) return hipErrorInvalidValue;
         if (post == POST_NONE) return go<T, NU, true, true, POST_NONE>(a, sh, s, nt);
         if (post == POST_NORM) return go<T, NU, true, true, POST_NORM>(a, sh, s, nt);
+        if constexpr (std::is_same<T, float>::value) {
+            if (post == POST_IR) return go<T, NU, true, true, POST_IR>(a, sh, s, nt);
+        }
         return hipErrorInvalidValue;
+    }
+    if constexpr (std::is_same<T, double>::value) {
+        if (post == POST_R32) {
+            if (load_phi) return go<T, NU, true, false, POST_R32>(a, sh, s, nt);
+            return go<T, NU, false, false, POST_R32>(a, sh, s, nt);
+        }
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        // the FP64 update after a cycle that ran entirely in the one-workgroup tail
+        if (post == POST_IR && load_phi && NU == 0) return go<T, NU, true, false, POST_IR>(a, sh, s, nt);
     }
     if (load_phi) {
         switch (post) {

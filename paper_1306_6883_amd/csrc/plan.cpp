@@ -47,7 +47,8 @@ struct LevelLay {
     int n = 0;
     double h = 0;
     long pitch = 0;        // pitch of the workspace arrays of this level
-    size_t a = 0, b = 0, f = 0;  // byte offsets (level 0 has only b)
+    size_t a = 0, b = 0, f = 0;  // byte offsets of phi (two buffers) and f in the level's precision
+    size_t f2 = 0;         // MIXED level 0: second FP32 residual buffer
     size_t fpart = 0;      // partial sums of this level's rhs
     int fpart_cap = 0;
 };
@@ -55,9 +56,12 @@ struct LevelLay {
 struct Layout {
     int L = 0;             // levels n, n/2, ..., 2
     int lt = 0;            // first level handled by the one-workgroup tail
+    size_t elem = 8;       // bytes per value of the relaxed levels (8 FP64, 4 MIXED)
     std::vector<LevelLay> lev;
+    size_t qb = 0;         // MIXED: second FP64 iterate buffer (finest level)
     size_t normpart = 0;
     int normpart_cap = 0;
+    size_t part3 = 0;      // MIXED: per-tile sums of the FP32 residual
     size_t fstats = 0;
     size_t scal = 0, hist = 0, flags = 0;
     size_t total = 0;
@@ -65,6 +69,8 @@ struct Layout {
 
 bool build_layout(const ccmg_problem &p, Layout &lay) {
     const int n = p.n;
+    const bool mixed = p.prec == CCMG_MIXED;
+    lay.elem = mixed ? sizeof(float) : sizeof(double);
     lay.L = 0;
     while ((n >> lay.L) >= 2) ++lay.L;
     lay.lev.assign(lay.L, LevelLay());
@@ -87,9 +93,15 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
         v.n = n >> l;
         v.h = h0 * (double)(1 << l);
         v.pitch = pitch_for(v.n);
-        const size_t bytes = sizeof(double) * (size_t)(v.n + 2) * (size_t)v.pitch;
-        if (l == 0) {
+        const size_t bytes = lay.elem * (size_t)(v.n + 2) * (size_t)v.pitch;
+        if (l == 0 && !mixed) {
+            v.b = take(bytes);  // the caller's phi is buffer a, its f the rhs
+        } else if (l == 0) {
+            v.a = take(bytes);  // FP32 correction e (two buffers)
             v.b = take(bytes);
+            v.f = take(bytes);  // FP32 residual r32 (two buffers)
+            v.f2 = take(bytes);
+            lay.qb = take(sizeof(double) * (size_t)(v.n + 2) * (size_t)v.pitch);
         } else if (l <= lay.lt) {
             v.a = take(bytes);
             v.b = take(bytes);
@@ -100,6 +112,7 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     }
     lay.normpart_cap = max_tiles(n);
     lay.normpart = take(sizeof(double) * 2 * lay.normpart_cap);
+    lay.part3 = take(sizeof(double) * lay.normpart_cap);
     lay.fstats = take(sizeof(double) * 4 * kStatBlocks);
     lay.scal = take(sizeof(double) * kScal);
     lay.hist = take(sizeof(double) * CCMG_HISTORY);
@@ -136,15 +149,15 @@ MarchShape shape_for(int n) {
 
 // Events bracketing finest-level launches while profiling is on.
 struct KernelTimer {
-    static constexpr int kKinds = 2;
+    static constexpr int kKinds = 4;
     static constexpr int kPairs = 1024;
     bool on = false;
     std::vector<hipEvent_t> ev;          // 2 * kPairs
     int used = 0;
     int kind[kPairs];
     double bytes[kPairs];
-    int launches[kKinds] = {0, 0};
-    double ms[kKinds] = {0, 0}, tbytes[kKinds] = {0, 0};
+    int launches[kKinds] = {0, 0, 0, 0};
+    double ms[kKinds] = {0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0};
 };
 
 constexpr int kMaxLevels = 16;
@@ -226,47 +239,106 @@ std::vector<int> split_nu(int nu) {
     return v;
 }
 
+template <typename T>
 struct Buf {
-    double *p;
+    T *p;
     long pitch;
 };
 
-// Enqueue one FP64 V-cycle.  phi0 (pitch pp0) holds the iterate and receives
-// the result.  first_zero: the iterate is zero (not read).  phi_shift: device
-// scalar subtracted from phi0 as it is read (singular problems), or null.
-// with_norm: also produce the relative residual of the result into hist[slot]
-// and the mean of phi into scal[S_PHIMEAN], and set the done flag.
-hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *phi0, long pp0,
-                            bool first_zero, const double *phi_shift, bool with_norm, int slot) {
+// What one V-cycle works on at the finest level (level 0).
+template <typename T>
+struct CycleIO {
+    const T *f0 = nullptr;         // level-0 rhs
+    long pf0 = 0;
+    T *phi0 = nullptr;             // level-0 iterate; the result ends here (unless post0 == POST_IR)
+    long pp0 = 0;
+    T *phi0b = nullptr;            // second level-0 buffer
+    long pp0b = 0;
+    bool zero = false;             // the level-0 iterate starts at zero (not read)
+    const double *phi_shift = nullptr;    // subtracted from the level-0 iterate as it is read
+    const double *f0mean_part = nullptr;  // sums whose mean is removed from f0 (singular, MIXED)
+    int f0mean_count = 0;
+    int post0 = POST_NONE;         // what the last level-0 launch does after relaxing
+    const int *skip = nullptr;
+    // POST_IR: the FP64 side of a refinement step
+    const double *q_in = nullptr;
+    long pq_in = 0;
+    double *q_out = nullptr;
+    long pq_out = 0;
+    const double *g = nullptr;
+    long pg = 0;
+    float *r_out = nullptr;
+    long pr = 0;
+    bool q_zero = false;           // the FP64 iterate is zero (first step without a guess)
+    const double *q_shift = nullptr;  // subtracted from the FP64 iterate as it is read
+};
+
+template <typename T>
+void coarse_consts(const ccmg_plan *P, int l, CoarseArgs<T> &c) {
+    for (int q = 0; q < 4; ++q) c.bc[q] = P->p.bc[q];
+    c.alpha = P->p.alpha;
+    c.beta = P->p.beta;
+    c.h_top = P->lay.lev[l].h;
+    c.nu1 = P->p.nu1;
+    c.nu2 = P->p.nu2;
+    c.nu_bottom = P->p.nu_bottom;
+    c.n_top = P->lay.lev[l].n;
+}
+
+// Enqueue one V-cycle in precision T.  Returns in *norm_tiles the tile count of
+// the launch that wrote per-tile norm partials (POST_NORM / POST_IR), else 0.
+template <typename T>
+hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     const Layout &lay = P->lay;
-    const MarchShape *dummy = nullptr;
-    (void)dummy;
     hipStream_t s = P->stream;
     hipError_t e;
-    std::vector<Buf> cur(lay.L), other(lay.L);
+    std::vector<Buf<T>> cur(lay.L), other(lay.L);
     std::vector<int> fpart_count(lay.L, 0);
-    const int *skip = with_norm ? P->done() : nullptr;
+    const bool f64 = sizeof(T) == sizeof(double);
+    *norm_tiles = 0;
 
-    auto fptr = [&](int l) -> Buf {
-        if (l == 0) return Buf{const_cast<double *>(f0), pf0};
-        return Buf{P->at<double>(lay.lev[l].f), lay.lev[l].pitch};
+    auto fptr = [&](int l) -> Buf<T> {
+        if (l == 0) return Buf<T>{const_cast<T *>(io.f0), io.pf0};
+        return Buf<T>{P->at<T>(lay.lev[l].f), lay.lev[l].pitch};
     };
     auto setup_bufs = [&](int l) {
         if (l == 0) {
-            cur[0] = Buf{phi0, pp0};
-            other[0] = Buf{P->at<double>(lay.lev[0].b), lay.lev[0].pitch};
+            cur[0] = Buf<T>{io.phi0, io.pp0};
+            other[0] = Buf<T>{io.phi0b, io.pp0b};
         } else {
-            cur[l] = Buf{P->at<double>(lay.lev[l].a), lay.lev[l].pitch};
-            other[l] = Buf{P->at<double>(lay.lev[l].b), lay.lev[l].pitch};
+            cur[l] = Buf<T>{P->at<T>(lay.lev[l].a), lay.lev[l].pitch};
+            other[l] = Buf<T>{P->at<T>(lay.lev[l].b), lay.lev[l].pitch};
         }
     };
-    auto fmean = [&](int l, MarchArgs<double> &a) {
+    auto fmean = [&](int l, MarchArgs<T> &a) {
         a.fmean_part = nullptr;
         a.fmean_count = 0;
-        if (P->singular && l > 0) {
+        if (!P->singular) return;
+        if (l > 0) {
             a.fmean_part = P->at<double>(lay.lev[l].fpart);
             a.fmean_count = fpart_count[l];
+        } else if (io.f0mean_part) {
+            a.fmean_part = io.f0mean_part;
+            a.fmean_count = io.f0mean_count;
         }
+    };
+    auto ir_args = [&](MarchArgs<T> &a) {
+        a.q_in = io.q_in;
+        a.pq_in = io.pq_in;
+        a.q_out = io.q_out;
+        a.pq_out = io.pq_out;
+        a.g = io.g;
+        a.pg = io.pg;
+        a.r_out = io.r_out;
+        a.pr = io.pr;
+        a.q_zero = io.q_zero ? 1 : 0;
+        a.phi_shift = io.q_shift;
+        a.partial = P->at<double>(lay.normpart);
+        a.partial3 = P->at<double>(lay.part3);
+        const double h = lay.lev[0].h;
+        a.alpha64 = P->p.alpha;
+        a.beta64 = P->p.beta;
+        a.ih2_64 = 1.0 / (h * h);
     };
 
     // down
@@ -274,12 +346,12 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
         setup_bufs(l);
         const MarchShape sh = P->shp_pre[l];
         const std::vector<int> chain = split_nu(P->p.nu1);
-        bool zero = (l > 0) || first_zero;
+        bool zero = (l > 0) || io.zero;
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
-            MarchArgs<double> a{};
+            MarchArgs<T> a{};
             level_consts(P, l, a);
-            const Buf fb = fptr(l);
+            const Buf<T> fb = fptr(l);
             a.f = fb.p;
             a.pf = fb.pitch;
             fmean(l, a);
@@ -287,20 +359,20 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
             a.pin = cur[l].pitch;
             a.phi_out = other[l].p;
             a.pout = other[l].pitch;
-            a.phi_shift = (l == 0 && i == 0 && !zero) ? phi_shift : nullptr;
-            a.skip = skip;
+            a.phi_shift = (l == 0 && i == 0 && !zero) ? io.phi_shift : nullptr;
+            a.skip = io.skip;
             int post = POST_NONE;
             if (last) {
                 post = POST_RESTRICT;
-                a.aux = P->at<double>(lay.lev[l + 1].f);
+                a.aux = P->at<T>(lay.lev[l + 1].f);
                 a.paux = lay.lev[l + 1].pitch;
                 a.partial = P->at<double>(lay.lev[l + 1].fpart);
             }
             int nt = 0;
             const double nn = (double)lay.lev[l].n * lay.lev[l].n;
-            const int ti = l == 0 ? P->tstart(0, sizeof(double) * nn * ((zero ? 2.0 : 3.0) + (last ? 0.25 : 0.0)))
+            const int ti = l == 0 ? P->tstart(f64 ? 0 : 2, sizeof(T) * nn * ((zero ? 2.0 : 3.0) + (last ? 0.25 : 0.0)))
                                   : -1;
-            e = launch_march<double>(a, chain[i], !zero, false, post, sh, s, &nt);
+            e = launch_march<T>(a, chain[i], !zero, false, post, sh, s, &nt);
             P->tstop(ti);
             if (e != hipSuccess) return e;
             if (last) fpart_count[l + 1] = nt;
@@ -312,40 +384,33 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
     {
         const int l = lay.lt;
         setup_bufs(l);
-        CoarseArgs<double> c{};
-        const Buf fb = fptr(l);
+        CoarseArgs<T> c{};
+        coarse_consts(P, l, c);
+        const Buf<T> fb = fptr(l);
         c.f = fb.p;
         c.pf = fb.pitch;
-        c.load_phi = (l == 0 && !first_zero) ? 1 : 0;
+        c.load_phi = (l == 0 && !io.zero) ? 1 : 0;
         c.phi_in = cur[l].p;
         c.pin = cur[l].pitch;
         c.phi_out = cur[l].p;  // the tail reads everything into LDS first
         c.pout = cur[l].pitch;
-        c.phi_shift = (l == 0) ? phi_shift : nullptr;
-        c.skip = skip;
-        c.n_top = lay.lev[l].n;
-        for (int q = 0; q < 4; ++q) c.bc[q] = P->p.bc[q];
-        c.alpha = P->p.alpha;
-        c.beta = P->p.beta;
-        c.h_top = lay.lev[l].h;
-        c.nu1 = P->p.nu1;
-        c.nu2 = P->p.nu2;
-        c.nu_bottom = P->p.nu_bottom;
-        c.sub_top_mean = (P->singular && l > 0) ? 1 : 0;
+        c.phi_shift = (l == 0) ? io.phi_shift : nullptr;
+        c.skip = io.skip;
+        // the top rhs is a restricted residual (or, MIXED, the FP32 residual): remove its mean
+        c.sub_top_mean = (P->singular && (l > 0 || !f64)) ? 1 : 0;
         c.singular = P->singular ? 1 : 0;
-        e = launch_coarse<double>(c, s);
+        e = launch_coarse<T>(c, s);
         if (e != hipSuccess) return e;
     }
     // up
-    int last_nt = 0;
     for (int l = lay.lt - 1; l >= 0; --l) {
         const MarchShape sh = P->shp_post[l];
         const std::vector<int> chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
-            MarchArgs<double> a{};
+            MarchArgs<T> a{};
             level_consts(P, l, a);
-            const Buf fb = fptr(l);
+            const Buf<T> fb = fptr(l);
             a.f = fb.p;
             a.pf = fb.pitch;
             fmean(l, a);
@@ -353,54 +418,154 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
             a.pin = cur[l].pitch;
             a.phi_out = other[l].p;
             a.pout = other[l].pitch;
-            a.skip = skip;
+            a.skip = io.skip;
             const bool prolong = i == 0;
             if (prolong) {
                 a.ec = cur[l + 1].p;
                 a.pc = cur[l + 1].pitch;
             }
             int post = POST_NONE;
-            if (last && l == 0 && with_norm) {
-                post = POST_NORM;
-                a.partial = P->at<double>(lay.normpart);
+            if (last && l == 0 && io.post0 != POST_NONE) {
+                post = io.post0;
+                if (post == POST_IR) ir_args(a);
+                else a.partial = P->at<double>(lay.normpart);
             }
             int nt = 0;
             const double nn = (double)lay.lev[l].n * lay.lev[l].n;
-            const int ti = l == 0 ? P->tstart(1, sizeof(double) * nn * (3.0 + (prolong ? 0.25 : 0.0))) : -1;
-            e = launch_march<double>(a, chain[i], true, prolong, post, sh, s, &nt);
+            // POST_IR also reads the FP64 iterate and rhs, writes the iterate and the FP32 residual
+            const double tb = sizeof(T) * nn * (3.0 + (prolong ? 0.25 : 0.0)) +
+                              (post == POST_IR ? nn * (3.0 * sizeof(double) + sizeof(float)) : 0.0);
+            const int ti = l == 0 ? P->tstart(f64 ? 1 : 3, tb) : -1;
+            e = launch_march<T>(a, chain[i], true, prolong, post, sh, s, &nt);
             P->tstop(ti);
             if (e != hipSuccess) return e;
-            if (post == POST_NORM) last_nt = nt;
+            if (post != POST_NONE) *norm_tiles = nt;
             std::swap(cur[l], other[l]);
         }
     }
     // the result must end in phi0
-    if (lay.lt > 0 && cur[0].p != phi0) {
-        e = hipMemcpy2DAsync(phi0 + pp0 + 1, sizeof(double) * pp0, cur[0].p + cur[0].pitch + 1,
-                             sizeof(double) * cur[0].pitch, sizeof(double) * lay.lev[0].n, lay.lev[0].n,
+    if (lay.lt > 0 && io.post0 != POST_IR && cur[0].p != io.phi0) {
+        e = hipMemcpy2DAsync(io.phi0 + io.pp0 + 1, sizeof(T) * io.pp0, cur[0].p + cur[0].pitch + 1,
+                             sizeof(T) * cur[0].pitch, sizeof(T) * lay.lev[0].n, lay.lev[0].n,
                              hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
-    if (with_norm) {
-        if (lay.lt == 0) {
-            // the whole cycle ran in the tail: one residual pass for the norm
-            MarchArgs<double> a{};
-            level_consts(P, 0, a);
-            a.f = f0;
-            a.pf = pf0;
-            a.phi_in = phi0;
-            a.pin = pp0;
-            a.partial = P->at<double>(lay.normpart);
-            a.skip = skip;
-            e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(lay.lev[0].n), s, &last_nt);
-            if (e != hipSuccess) return e;
-        }
-        e = launch_cycle_end(P->at<double>(lay.normpart), last_nt, lay.lev[0].n, P->singular ? 1 : 0,
-                             P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN,
-                             P->done(), P->drho + slot, s);
+    if (lay.lt == 0 && io.post0 != POST_NONE) {
+        // the whole cycle ran in the tail: one more pass over level 0 for the norm
+        // (and, MIXED, the FP64 update)
+        MarchArgs<T> a{};
+        level_consts(P, 0, a);
+        a.f = io.f0;
+        a.pf = io.pf0;
+        a.phi_in = io.phi0;
+        a.pin = io.pp0;
+        a.skip = io.skip;
+        if (io.post0 == POST_IR) ir_args(a);
+        else a.partial = P->at<double>(lay.normpart);
+        e = launch_march<T>(a, 0, true, false, io.post0, shape_for(lay.lev[0].n), s, norm_tiles);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// One FP64 V-cycle on the caller's arrays (the plain form).
+hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *phi0, long pp0, bool first_zero,
+                            const double *phi_shift, bool with_norm, int slot) {
+    CycleIO<double> io;
+    io.f0 = f0;
+    io.pf0 = pf0;
+    io.phi0 = phi0;
+    io.pp0 = pp0;
+    io.phi0b = P->at<double>(P->lay.lev[0].b);
+    io.pp0b = P->lay.lev[0].pitch;
+    io.zero = first_zero;
+    io.phi_shift = phi_shift;
+    io.post0 = with_norm ? POST_NORM : POST_NONE;
+    io.skip = with_norm ? P->done() : nullptr;
+    int nt = 0;
+    hipError_t e = enqueue_cycle<double>(P, io, &nt);
+    if (e == hipSuccess && with_norm)
+        e = launch_cycle_end(P->at<double>(P->lay.normpart), nt, P->lay.lev[0].n, P->singular ? 1 : 0,
+                             P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(),
+                             P->drho + slot, P->stream);
+    return e;
+}
+
+// State of the mixed-precision refinement between steps: which of the two FP64
+// iterate buffers and which of the two FP32 residual buffers are current.
+struct MixedState {
+    double *q;     // current FP64 iterate
+    long pq;
+    double *qo;    // the other FP64 buffer
+    long pqo;
+    float *r;      // current FP32 residual (rhs of the next correction)
+    float *ro;
+    long pr;
+    int r_tiles;   // tiles of the launch that wrote the current residual's partial sums
+    bool q_zero;   // the FP64 iterate is still zero
+};
+
+// r32 = f - A phi64 in FP64 (and its norm -> hist[slot]); phi64 is not changed.
+hipError_t enqueue_mixed_start(ccmg_plan *P, const double *d_f, long pf, MixedState &st, bool use_guess, int slot) {
+    MarchArgs<double> a{};
+    level_consts(P, 0, a);
+    a.f = d_f;
+    a.pf = pf;
+    a.phi_in = st.q;
+    a.pin = st.pq;
+    a.r_out = st.r;
+    a.pr = st.pr;
+    a.partial = P->at<double>(P->lay.normpart);
+    a.partial3 = P->at<double>(P->lay.part3);
+    int nt = 0;
+    hipError_t e = launch_march<double>(a, 0, use_guess, false, POST_R32, P->shp_pre[0], P->stream, &nt);
+    st.r_tiles = nt;
+    if (e == hipSuccess)
+        e = launch_cycle_end(P->at<double>(P->lay.normpart), nt, P->lay.lev[0].n, P->singular ? 1 : 0,
+                             P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(),
+                             P->drho + slot, P->stream);
+    return e;
+}
+
+// One refinement step: an FP32 V-cycle for A e = r32 from e = 0, then (fused
+// into its last launch) phi64 += e and the new FP64 residual -> r32.
+hipError_t enqueue_mixed_step(ccmg_plan *P, const double *d_f, long pf, MixedState &st, const int *skip,
+                              int slot) {
+    const Layout &lay = P->lay;
+    CycleIO<float> io;
+    io.f0 = st.r;
+    io.pf0 = st.pr;
+    io.phi0 = P->at<float>(lay.lev[0].a);
+    io.pp0 = lay.lev[0].pitch;
+    io.phi0b = P->at<float>(lay.lev[0].b);
+    io.pp0b = lay.lev[0].pitch;
+    io.zero = true;
+    io.f0mean_part = P->at<double>(lay.part3);
+    io.f0mean_count = st.r_tiles;
+    io.post0 = POST_IR;
+    io.skip = skip;
+    io.q_in = st.q;
+    io.pq_in = st.pq;
+    io.q_out = st.qo;
+    io.pq_out = st.pqo;
+    io.g = d_f;
+    io.pg = pf;
+    io.r_out = st.ro;
+    io.pr = st.pr;
+    io.q_zero = st.q_zero;
+    // the mean of phi64 from the last norm pass is removed as it is read
+    io.q_shift = P->singular ? P->scal() + S_PHIMEAN : nullptr;
+    int nt = 0;
+    hipError_t e = enqueue_cycle<float>(P, io, &nt);
+    if (e != hipSuccess) return e;
+    std::swap(st.q, st.qo);
+    std::swap(st.pq, st.pqo);
+    std::swap(st.r, st.ro);
+    st.r_tiles = nt;
+    st.q_zero = false;
+    return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0, P->scal() + S_F2,
+                            P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, skip ? P->done() : nullptr,
+                            skip ? P->drho + slot : nullptr, P->stream);
 }
 
 int check_pitch(const ccmg_plan *P, int level, ptrdiff_t pitch) {
@@ -489,7 +654,6 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     *out = nullptr;
     int st = ccmg_problem_check(p);
     if (st != CCMG_OK) return st;
-    if (p->prec != CCMG_FP64) return CCMG_EINVAL;  // set up below once the mixed form exists
     ccmg_plan *P = new (std::nothrow) ccmg_plan();
     if (!P) return CCMG_EINVAL;
     P->p = *p;
@@ -521,19 +685,22 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     return CCMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
 // Time every candidate launch shape of each row-march level (the nu1 half and
-// the nu2 half of the cycle separately) on the caller's data and keep the
-// fastest.  Inputs are only read; outputs go to workspace buffers.
-int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
-    if (!P || !d_f || !d_phi) return CCMG_EINVAL;
-    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+// the nu2 half of the cycle separately) and keep the fastest.  T is the
+// precision of the relaxed levels (double for FP64 plans, float for MIXED).
+template <typename T>
+hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
     const Layout &lay = P->lay;
     hipStream_t s = P->stream;
+    const bool f64 = sizeof(T) == sizeof(double);
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return CCMG_EHIP;
+    if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
     if (hipEventCreate(&e1) != hipSuccess) {
         hipEventDestroy(e0);
-        return CCMG_EHIP;
+        return hipErrorOutOfMemory;
     }
     // the workspace is scratch between calls: start from zeros (values do not
     // change the timing, but keep them finite)
@@ -544,41 +711,56 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
     for (int l = 0; l < lay.lt && err == hipSuccess; ++l) {
         const int n = lay.lev[l].n;
         for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
-            MarchArgs<double> a{};
+            MarchArgs<T> a{};
             level_consts(P, l, a);
-            if (l == 0) {
-                a.f = d_f;
+            if (l == 0 && f64) {
+                a.f = reinterpret_cast<const T *>(d_f);
                 a.pf = pitch;
             } else {
-                a.f = P->at<double>(lay.lev[l].f);
+                a.f = P->at<T>(lay.lev[l].f);
                 a.pf = lay.lev[l].pitch;
             }
+            const bool caller_phi = l == 0 && f64;
+            T *pa = caller_phi ? reinterpret_cast<T *>(d_phi) : P->at<T>(lay.lev[l].a);
+            const long ppa = caller_phi ? pitch : lay.lev[l].pitch;
             int nu, post;
             bool load_phi, prolong;
+            a.phi_in = pa;
+            a.pin = ppa;
+            a.phi_out = P->at<T>(lay.lev[l].b);
+            a.pout = lay.lev[l].pitch;
             if (kind == 0) {  // the restricting launch of the nu1 half
                 nu = split_nu(P->p.nu1).back();
-                load_phi = l == 0;
+                load_phi = l == 0 && f64;
                 prolong = false;
                 post = POST_RESTRICT;
-                a.phi_in = l == 0 ? d_phi : P->at<double>(lay.lev[l].a);
-                a.pin = l == 0 ? pitch : lay.lev[l].pitch;
-                a.phi_out = P->at<double>(lay.lev[l].b);
-                a.pout = lay.lev[l].pitch;
-                a.aux = P->at<double>(lay.lev[l + 1].f);
+                a.aux = P->at<T>(lay.lev[l + 1].f);
                 a.paux = lay.lev[l + 1].pitch;
                 a.partial = P->at<double>(lay.lev[l + 1].fpart);
             } else {  // the prolongating launch of the nu2 half
                 nu = split_nu(P->p.nu2).front();
                 load_phi = true;
                 prolong = true;
-                post = (l == 0 && split_nu(P->p.nu2).size() == 1) ? POST_NORM : POST_NONE;
-                a.phi_in = l == 0 ? d_phi : P->at<double>(lay.lev[l].a);
-                a.pin = l == 0 ? pitch : lay.lev[l].pitch;
-                a.phi_out = P->at<double>(lay.lev[l].b);
-                a.pout = lay.lev[l].pitch;
-                a.ec = P->at<double>(lay.lev[l + 1].a);
+                const bool single = split_nu(P->p.nu2).size() == 1;
+                post = POST_NONE;
+                if (l == 0 && single) post = f64 ? POST_NORM : POST_IR;
+                a.ec = P->at<T>(lay.lev[l + 1].a);
                 a.pc = lay.lev[l + 1].pitch;
                 a.partial = P->at<double>(lay.normpart);
+                if (post == POST_IR) {
+                    a.q_in = d_phi;  // read only
+                    a.pq_in = pitch;
+                    a.q_out = P->at<double>(lay.qb);
+                    a.pq_out = lay.lev[0].pitch;
+                    a.g = d_f;
+                    a.pg = pitch;
+                    a.r_out = P->at<float>(lay.lev[0].f2);
+                    a.pr = lay.lev[0].pitch;
+                    a.partial3 = P->at<double>(lay.part3);
+                    a.alpha64 = P->p.alpha;
+                    a.beta64 = P->p.beta;
+                    a.ih2_64 = 1.0 / (lay.lev[0].h * lay.lev[0].h);
+                }
             }
             float best = 1e30f;
             MarchShape bs = kind == 0 ? P->shp_pre[l] : P->shp_post[l];
@@ -587,10 +769,10 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
                 for (int wpb : wpbs) {
                     MarchShape sh{ty < n ? ty : n, wpb};
                     int nt;
-                    err = launch_march<double>(a, nu, load_phi, prolong, post, sh, s, &nt);  // warm-up
+                    err = launch_march<T>(a, nu, load_phi, prolong, post, sh, s, &nt);  // warm-up
                     if (err == hipSuccess) err = hipEventRecord(e0, s);
                     for (int r = 0; r < reps && err == hipSuccess; ++r)
-                        err = launch_march<double>(a, nu, load_phi, prolong, post, sh, s, &nt);
+                        err = launch_march<T>(a, nu, load_phi, prolong, post, sh, s, &nt);
                     if (err == hipSuccess) err = hipEventRecord(e1, s);
                     if (err == hipSuccess) err = hipEventSynchronize(e1);
                     float ms = 0.f;
@@ -609,7 +791,19 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    return hip_status(err);
+    return err;
+}
+}  // namespace
+
+extern "C" {
+
+// Autotune the launch shapes of every row-march level on the caller's data.
+// Inputs are only read; outputs go to workspace buffers.
+int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
+    if (!P || !d_f || !d_phi) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    if (P->p.prec == CCMG_MIXED) return hip_status(autotune_levels<float>(P, d_f, d_phi, pitch));
+    return hip_status(autotune_levels<double>(P, d_f, d_phi, pitch));
 }
 
 int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
@@ -656,7 +850,8 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     if (!P || !count || (max > 0 && !out)) return CCMG_EINVAL;
     if (hipStreamSynchronize(P->stream) != hipSuccess) return CCMG_EHIP;
     P->tcollect();
-    static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post"};
+    static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post", "mixed_finest_pre",
+                                                      "mixed_finest_post_ir"};
     *count = KernelTimer::kKinds;
     for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
         std::memset(&out[k], 0, sizeof(out[k]));
@@ -682,10 +877,52 @@ int ccmg_plan_destroy(ccmg_plan *P) {
     return CCMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+MixedState mixed_state(ccmg_plan *P, double *d_phi, ptrdiff_t pitch, bool q_zero) {
+    const Layout &lay = P->lay;
+    MixedState st;
+    st.q = d_phi;
+    st.pq = pitch;
+    st.qo = P->at<double>(lay.qb);
+    st.pqo = lay.lev[0].pitch;
+    st.r = P->at<float>(lay.lev[0].f);
+    st.ro = P->at<float>(lay.lev[0].f2);
+    st.pr = lay.lev[0].pitch;
+    st.r_tiles = 0;
+    st.q_zero = q_zero;
+    return st;
+}
+
+// Copy the valid cells of an FP64 level-0 array (the iterate ended in the workspace).
+hipError_t copy_valid(double *dst, long pd, const double *src, long ps, int n, hipStream_t s) {
+    if (dst == src) return hipSuccess;
+    return hipMemcpy2DAsync(dst + pd + 1, sizeof(double) * pd, src + ps + 1, sizeof(double) * ps,
+                            sizeof(double) * n, n, hipMemcpyDeviceToDevice, s);
+}
+}  // namespace
+
+extern "C" {
+
 int ccmg_vcycle(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch) {
     if (!P || !d_f || !d_phi) return CCMG_EINVAL;
     if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
-    return hip_status(enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, false, nullptr, false, 0));
+    if (P->p.prec == CCMG_FP64)
+        return hip_status(enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, false, nullptr, false, 0));
+    // MIXED: one refinement step in place
+    MixedState st = mixed_state(P, d_phi, pitch, false);
+    hipError_t e = launch_set_int(P->done(), 1, 0, P->stream);
+    if (e == hipSuccess) e = launch_set(P->scal(), kScal, 0.0, P->stream);
+    if (e == hipSuccess) e = launch_fstats(d_f, pitch, P->lay.lev[0].n, P->at<double>(P->lay.fstats), kStatBlocks,
+                                           P->scal() + S_FSUM, P->stream);
+    if (e == hipSuccess) e = enqueue_mixed_start(P, d_f, pitch, st, true, 0);
+    // the start pass may have set the done flag; the hook always runs the step
+    if (e == hipSuccess) e = launch_set_int(P->done(), 1, 0, P->stream);
+    if (e == hipSuccess) e = launch_set(P->scal() + S_PHIMEAN, 1, 0.0, P->stream);
+    if (e == hipSuccess) e = enqueue_mixed_step(P, d_f, pitch, st, nullptr, 1);
+    if (e == hipSuccess) e = copy_valid(d_phi, pitch, st.q, st.pq, P->lay.lev[0].n, P->stream);
+    return hip_status(e);
 }
 
 int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
@@ -698,6 +935,7 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     hipStream_t s = P->stream;
     const Layout &lay = P->lay;
     const int n = lay.lev[0].n;
+    const bool mixed = P->p.prec == CCMG_MIXED;
     double *scal = P->scal();
     hipError_t e = hipEventRecord(P->ev_t0, s);
 
@@ -706,7 +944,10 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     if (e == hipSuccess) e = launch_set(scal, kScal, 0.0, s);
     if (e == hipSuccess)
         e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
-    if (e == hipSuccess && use_guess) {
+    MixedState st = mixed_state(P, d_phi, pitch, !use_guess);
+    if (e == hipSuccess && mixed) {
+        e = enqueue_mixed_start(P, d_f, pitch, st, use_guess != 0, 0);  // r32, rho0 -> hist[0]
+    } else if (e == hipSuccess && use_guess) {
         MarchArgs<double> a{};
         level_consts(P, 0, a);
         a.f = d_f;
@@ -735,29 +976,37 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     }
     if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
 
-    const double rho0 = use_guess ? P->hrho[0] : 1.0;
+    const double rho0 = (use_guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
-    if (use_guess && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
+    if (!std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
     int status = CCMG_NOT_CONVERGED;
     int cycles = 0;
     double rho = rho0;
+    // MIXED: where the iterate is after each step (steps queued past convergence do nothing)
+    std::vector<MixedState> after(P->p.max_cycles + 2, st);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;
     } else if (P->p.max_cycles > 0) {
         const double *shift = P->singular ? scal + S_PHIMEAN : nullptr;
-        auto enqueue = [&](int k) -> hipError_t {  // cycle k (1-based) -> hist[k]
-            hipError_t x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
+        auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
+            hipError_t x;
+            if (mixed) {
+                x = enqueue_mixed_step(P, d_f, pitch, st, P->done(), k);
+                after[k] = st;
+            } else {
+                x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
+            }
             if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
             return x;
         };
         e = enqueue(1);
         for (int k = 1; e == hipSuccess; ++k) {
-            if (k < P->p.max_cycles) e = enqueue(k + 1);  // runs as no-ops if cycle k converges
+            if (k < P->p.max_cycles) e = enqueue(k + 1);  // runs as no-ops if step k converges
             if (e != hipSuccess) break;
             e = hipEventSynchronize(P->ev_sync[k & 1]);
             if (e != hipSuccess) break;
-            rho = P->hrho[k];  // written by the cycle's last kernel (host-mapped)
+            rho = P->hrho[k];  // written by the step's last kernel (host-mapped)
             R->history[k] = rho;
             cycles = k;
             if (!std::isfinite(rho)) {
@@ -771,6 +1020,14 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
             if (k >= P->p.max_cycles) break;
         }
         if (e != hipSuccess) return R->status = CCMG_EHIP;
+    }
+    if (mixed) {
+        // the FP64 iterate of the last step that ran (or the guess / zero)
+        const MixedState &fin = cycles > 0 ? after[cycles] : st;
+        if (fin.q_zero) e = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
+        else e = copy_valid(d_phi, pitch, fin.q, fin.pq, n, s);
+        if (e != hipSuccess) return R->status = CCMG_EHIP;
+        R->inner_cycles = cycles;
     }
     // output: zero-mean representative for singular problems, ghost cells filled
     e = launch_fill_ghosts_f64(d_phi, pitch, n, P->p.bc, P->singular ? scal + S_PHIMEAN : nullptr, s);

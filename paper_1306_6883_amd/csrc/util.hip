@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kRed) void k_cycle_end(const double *p, int count, 
                                                     const double *f2, double rtol, double *rho_out,
                                                     double *phi_mean, int *done, double *host_rho) {
     __shared__ double red[4];
-    if (*done) return;  // uniform
+    if (done && *done) return;  // uniform
     double s0 = 0.0, s1 = 0.0;
     for (int i = threadIdx.x; i < count; i += kRed) {
         s0 += p[2 * i];
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kRed) void k_cycle_end(const double *p, int count, 
         *rho_out = rho;
         if (host_rho) *host_rho = rho;  // host-mapped: read by the host after the cycle's event
         *phi_mean = singular ? s1 / ((double)n * (double)n) : 0.0;
-        if (rho <= rtol || !isfinite(rho)) *done = 1;
+        if (done && (rho <= rtol || !isfinite(rho))) *done = 1;
     }
 }
 

@@ -1,0 +1,121 @@
+"""Mixed-precision form (FP32 V-cycles, FP64 residual and correction) against
+the FP64 oracle: the converged iterate meets the same FP64 tolerances as the
+plain form."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import exact
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_1306_6883_amd")
+
+
+def dev_field(a, pad=3):
+    n = a.shape[0] - 2
+    t = torch.zeros((n + 2, n + 2 + pad), dtype=torch.float64, device="cuda")
+    t[:, :n + 2] = torch.from_numpy(a).cuda()
+    return t
+
+
+def host(t):
+    n = t.shape[0] - 2
+    return t[:, :n + 2].cpu().numpy()
+
+
+def mixed_plan(n, bc, alpha=0.0, beta=-1.0, **kw):
+    return cc.Plan(cc.Problem(n=n, bc=tuple(bc), alpha=alpha, beta=beta, prec=cc.MIXED, **kw))
+
+
+@pytest.mark.parametrize("bc", ["PPPP", "DDDD", "NNNN", "DNPP", "PPDD"])
+@pytest.mark.parametrize("n", [8, 32, 64, 256, 1024])
+def test_mixed_solve_meets_fp64_tolerance(bc, n):
+    h = 1.0 / n
+    sing = exact.is_singular(0.0, bc)
+    fv = np.random.default_rng(21).standard_normal((n, n))
+    if sing:
+        fv -= fv.mean()
+    plan = mixed_plan(n, bc)
+    d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, d_f, d_phi)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10
+    got = oracle.interior(host(d_phi))
+    # the FP64 residual of the returned field, recomputed on the host
+    assert exact.relative_residual(got, fv, h, 0.0, -1.0, bc) <= 1.5e-10
+    _, ro = oracle.solve(oracle.Problem(n=n, h=h, bc=bc, rtol=1e-10), oracle.embed(fv))
+    assert r.cycles <= ro.cycles + 2
+    if bc[0] == bc[1] and bc[2] == bc[3]:
+        x = exact.transform_solve(fv, h, 0.0, -1.0, bc)
+        assert np.linalg.norm(got - x) / np.linalg.norm(x) < 1e-9
+    if sing:
+        assert abs(got.mean()) < 1e-13 * np.abs(got).max()
+
+
+@pytest.mark.parametrize("bc", ["PPPP", "DDDD", "DNPP"])
+def test_mixed_step_matches_fp64_vcycle(bc):
+    """One refinement step = phi + (FP32 V-cycle for A e = r from 0); the FP64
+    V-cycle from phi is phi + B r with the same B, so the two agree to FP32
+    rounding of the correction."""
+    n = 256
+    h = 1.0 / n
+    fv = np.random.default_rng(22).standard_normal((n, n))
+    if "D" not in bc:
+        fv -= fv.mean()
+    phi0 = oracle.embed(np.random.default_rng(23).standard_normal((n, n)))
+    plan = mixed_plan(n, bc)
+    d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(phi0)
+    cc.ccmg_vcycle(plan, d_f, d_phi)
+    got = oracle.interior(host(d_phi))
+    ref = phi0.copy()
+    oracle.vcycle(oracle.Problem(n=n, h=h, bc=bc), ref, oracle.embed(fv))
+    corr = oracle.interior(ref) - oracle.interior(phi0)
+    err = np.linalg.norm(got - oracle.interior(ref)) / np.linalg.norm(corr)
+    assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("c", [0.1, 1.0, 10.0])
+def test_mixed_crank_nicolson_helmholtz(c):
+    """(1 - (k dt / 2) Lap) phi = g with k dt / h^2 = c, g a Gaussian random field."""
+    n = 1024
+    h = 1.0 / n
+    beta = c * h * h / 2
+    g = W.gaussian_random_field(n, seed=1)
+    plan = mixed_plan(n, "PPPP", alpha=1.0, beta=beta)
+    d_f, d_phi = dev_field(oracle.embed(g)), dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, d_f, d_phi)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10
+    x = exact.transform_solve(g, h, 1.0, beta, "PPPP")
+    got = oracle.interior(host(d_phi))
+    assert np.linalg.norm(got - x) / np.linalg.norm(x) < 1e-9
+    assert exact.relative_residual(got, g, h, 1.0, beta, "PPPP") <= 1.5e-10
+
+
+def test_mixed_large_poisson_periodic():
+    n = 4096
+    h = 1.0 / n
+    fv = W.fourier_modes(n, seed=0)
+    plan = mixed_plan(n, "PPPP")
+    d_f, d_phi = dev_field(oracle.embed(fv), pad=0), dev_field(oracle.field_zeros(n), pad=0)
+    cc.ccmg_plan_autotune(plan, d_f, d_phi)
+    r = cc.ccmg_solve(plan, d_f, d_phi)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10
+    got = oracle.interior(host(d_phi))
+    x = exact.transform_solve(fv, h, 0.0, -1.0, "PPPP")
+    assert np.linalg.norm(got - x) / np.linalg.norm(x) < 1e-9
+
+
+def test_mixed_guess_and_history():
+    n = 128
+    fv = np.random.default_rng(24).standard_normal((n, n))
+    plan = mixed_plan(n, "DDDD")
+    d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
+    r1 = cc.ccmg_solve(plan, d_f, d_phi)
+    assert r1.history[0] == 1.0 and all(np.diff(np.log(r1.history)) < 0)
+    r2 = cc.ccmg_solve(plan, d_f, d_phi, use_guess=True)
+    assert r2.cycles == 0 and r2.rel_resid0 <= 1e-10
+    plan1 = mixed_plan(n, "DDDD", max_cycles=2)
+    r3 = cc.ccmg_solve(plan1, d_f, dev_field(oracle.field_zeros(n)))
+    assert r3.status == cc.NOT_CONVERGED and r3.cycles == 2
