@@ -84,6 +84,57 @@ def measure(cc, torch, n, bc, fv, steps, warmup):
     return out
 
 
+def time_form(cc, torch, prob, fv, steps, warmup):
+    """Time-to-tolerance of one problem: autotune, warm up, then `steps` solves."""
+    plan = cc.Plan(prob)
+    f = upload(cc, torch, fv)
+    phi = cc.field(prob.n)
+    cc.ccmg_plan_autotune(plan, f, phi)
+    for _ in range(warmup):
+        r = cc.ccmg_solve(plan, f, phi)
+        assert r.status == cc.OK, r
+    dt, res, _ = run_solves(cc, torch, plan, f, phi, steps)
+    assert all(r.status == cc.OK and r.rel_resid <= prob.rtol for r in res)
+    _, _, stats = run_solves(cc, torch, plan, f, phi, max(2, steps // 2), profile=True)
+    out = dict(ms=1e3 * dt / steps, cycles=res[-1].cycles, rel_resid=res[-1].rel_resid,
+               kernels=[dict(name=k["name"], avg_ms=round(k["ms"] / k["launches"], 5),
+                             gbs=round(k["bytes"] / k["launches"] / (k["ms"] / k["launches"] * 1e-3) / 1e9, 1))
+                        for k in stats if k["launches"] > 0])
+    del plan, f, phi
+    torch.cuda.empty_cache()
+    return out
+
+
+def mixed_vs_plain(cc, torch, W, steps):
+    """Mixed precision against the plain FP64 form on the same problems: the
+    Crank-Nicolson Helmholtz solves (1 - (k dt/2) Lap) phi = g on 8192^2
+    (k dt / h^2 = 0.1, 1, 10; g a Gaussian random field of correlation length
+    0.05, periodic) and the headline 4096^2 Poisson problem."""
+    out = {}
+    n = 8192
+    g = W.gaussian_random_field(n, seed=0)
+    for c in (0.1, 1.0, 10.0):
+        beta = c / (2.0 * n * n)
+        row = {}
+        for name, prec in (("plain_fp64", cc.FP64), ("mixed", cc.MIXED)):
+            prob = cc.Problem(n=n, bc="P", alpha=1.0, beta=beta, rtol=1e-10, prec=prec)
+            row[name] = time_form(cc, torch, prob, g, steps, 1)
+        row["speedup"] = round(row["plain_fp64"]["ms"] / row["mixed"]["ms"], 3)
+        out[f"helmholtz_8192_c{c}"] = row
+        log(f"helmholtz 8192^2 c={c}: plain {row['plain_fp64']['ms']:.3f} ms ({row['plain_fp64']['cycles']} cyc), "
+            f"mixed {row['mixed']['ms']:.3f} ms ({row['mixed']['cycles']} steps), x{row['speedup']}")
+    del g
+    n = 4096
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    row = {}
+    for name, prec in (("plain_fp64", cc.FP64), ("mixed", cc.MIXED)):
+        row[name] = time_form(cc, torch, cc.Problem(n=n, bc="P", rtol=1e-10, prec=prec), fv, steps, 2)
+    row["speedup"] = round(row["plain_fp64"]["ms"] / row["mixed"]["ms"], 3)
+    out["poisson_4096_periodic"] = row
+    log(f"poisson 4096^2: plain {row['plain_fp64']['ms']:.3f} ms, mixed {row['mixed']['ms']:.3f} ms, x{row['speedup']}")
+    return out
+
+
 def roofline_of(meas):
     ks = [k for k in meas["kernels"] if k["launches"] > 0]
     dom = max(ks, key=lambda k: k["ms"])
@@ -127,7 +178,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run")
+    ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run and the other forms")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -175,6 +226,7 @@ def main():
         log(f"8192^2: {m8['ms_per_solve']:.3f} ms/solve, {m8['pts_cycles_per_s'] / 1e9:.2f} G; "
             f"{rl8['kernel']} {rl8['achieved']} GB/s")
         del f8
+        also["mixed_precision"] = mixed_vs_plain(cc, torch, W, max(args.steps // 4, 3))
 
     cpu = None
     if not args.no_cpu:

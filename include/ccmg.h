@@ -142,6 +142,42 @@ int ccmg_restrict_residual(ccmg_plan *plan, int level, const double *d_f, const 
 int ccmg_prolong_add(ccmg_plan *plan, int level, const double *d_ec, ptrdiff_t pitch_c,
                      const double *d_phi_in, double *d_phi_out, ptrdiff_t pitch);
 
+/* ---- batched solves.
+ * m independent problems of any sizes and side types advanced together (the
+ * same refinement as CCMG_MIXED: FP32 V(2,2) cycles for the correction, FP64
+ * update and FP64 stop test, whatever each problem's `prec` says).  Each batch
+ * step is one fixed sequence of launches (per level size class, one
+ * persistent launch over the tiles of every problem that has a level of that
+ * size; one launch for all problems' levels of <= 32 cells; one launch for
+ * all problems' stop tests) captured in a hipGraph and replayed; converged
+ * problems are skipped.  Every problem needs nu1 == nu2 == 2.
+ * Pointer arrays (d_f, d_phi, pitch) are host arrays of m entries; f[i] and
+ * phi[i] are device arrays of problem i as for ccmg_solve.  The batch works
+ * on an internal stream ordered after, and before, the caller's `stream`. */
+typedef struct ccmg_batch ccmg_batch;
+typedef struct {
+    int steps;             /* batch steps replayed                              */
+    int converged;         /* problems that reached their rtol                  */
+    float ms;              /* device time of the solve (HIP events)             */
+} ccmg_batch_info;
+
+size_t ccmg_batch_workspace_bytes(int m, const ccmg_problem *probs);
+int ccmg_batch_create(int m, const ccmg_problem *probs, void *d_ws, size_t ws_bytes, void *stream,
+                      ccmg_batch **out);
+int ccmg_batch_destroy(ccmg_batch *batch);
+/* Solve all problems; out (m entries, may be NULL) receives each problem's
+ * result, info (may be NULL) the batch summary.  Returns CCMG_OK if every
+ * problem converged, else the first error status, else CCMG_NOT_CONVERGED. */
+int ccmg_batch_solve(ccmg_batch *batch, const double *const *d_f, double *const *d_phi, const ptrdiff_t *pitch,
+                     int use_guess, ccmg_result *out, ccmg_batch_info *info);
+/* Time the candidate rows-per-band of each level size class and the number of
+ * persistent wavefronts over whole batch steps on the given arrays and keep the
+ * fastest.  d_phi is used as scratch (overwritten). */
+int ccmg_batch_autotune(ccmg_batch *batch, const double *const *d_f, double *const *d_phi,
+                        const ptrdiff_t *pitch);
+/* Level size classes (descending), their rows per band, and the wavefront count. */
+int ccmg_batch_shapes(ccmg_batch *batch, int *sizes, int *ty, int max, int *count, int *waves);
+
 /* ---- launch-shape autotuning.
  * Times every candidate tile shape (rows per wavefront band x wavefronts per
  * workgroup) of the two row-march launches of each level on the given data and

@@ -51,6 +51,10 @@ class ccmg_result(ctypes.Structure):
                 ("inner_cycles", ctypes.c_int)]
 
 
+class ccmg_batch_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("ms", ctypes.c_float)]
+
+
 class ccmg_kernel_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -84,6 +88,16 @@ def lib():
         L.ccmg_restrict_residual.argtypes = [vp, i, dp, dp, pd, dp, pd]
         L.ccmg_prolong_add.argtypes = [vp, i, dp, pd, dp, dp, pd]
         L.ccmg_plan_profile.argtypes = [vp, i]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.ccmg_batch_workspace_bytes.restype = sz
+        L.ccmg_batch_workspace_bytes.argtypes = [i, P]
+        L.ccmg_batch_create.argtypes = [i, P, vp, sz, vp, ctypes.POINTER(vp)]
+        L.ccmg_batch_destroy.argtypes = [vp]
+        L.ccmg_batch_solve.argtypes = [vp, PP, PP, ctypes.POINTER(pd), i, ctypes.POINTER(ccmg_result),
+                                       ctypes.POINTER(ccmg_batch_info)]
+        L.ccmg_batch_autotune.argtypes = [vp, PP, PP, ctypes.POINTER(pd)]
+        L.ccmg_batch_shapes.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), i, ctypes.POINTER(i),
+                                        ctypes.POINTER(i)]
         L.ccmg_plan_autotune.argtypes = [vp, dp, dp, pd]
         ip = ctypes.POINTER(ctypes.c_int)
         L.ccmg_plan_shapes.argtypes = [vp, ip, ip, ip, ip, i]
@@ -307,6 +321,77 @@ def ccmg_plan_kernel_stats(plan: Plan) -> list:
     _check(lib().ccmg_plan_kernel_stats(plan.handle, arr, 8, ctypes.byref(cnt)), "ccmg_plan_kernel_stats")
     return [dict(name=arr[k].name.decode(), launches=arr[k].launches, ms=arr[k].ms, bytes=arr[k].bytes)
             for k in range(min(cnt.value, 8))]
+
+
+class Batch:
+    """A ccmg batch of independent problems with its own workspace tensor."""
+
+    def __init__(self, probs, device=None, stream=None):
+        self.probs = list(probs)
+        self.m = len(self.probs)
+        arr = (ccmg_problem * self.m)(*[p.to_c() for p in self.probs])
+        self._c = arr
+        nbytes = lib().ccmg_batch_workspace_bytes(self.m, arr)
+        if nbytes == 0:
+            raise CcmgError(EINVAL, "batch problems (each needs a valid problem with nu1 = nu2 = 2)")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        _check(lib().ccmg_batch_create(self.m, arr, ctypes.c_void_p(aligned), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "batch_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ccmg_batch_destroy(h)
+            self.handle = None
+
+
+def _batch_arrays(batch: Batch, fs, phis):
+    if len(fs) != batch.m or len(phis) != batch.m:
+        raise ValueError("one f and one phi per problem")
+    fp = (ctypes.c_void_p * batch.m)()
+    pp = (ctypes.c_void_p * batch.m)()
+    pit = (ctypes.c_ssize_t * batch.m)()
+    for i, (f, phi, pr) in enumerate(zip(fs, phis, batch.probs)):
+        a, p1 = _field_args(f, pr.n)
+        b, p2 = _field_args(phi, pr.n)
+        if p1 != p2:
+            raise ValueError("f and phi of one problem must share a pitch")
+        fp[i], pp[i], pit[i] = a, b, p1
+    return fp, pp, pit
+
+
+def ccmg_batch_solve(batch: Batch, fs, phis, use_guess: bool = False):
+    """Returns (list of Result, {steps, converged, ms})."""
+    fp, pp, pit = _batch_arrays(batch, fs, phis)
+    res = (ccmg_result * batch.m)()
+    info = ccmg_batch_info()
+    st = lib().ccmg_batch_solve(batch.handle, fp, pp, pit, int(use_guess), res, ctypes.byref(info))
+    if st in (EINVAL, EHIP, EWORKSPACE):
+        raise CcmgError(st, "ccmg_batch_solve")
+    out = []
+    for r in res:
+        hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+        out.append(Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles))
+    return out, dict(status=st, steps=info.steps, converged=info.converged, ms=info.ms)
+
+
+def ccmg_batch_autotune(batch: Batch, fs, phis) -> None:
+    fp, pp, pit = _batch_arrays(batch, fs, phis)
+    _check(lib().ccmg_batch_autotune(batch.handle, fp, pp, pit), "ccmg_batch_autotune")
+
+
+def ccmg_batch_shapes(batch: Batch) -> dict:
+    sizes, ty = (ctypes.c_int * 16)(), (ctypes.c_int * 16)()
+    cnt, waves = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ccmg_batch_shapes(batch.handle, sizes, ty, 16, ctypes.byref(cnt), ctypes.byref(waves)),
+           "ccmg_batch_shapes")
+    return dict(sizes=[sizes[k] for k in range(cnt.value)], ty=[ty[k] for k in range(cnt.value)],
+                waves=waves.value)
 
 
 def field(n: int, dtype=torch.float64, device="cuda", pitch: int | None = None) -> torch.Tensor:

@@ -132,7 +132,7 @@ __device__ void prolong_add(const T *E, T *P, int lg, const Sides &sd) {
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse(const CoarseArgs<T> a) {
+__device__ void coarse_body(const CoarseArgs<T> &a) {
     __shared__ T sP[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ T sF[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ double red[kThreads / 64];
@@ -218,9 +218,18 @@ __global__ __launch_bounds__(kThreads) void k_coarse(const CoarseArgs<T> a) {
 }
 
 template <typename T>
-hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
-    if (a0.n_top < 2 || a0.n_top > kCoarseMax || (a0.n_top & (a0.n_top - 1))) return hipErrorInvalidValue;
-    CoarseArgs<T> a = a0;
+__global__ __launch_bounds__(kThreads) void k_coarse(const CoarseArgs<T> a) {
+    coarse_body(a);
+}
+
+// Batches: one workgroup per problem.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse_list(const CoarseArgs<T> *__restrict__ list) {
+    coarse_body(list[blockIdx.x]);
+}
+
+template <typename T>
+void coarse_fill_consts(CoarseArgs<T> &a) {
     for (int l = 0; (a.n_top >> l) >= 2 && l < 8; ++l) {
         const double h = a.h_top * (double)(1 << l);
         const double c = a.beta / (h * h);
@@ -228,11 +237,29 @@ hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
         a.invd[l] = 1.0 / (a.alpha + 4.0 * c);
         a.ih2[l] = 1.0 / (h * h);
     }
+}
+
+template <typename T>
+hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
+    if (a0.n_top < 2 || a0.n_top > kCoarseMax || (a0.n_top & (a0.n_top - 1))) return hipErrorInvalidValue;
+    CoarseArgs<T> a = a0;
+    coarse_fill_consts(a);
     hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_list(const CoarseArgs<T> *list, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_list<T>, dim3(count), dim3(kThreads), 0, s, list);
     return hipGetLastError();
 }
 
 template hipError_t launch_coarse<double>(const CoarseArgs<double> &, hipStream_t);
 template hipError_t launch_coarse<float>(const CoarseArgs<float> &, hipStream_t);
+template hipError_t launch_coarse_list<float>(const CoarseArgs<float> *, int, hipStream_t);
+template hipError_t launch_coarse_list<double>(const CoarseArgs<double> *, int, hipStream_t);
+template void coarse_fill_consts<float>(CoarseArgs<float> &);
+template void coarse_fill_consts<double>(CoarseArgs<double> &);
 
 }  // namespace ccmg

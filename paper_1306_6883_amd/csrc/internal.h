@@ -8,6 +8,9 @@
 
 namespace ccmg {
 
+// Device scalars of a solve (workspace): statistics of f, mean of phi.
+enum { S_FSUM = 0, S_FABS = 1, S_F2 = 2, S_FBAD = 3, S_PHIMEAN = 4, S_RHO0 = 5, kScal = 16 };
+
 enum Post {
     POST_NONE = 0,
     POST_RESTRICT = 1,  // residual -> four-cell restriction into aux (+ partial sums)
@@ -34,6 +37,7 @@ struct MarchArgs {
     double *partial;     // per-tile sums: RESTRICT -> sum of coarse rhs; NORM -> sum r^2, sum phi
     const double *fmean_part;  // partial sums whose total / (n*n) is subtracted from f (or null)
     int fmean_count;
+    const int *fmean_count_ptr;  // if set, the number of partial sums is read from here
     const double *phi_shift;   // device scalar subtracted from loaded phi (or null)
     const int *skip;     // device flag: when set (solve converged) the launch does nothing
     int n;               // cells per side of this level
@@ -53,6 +57,13 @@ struct MarchArgs {
     double *partial3;    // per tile: sum of the FP32 residual (mean removal of singular problems)
     double alpha64, beta64, ih2_64;
     int q_zero;          // POST_IR: the FP64 iterate is zero (q_in is not used)
+    int *count_out;      // if set, receives ntiles (producers of per-tile sums)
+};
+
+// One unit of work of a batched launch: tile `tile` of level descriptor `desc`.
+struct WorkItem {
+    int desc;
+    int tile;
 };
 
 // Launch description chosen by the host for one level.
@@ -98,6 +109,12 @@ struct CoarseArgs {
 };
 template <typename T>
 hipError_t launch_coarse(const CoarseArgs<T> &a, hipStream_t s);
+// One workgroup per entry of a device array of tail descriptors (batches).
+// The descriptors must hold the per-level constants (see coarse_fill_consts).
+template <typename T>
+hipError_t launch_coarse_list(const CoarseArgs<T> *list, int count, hipStream_t s);
+template <typename T>
+void coarse_fill_consts(CoarseArgs<T> &a);
 
 // util.hip
 hipError_t launch_fill_ghosts_f64(double *a, long pitch, int n, const int bc[4], const double *shift,

@@ -128,7 +128,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     const bool subp = LOADPHI && a.phi_shift != nullptr;
     T fsub = T(0), psub = T(0);
     double psub64 = 0.0;  // POST_IR: the shift applies to the FP64 iterate, in FP64
-    if (subf) fsub = T(sum_partials(a.fmean_part, a.fmean_count) / ((double)tl.n * (double)tl.n));
+    if (subf) {
+        const int cnt = a.fmean_count_ptr ? *a.fmean_count_ptr : a.fmean_count;
+        fsub = T(sum_partials(a.fmean_part, cnt) / ((double)tl.n * (double)tl.n));
+    }
     if (subp) {
         psub64 = *a.phi_shift;
         psub = T(psub64);
@@ -433,19 +436,13 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     }
 }
 
+// One tile of one level: derive the tile geometry from the launch arguments and
+// run the row march, specialised on whether the tile meets a Dirichlet /
+// Neumann side.  `a` may live in the kernel arguments or in global memory.
 template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
-__global__ __launch_bounds__(256) void k_march(const MarchArgs<T> a) {
+__device__ __forceinline__ void march_one(const MarchArgs<T> &a, const int tile) {
     using C = Cfg<NU, PROLONG, POST>;
     const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    // The wave index is uniform across the wavefront; saying so keeps every row
-    // decision in scalar registers and scalar branches.
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // XCD-aware order: consecutive workgroup ids go to different XCDs, so give
-    // each XCD a contiguous run of tiles (neighbouring tiles share halo rows in L2).
-    const int lb = (blockIdx.x & 7) * a.groups_per_xcd + (blockIdx.x >> 3);
-    const int tile = lb * wpb + wib;
-    if (tile >= a.ntiles) return;  // whole wavefront leaves; no barriers anywhere
     if (a.skip && *a.skip) return;
     const int strip = tile % a.strips, chunk = tile / a.strips;
 
@@ -474,6 +471,9 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<T> a) {
     tl.ys = tl.py ? tl.y0 - C::HY : max(tl.y0 - C::HY, 0);
     tl.ye = tl.py ? tl.y1 + C::HY : min(tl.y1 + C::HY, tl.n);
 
+    // the producer of per-tile partial sums publishes how many tiles it has
+    if (a.count_out && tile == 0 && lane == 0) *a.count_out = a.ntiles;
+
     // does any lane / row of the tile meet a Dirichlet or Neumann side?
     const bool xb = !tl.px && (X0 <= 0 || X0 + 128 >= tl.n - 1);
     const bool yb = !tl.py && (tl.ys == 0 || tl.ye == tl.n);
@@ -483,6 +483,33 @@ __global__ __launch_bounds__(256) void k_march(const MarchArgs<T> a) {
     } else {
         if (yb) march_tile<T, NU, LOADPHI, PROLONG, POST, false, true>(a, tl, tile);
         else march_tile<T, NU, LOADPHI, PROLONG, POST, false, false>(a, tl, tile);
+    }
+}
+
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
+__global__ __launch_bounds__(256) void k_march(const MarchArgs<T> a) {
+    const int wpb = blockDim.x >> 6;
+    // The wave index is uniform across the wavefront; saying so keeps every row
+    // decision in scalar registers and scalar branches.
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware order: consecutive workgroup ids go to different XCDs, so give
+    // each XCD a contiguous run of tiles (neighbouring tiles share halo rows in L2).
+    const int lb = (blockIdx.x & 7) * a.groups_per_xcd + (blockIdx.x >> 3);
+    const int tile = lb * wpb + wib;
+    if (tile >= a.ntiles) return;  // whole wavefront leaves; no barriers anywhere
+    march_one<T, NU, LOADPHI, PROLONG, POST>(a, tile);
+}
+
+// Persistent form for batches: the waves walk a list of (level descriptor,
+// tile) items that spans many independent problems.
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
+__global__ __launch_bounds__(256) void k_march_list(const MarchArgs<T> *__restrict__ descs,
+                                                     const WorkItem *__restrict__ items, int nitems) {
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = gridDim.x * (blockDim.x >> 6);
+    for (int it = blockIdx.x * (blockDim.x >> 6) + wib; it < nitems; it += nw) {
+        const WorkItem wi = items[it];
+        march_one<T, NU, LOADPHI, PROLONG, POST>(descs[wi.desc], wi.tile);
     }
 }
 
@@ -544,6 +571,18 @@ hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int p
         }
     }
     return hipErrorInvalidValue;
+}
+
+// Work-list launch of one variant (see k_march_list); `waves` wavefronts in
+// workgroups of four.
+template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST>
+hipError_t launch_list_variant(const MarchArgs<T> *descs, const WorkItem *items, int nitems, int waves,
+                               hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL((k_march_list<T, NU, LOADPHI, PROLONG, POST>), dim3(blocks), dim3(256), 0, s, descs, items,
+                       nitems);
+    return hipGetLastError();
 }
 
 }  // namespace ccmg

@@ -35,7 +35,6 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 long pitch_for(int n) { return (long)((n + 2 + 31) & ~31); }
 bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 
-enum { S_FSUM = 0, S_FABS = 1, S_F2 = 2, S_FBAD = 3, S_PHIMEAN = 4, S_RHO0 = 5, kScal = 16 };
 
 int max_tiles(int n) {
     const int strips = (n + kMinOutw - 1) / kMinOutw;
@@ -61,7 +60,8 @@ struct Layout {
     size_t qb = 0;         // MIXED: second FP64 iterate buffer (finest level)
     size_t normpart = 0;
     int normpart_cap = 0;
-    size_t part3 = 0;      // MIXED: per-tile sums of the FP32 residual
+    size_t part3 = 0;      // MIXED: per-tile sums of the FP32 residual (two buffers: one read,
+    size_t part3b = 0;     // one written by the same launch)
     size_t fstats = 0;
     size_t scal = 0, hist = 0, flags = 0;
     size_t total = 0;
@@ -113,6 +113,7 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     lay.normpart_cap = max_tiles(n);
     lay.normpart = take(sizeof(double) * 2 * lay.normpart_cap);
     lay.part3 = take(sizeof(double) * lay.normpart_cap);
+    lay.part3b = take(sizeof(double) * lay.normpart_cap);
     lay.fstats = take(sizeof(double) * 4 * kStatBlocks);
     lay.scal = take(sizeof(double) * kScal);
     lay.hist = take(sizeof(double) * CCMG_HISTORY);
@@ -271,6 +272,7 @@ struct CycleIO {
     long pr = 0;
     bool q_zero = false;           // the FP64 iterate is zero (first step without a guess)
     const double *q_shift = nullptr;  // subtracted from the FP64 iterate as it is read
+    double *partial3_out = nullptr;   // per-tile sums of the new FP32 residual
 };
 
 template <typename T>
@@ -334,7 +336,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         a.q_zero = io.q_zero ? 1 : 0;
         a.phi_shift = io.q_shift;
         a.partial = P->at<double>(lay.normpart);
-        a.partial3 = P->at<double>(lay.part3);
+        a.partial3 = io.partial3_out;
         const double h = lay.lev[0].h;
         a.alpha64 = P->p.alpha;
         a.beta64 = P->p.beta;
@@ -501,6 +503,8 @@ struct MixedState {
     float *r;      // current FP32 residual (rhs of the next correction)
     float *ro;
     long pr;
+    double *s3;    // per-tile sums of the current FP32 residual
+    double *s3o;
     int r_tiles;   // tiles of the launch that wrote the current residual's partial sums
     bool q_zero;   // the FP64 iterate is still zero
 };
@@ -516,7 +520,7 @@ hipError_t enqueue_mixed_start(ccmg_plan *P, const double *d_f, long pf, MixedSt
     a.r_out = st.r;
     a.pr = st.pr;
     a.partial = P->at<double>(P->lay.normpart);
-    a.partial3 = P->at<double>(P->lay.part3);
+    a.partial3 = st.s3;
     int nt = 0;
     hipError_t e = launch_march<double>(a, 0, use_guess, false, POST_R32, P->shp_pre[0], P->stream, &nt);
     st.r_tiles = nt;
@@ -540,8 +544,9 @@ hipError_t enqueue_mixed_step(ccmg_plan *P, const double *d_f, long pf, MixedSta
     io.phi0b = P->at<float>(lay.lev[0].b);
     io.pp0b = lay.lev[0].pitch;
     io.zero = true;
-    io.f0mean_part = P->at<double>(lay.part3);
+    io.f0mean_part = st.s3;
     io.f0mean_count = st.r_tiles;
+    io.partial3_out = st.s3o;
     io.post0 = POST_IR;
     io.skip = skip;
     io.q_in = st.q;
@@ -561,6 +566,7 @@ hipError_t enqueue_mixed_step(ccmg_plan *P, const double *d_f, long pf, MixedSta
     std::swap(st.q, st.qo);
     std::swap(st.pq, st.pqo);
     std::swap(st.r, st.ro);
+    std::swap(st.s3, st.s3o);
     st.r_tiles = nt;
     st.q_zero = false;
     return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0, P->scal() + S_F2,
@@ -890,6 +896,8 @@ MixedState mixed_state(ccmg_plan *P, double *d_phi, ptrdiff_t pitch, bool q_zero
     st.r = P->at<float>(lay.lev[0].f);
     st.ro = P->at<float>(lay.lev[0].f2);
     st.pr = lay.lev[0].pitch;
+    st.s3 = P->at<double>(lay.part3);
+    st.s3o = P->at<double>(lay.part3b);
     st.r_tiles = 0;
     st.q_zero = q_zero;
     return st;
