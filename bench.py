@@ -135,6 +135,64 @@ def mixed_vs_plain(cc, torch, W, steps):
     return out
 
 
+def batched_vs_sequential(cc, torch, W, reps):
+    """The batched workload: 512 independent Poisson problems, sizes uniform in
+    {32, ..., 1024}^2, per-axis periodic / Dirichlet sides, 16 seeded Fourier
+    modes |k| <= 8 (zero mean), to 1e-10 -- one batched solve (graph-replayed
+    steps, FP32 cycles + FP64 refinement) against the same 512 problems solved
+    one after another with plain FP64 plans."""
+    items = W.batch(seed=0)
+    cells = sum(it.n * it.n for it in items)
+    fs, phis = [], []
+    for it in items:
+        fs.append(upload(cc, torch, it.f))
+        phis.append(cc.field(it.n))
+    probs = [cc.Problem(n=it.n, bc=it.bc, rtol=1e-10, prec=cc.MIXED) for it in items]
+    batch = cc.Batch(probs)
+    cc.ccmg_batch_autotune(batch, fs, phis)
+    shapes = cc.ccmg_batch_shapes(batch)
+    res, info = cc.ccmg_batch_solve(batch, fs, phis)  # warm-up
+    assert info["converged"] == len(items), info
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    for _ in range(reps):
+        res, info = cc.ccmg_batch_solve(batch, fs, phis)
+        steps += info["steps"]
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    assert info["converged"] == len(items) and all(r.rel_resid <= 1e-10 for r in res)
+    del batch
+    torch.cuda.empty_cache()
+    # sequential plain FP64 solves (one plan per size and side pairing)
+    plans = {}
+    for it, f in zip(items, fs):
+        key = (it.n, it.bc)
+        if key not in plans:
+            plans[key] = cc.Plan(cc.Problem(n=it.n, bc=it.bc, rtol=1e-10))
+            cc.ccmg_plan_autotune(plans[key], f, cc.field(it.n))
+    for it, f, phi in zip(items, fs, phis):  # warm-up
+        cc.ccmg_solve(plans[(it.n, it.bc)], f, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_cycles = 0
+    for it, f, phi in zip(items, fs, phis):
+        r = cc.ccmg_solve(plans[(it.n, it.bc)], f, phi)
+        assert r.status == cc.OK
+        seq_cycles += r.cycles
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out = dict(problems=len(items), cells=cells, batched_ms=round(1e3 * tb, 3), batched_steps=steps // reps,
+               sequential_plain_fp64_ms=round(1e3 * ts, 3), sequential_cycles=seq_cycles,
+               speedup=round(ts / tb, 3), batched_cells_steps_per_s=cells * (steps / reps) / tb,
+               shapes=shapes)
+    log(f"batched 512: {1e3 * tb:.2f} ms ({steps // reps} steps) vs sequential plain {1e3 * ts:.2f} ms, "
+        f"x{ts / tb:.2f}")
+    del plans, fs, phis
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(meas):
     ks = [k for k in meas["kernels"] if k["launches"] > 0]
     dom = max(ks, key=lambda k: k["ms"])
@@ -227,6 +285,7 @@ def main():
             f"{rl8['kernel']} {rl8['achieved']} GB/s")
         del f8
         also["mixed_precision"] = mixed_vs_plain(cc, torch, W, max(args.steps // 4, 3))
+        also["batched"] = batched_vs_sequential(cc, torch, W, 3)
 
     cpu = None
     if not args.no_cpu:

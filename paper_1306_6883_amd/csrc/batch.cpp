@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -683,13 +684,20 @@ int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_p
         return true;
     };
     int steps = 0;
+    // CCMG_BATCH_EAGER=1 issues each step's launches directly instead of
+    // replaying the captured graphs (same launches; used to check the replays)
+    const char *eg = getenv("CCMG_BATCH_EAGER");
+    const bool eager = eg && eg[0] == '1';
+    auto run_step = [&](int k) -> hipError_t {
+        return eager ? record_step(B, k & 1) : hipGraphLaunch(B->graph[k & 1], B->stream);
+    };
     if (!all_done() && max_steps > 0) {
         // step k replays graph (k & 1); step k+1 is queued before step k is checked
-        e = hipGraphLaunch(B->graph[1], B->stream);
+        e = run_step(1);
         if (e == hipSuccess) e = hipEventRecord(B->ev_sync[1], B->stream);
         for (int k = 1; e == hipSuccess; ++k) {
             if (k < max_steps) {
-                e = hipGraphLaunch(B->graph[(k + 1) & 1], B->stream);
+                e = run_step(k + 1);
                 if (e == hipSuccess) e = hipEventRecord(B->ev_sync[(k + 1) & 1], B->stream);
                 if (e != hipSuccess) break;
             }
