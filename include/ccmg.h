@@ -178,6 +178,58 @@ int ccmg_batch_autotune(ccmg_batch *batch, const double *const *d_f, double *con
 /* Level size classes (descending), their rows per band, and the wavefront count. */
 int ccmg_batch_shapes(ccmg_batch *batch, int *sizes, int *ty, int max, int *count, int *waves);
 
+/* ---- learned initial guess.
+ * A linear network of six 3x3 convolutions with circular padding and
+ * dilations 1, 2, 4, 8, 16, 32 on a 128 x 128 grid (channels 1 -> 32 -> ... ->
+ * 32 -> 1, no biases; BF16 operands, FP32 accumulation on the matrix cores)
+ * maps a right-hand side, averaged onto that grid and divided by its RMS, to
+ * the solution averaged the same way.  The guess for an n x n problem
+ * (n >= 256, power of two) is that output times the RMS, prolonged back to
+ * n x n by multigrid prolongations; the solver then continues from it
+ * (ccmg_solve with use_guess = 1) to the same tolerance.  Parameters: FP32,
+ * ccmg_net_param_count() of them, in layer order ([32][9], four x
+ * [32][9][32] (out, tap, in), [9][32]); tap = 3 (dy + 1) + (dx + 1) reads the
+ * input at (y + dy d, x + dx d).  Network inputs / targets: nb x 128 x 128
+ * FP32 device arrays.  All work on the net's stream. */
+typedef struct ccmg_net ccmg_net;
+int ccmg_net_param_count(void);
+/* Workspace for training batches of up to `batch` samples and guesses for
+ * problems of up to n_max cells per side (0 if invalid). */
+size_t ccmg_net_workspace_bytes(int batch, int n_max);
+int ccmg_net_create(int batch, int n_max, void *d_ws, size_t ws_bytes, void *stream, ccmg_net **out);
+int ccmg_net_destroy(ccmg_net *net);
+/* Load parameters (device FP32); resets the optimiser state. */
+int ccmg_net_set_params(ccmg_net *net, const float *d_params);
+int ccmg_net_get_params(ccmg_net *net, float *d_params);
+/* y = net(x) for nb samples. */
+int ccmg_net_forward(ccmg_net *net, const float *d_x, float *d_y, int nb);
+/* Mean squared error of net(x) against t and its gradient with respect to
+ * every parameter (device FP32, may be NULL); *loss (host, may be NULL). */
+int ccmg_net_loss_grad(ccmg_net *net, const float *d_x, const float *d_t, int nb, float *d_grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss with rate lr. */
+int ccmg_net_train_step(ccmg_net *net, const float *d_x, const float *d_t, int nb, float lr, float *loss);
+/* Encoder: block means of `a` (n x n, ghosted FP64) on the 128 x 128 grid
+ * divided by the RMS of `scale_src` (the sample's right-hand side). */
+int ccmg_net_encode(ccmg_net *net, const double *d_a, ptrdiff_t pitch, int n, const double *d_scale_src,
+                    ptrdiff_t scale_pitch, float *d_x);
+/* The guess for f (n x n, ghosted FP64, 256 <= n <= n_max) on a square of
+ * side `length`: encode, network, `coarse_iters` (0..64) red-black
+ * Gauss-Seidel iterations of the periodic Poisson problem on the network's
+ * grid (they remove the grid-scale noise of the network output), then
+ * multigrid prolongations to n x n.  Writes the valid cells of d_phi. */
+int ccmg_net_guess(ccmg_net *net, const double *d_f, ptrdiff_t pitch, int n, double length, int coarse_iters,
+                   double *d_phi, ptrdiff_t phi_pitch);
+/* Learned solve for the problem the network is trained on (alpha = 0,
+ * beta = -1, square domain; any sides): ccmg_net_guess, then ccmg_solve from
+ * that guess to the plan's tolerance.  A guess whose relative residual is not
+ * finite or above 1e6 is discarded and the solve starts from zero instead
+ * (*guess_used = 0, may be NULL).  out->ms covers guess and solve,
+ * out->rel_resid0 is the guess's relative residual.  The plan and the net
+ * must share one stream; the plan's n must lie in [256, n_max].  Returns
+ * ccmg_solve's status (CCMG_EINVAL for a problem the network does not fit). */
+int ccmg_solve_learned(ccmg_plan *plan, ccmg_net *net, const double *d_f, double *d_phi, ptrdiff_t pitch,
+                       int coarse_iters, ccmg_result *out, int *guess_used);
+
 /* ---- launch-shape autotuning.
  * Times every candidate tile shape (rows per wavefront band x wavefronts per
  * workgroup) of the two row-march launches of each level on the given data and

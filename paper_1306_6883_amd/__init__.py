@@ -103,6 +103,20 @@ def lib():
         L.ccmg_plan_shapes.argtypes = [vp, ip, ip, ip, ip, i]
         L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
         L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.ccmg_net_param_count.argtypes = []
+        L.ccmg_net_workspace_bytes.restype = sz
+        L.ccmg_net_workspace_bytes.argtypes = [i, i]
+        L.ccmg_net_create.argtypes = [i, i, vp, sz, vp, ctypes.POINTER(vp)]
+        L.ccmg_net_destroy.argtypes = [vp]
+        L.ccmg_net_set_params.argtypes = [vp, vp]
+        L.ccmg_net_get_params.argtypes = [vp, vp]
+        L.ccmg_net_forward.argtypes = [vp, vp, vp, i]
+        L.ccmg_net_loss_grad.argtypes = [vp, vp, vp, i, vp, fp]
+        L.ccmg_net_train_step.argtypes = [vp, vp, vp, i, ctypes.c_float, fp]
+        L.ccmg_net_encode.argtypes = [vp, dp, pd, i, dp, pd, vp]
+        L.ccmg_net_guess.argtypes = [vp, dp, pd, i, ctypes.c_double, i, dp, pd]
+        L.ccmg_solve_learned.argtypes = [vp, vp, dp, dp, pd, i, ctypes.POINTER(ccmg_result), ip]
         _lib = L
     return _lib
 
@@ -392,6 +406,142 @@ def ccmg_batch_shapes(batch: Batch) -> dict:
            "ccmg_batch_shapes")
     return dict(sizes=[sizes[k] for k in range(cnt.value)], ty=[ty[k] for k in range(cnt.value)],
                 waves=waves.value)
+
+
+NET_G = 128  # side of the network's grid
+
+
+def ccmg_net_param_count() -> int:
+    return lib().ccmg_net_param_count()
+
+
+def ccmg_net_workspace_bytes(batch: int, n_max: int) -> int:
+    return lib().ccmg_net_workspace_bytes(batch, n_max)
+
+
+class Net:
+    """A ccmg net (learned initial guess) with its own workspace tensor.
+    `batch`: largest training batch; `n_max`: largest problem side it guesses for."""
+
+    def __init__(self, batch: int = 32, n_max: int = 1024, device=None, stream=None):
+        nbytes = lib().ccmg_net_workspace_bytes(batch, n_max)
+        if nbytes == 0:
+            raise CcmgError(EINVAL, "net sizes (batch 1..1024, n_max a power of two in 128..16384)")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.batch, self.n_max, self.device = batch, n_max, dev
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        _check(lib().ccmg_net_create(batch, n_max, ctypes.c_void_p(aligned), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "net_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.ccmg_net_destroy(h)
+            self.handle = None
+
+
+def _net_images(net: Net, t: torch.Tensor, what: str) -> int:
+    if (not t.is_cuda or t.dtype != torch.float32 or t.dim() != 3 or tuple(t.shape[1:]) != (NET_G, NET_G)
+            or not t.is_contiguous()):
+        raise ValueError(f"{what}: expected a contiguous float32 device tensor of shape (nb, {NET_G}, {NET_G})")
+    if not 1 <= t.shape[0] <= net.batch:
+        raise ValueError(f"{what}: batch of {t.shape[0]} outside 1..{net.batch}")
+    return t.shape[0]
+
+
+def _param_vec(t: torch.Tensor) -> None:
+    if (not t.is_cuda or t.dtype != torch.float32 or t.numel() != ccmg_net_param_count()
+            or not t.is_contiguous()):
+        raise ValueError("parameters: expected a contiguous float32 device vector of ccmg_net_param_count()")
+
+
+def ccmg_net_set_params(net: Net, params: torch.Tensor) -> None:
+    _param_vec(params)
+    _check(lib().ccmg_net_set_params(net.handle, params.data_ptr()), "ccmg_net_set_params")
+
+
+def ccmg_net_get_params(net: Net) -> torch.Tensor:
+    out = torch.empty(ccmg_net_param_count(), dtype=torch.float32, device=net.device)
+    _check(lib().ccmg_net_get_params(net.handle, out.data_ptr()), "ccmg_net_get_params")
+    return out
+
+
+def ccmg_net_forward(net: Net, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    nb = _net_images(net, x, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _net_images(net, y, "y")
+    _check(lib().ccmg_net_forward(net.handle, x.data_ptr(), y.data_ptr(), nb), "ccmg_net_forward")
+    return y
+
+
+def ccmg_net_loss_grad(net: Net, x: torch.Tensor, t: torch.Tensor):
+    """(loss, gradient vector) of the mean squared error of net(x) against t."""
+    nb = _net_images(net, x, "x")
+    if _net_images(net, t, "t") != nb:
+        raise ValueError("x and t differ in batch")
+    g = torch.empty(ccmg_net_param_count(), dtype=torch.float32, device=net.device)
+    loss = ctypes.c_float()
+    _check(lib().ccmg_net_loss_grad(net.handle, x.data_ptr(), t.data_ptr(), nb, g.data_ptr(), ctypes.byref(loss)),
+           "ccmg_net_loss_grad")
+    return loss.value, g
+
+
+def ccmg_net_train_step(net: Net, x: torch.Tensor, t: torch.Tensor, lr: float, want_loss: bool = True):
+    """One Adam step; returns the loss before the step (None unless want_loss:
+    reading it back synchronises the stream)."""
+    nb = _net_images(net, x, "x")
+    if _net_images(net, t, "t") != nb:
+        raise ValueError("x and t differ in batch")
+    loss = ctypes.c_float()
+    _check(lib().ccmg_net_train_step(net.handle, x.data_ptr(), t.data_ptr(), nb, float(lr),
+                                     ctypes.byref(loss) if want_loss else None), "ccmg_net_train_step")
+    return loss.value if want_loss else None
+
+
+def ccmg_net_encode(net: Net, a: torch.Tensor, scale_src: torch.Tensor, out: torch.Tensor | None = None):
+    """Block means of the field `a` on the network grid, divided by the RMS of
+    the field `scale_src`; out: (NET_G, NET_G) float32 (a view into a batch is fine)."""
+    n = a.shape[0] - 2
+    ap, pa = _field_args(a, n)
+    sp, ps = _field_args(scale_src, n)
+    if out is None:
+        out = torch.empty((NET_G, NET_G), dtype=torch.float32, device=a.device)
+    if out.dtype != torch.float32 or tuple(out.shape) != (NET_G, NET_G) or not out.is_contiguous():
+        raise ValueError(f"out: expected a contiguous float32 ({NET_G}, {NET_G}) tensor")
+    _check(lib().ccmg_net_encode(net.handle, ap, pa, n, sp, ps, out.data_ptr()), "ccmg_net_encode")
+    return out
+
+
+COARSE_ITERS = 16  # default relaxation iterations on the network's grid
+
+
+def ccmg_net_guess(net: Net, f: torch.Tensor, phi: torch.Tensor, length: float = 1.0,
+                   coarse_iters: int = COARSE_ITERS) -> None:
+    n = f.shape[0] - 2
+    fp, pf = _field_args(f, n)
+    pp, pph = _field_args(phi, n)
+    _check(lib().ccmg_net_guess(net.handle, fp, pf, n, float(length), int(coarse_iters), pp, pph), "ccmg_net_guess")
+
+
+def ccmg_solve_learned(plan: Plan, net: Net, f: torch.Tensor, phi: torch.Tensor, coarse_iters: int = COARSE_ITERS):
+    """Guess with the net, then plain multigrid to tolerance; returns (Result, guess_used)."""
+    n = plan.n
+    fp, pitch = _field_args(f, n)
+    pp, pitch2 = _field_args(phi, n)
+    if pitch != pitch2:
+        raise ValueError("f and phi must share one pitch")
+    r = ccmg_result()
+    used = ctypes.c_int()
+    st = lib().ccmg_solve_learned(plan.handle, net.handle, fp, pp, pitch, int(coarse_iters), ctypes.byref(r),
+                                  ctypes.byref(used))
+    _check(st, "ccmg_solve_learned", allow=(OK, NOT_CONVERGED))
+    hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles), bool(used.value)
 
 
 def field(n: int, dtype=torch.float64, device="cuda", pitch: int | None = None) -> torch.Tensor:

@@ -133,4 +133,13 @@ hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, in
 hipError_t launch_set(double *p, int count, double v, hipStream_t s);
 hipError_t launch_set_int(int *p, int count, int v, hipStream_t s);
 
+// The stream and finest size of a plan (for entry points outside plan.cpp).
+hipStream_t plan_stream(const ccmg_plan *P);
+int plan_n(const ccmg_plan *P);
+const ccmg_problem *plan_problem(const ccmg_plan *P);
+// ccmg_solve with a bound on the guess's relative residual (see plan.cpp).
+constexpr int kGuessRejected = 100;
+int solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess, ccmg_result *out,
+               double guess_reject);
+
 }  // namespace ccmg

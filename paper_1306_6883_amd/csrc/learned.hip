@@ -1,0 +1,380 @@
+// learned.hip -- kernels of the learned initial guess.
+//
+// The network maps the right-hand side, averaged onto a G x G grid (G = 128),
+// to the solution on that grid.  The map it has to learn is linear, so the
+// network is linear: six 3x3 convolutions with circular padding and dilations
+// 1, 2, 4, 8, 16, 32 (receptive field 127 cells: the whole periodic grid),
+// channels 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, no biases.  Activations are
+// pixel-major with the 32 channels contiguous ([b][y][x][c]), BF16 between
+// layers; weights are BF16 copies of FP32 master weights.
+//
+// The 32 -> 32 layers are implicit GEMMs on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation): M = 32 pixels of one row,
+// N = 32 output channels, K = 9 taps x 32 input channels.  The input gradient
+// of such a layer is the same product with transposed, tap-flipped weights;
+// the weight gradient is a product with K running over pixels.  The 1-channel
+// first and last layers are small and run on the vector units.
+//
+// Operand layouts of v_mfma_f32_32x32x16_bf16 (wave64): lane l holds
+//   A (32 x 16): row l % 32, k = 8 (l / 32) + i, i = 0..7;
+//   B (16 x 32): column l % 32, k = 8 (l / 32) + i;
+//   D (32 x 32, FP32): register j holds row 8 (j / 4) + 4 (l / 32) + j % 4,
+//   column l % 32.
+#include "learned.h"
+
+namespace ccmg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+__device__ __forceinline__ int wrapg(int v) { return v & (kNetG - 1); }
+// tap t = 3 ky + kx -> offset (ky - 1, kx - 1) * dilation
+__device__ __forceinline__ int tap_dy(int t, int d) { return (t / 3 - 1) * d; }
+__device__ __forceinline__ int tap_dx(int t, int d) { return (t % 3 - 1) * d; }
+
+__device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+}  // namespace
+
+// out[b][y][x][co] = sum_{tap, ci} w[co][tap][ci] * in[b][y + dy][x + dx][ci]
+// One wavefront per 32 pixels of one row.  out32 (FP32) and/or out16 (BF16).
+__global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, const __bf16 *__restrict__ w,
+                                                float *__restrict__ out32, __bf16 *__restrict__ out16, int nb, int dil) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tiles_per_row = kNetG / 32;
+    if (wave >= nb * kNetG * tiles_per_row) return;
+    const int b = wave / (kNetG * tiles_per_row);
+    const int rem = wave - b * kNetG * tiles_per_row;
+    const int y = rem / tiles_per_row;
+    const int x0 = (rem - y * tiles_per_row) * 32;
+    const int r = lane & 31, hk = lane >> 5;
+    const __bf16 *img = in + (size_t)b * kNetG * kNetG * kNetC;
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ys = wrapg(y + tap_dy(t, dil));
+        const int xs = wrapg(x0 + r + tap_dx(t, dil));
+        const __bf16 *px = img + ((size_t)ys * kNetG + xs) * kNetC;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bf16x8 av = load8(px + 16 * h + 8 * hk);
+            const bf16x8 bv = load8(w + ((size_t)r * 9 + t) * kNetC + 16 * h + 8 * hk);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    float *o32 = out32 ? out32 + (((size_t)b * kNetG + y) * kNetG + x0) * kNetC : nullptr;
+    __bf16 *o16 = out16 ? out16 + (((size_t)b * kNetG + y) * kNetG + x0) * kNetC : nullptr;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = 8 * (j / 4) + 4 * hk + (j % 4);  // pixel within the tile
+        if (o32) o32[(size_t)row * kNetC + r] = acc[j];
+        if (o16) o16[(size_t)row * kNetC + r] = (__bf16)acc[j];
+    }
+}
+
+// Weight gradient of a 32 -> 32 layer:
+//   dw[co][tap][ci] = sum_{b, y, x} g[b][y][x][co] * in[b][y + dy][x + dx][ci]
+// K runs over pixels.  Each wavefront sums `chunk` consecutive pixels (a
+// multiple of 16) and writes its 9 x 32 x 32 partial sums.
+__global__ __launch_bounds__(256) void k_conv32_wgrad(const __bf16 *__restrict__ g, const __bf16 *__restrict__ in,
+                                                      float *__restrict__ part, int npix, int chunk, int dil) {
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = (npix + chunk - 1) / chunk;
+    if (wave >= nwaves) return;
+    const int r = lane & 31, hk = lane >> 5;
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
+    const int p0 = wave * chunk;
+    const int p1 = min(p0 + chunk, npix);
+    for (int p = p0; p < p1; p += 16) {
+        // A (32 co x 16 px): lane holds co = r, pixels p + 8 hk + i
+        bf16x8 av;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) av[i] = g[(size_t)(p + 8 * hk + i) * kNetC + r];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            // B (16 px x 32 ci): lane holds ci = r, the same pixels shifted by the tap
+            bf16x8 bv;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int q = p + 8 * hk + i;
+                const int bb = q / (kNetG * kNetG);
+                const int rem = q - bb * kNetG * kNetG;
+                const int yy = wrapg(rem / kNetG + tap_dy(t, dil));
+                const int xx = wrapg(rem % kNetG + tap_dx(t, dil));
+                bv[i] = in[(((size_t)bb * kNetG + yy) * kNetG + xx) * kNetC + r];
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    float *o = part + (size_t)wave * 9 * kNetC * kNetC;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int co = 8 * (j / 4) + 4 * hk + (j % 4);
+            o[((size_t)co * 9 + t) * kNetC + r] = acc[t][j];
+        }
+}
+
+// out[i] = sum over `count` partial vectors of length len, in a fixed order.
+__global__ void k_sum_partials(const float *__restrict__ part, int count, int len, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int k = 0; k < count; ++k) s += part[(size_t)k * len + i];
+    out[i] = s;
+}
+
+// wt[ci][tap][co] = w[co][8 - tap][ci]: the input gradient of a layer is the
+// same convolution with these weights applied to the output gradient.
+__global__ void k_transpose_flip(const __bf16 *__restrict__ w, __bf16 *__restrict__ wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNetC * 9 * kNetC) return;
+    const int ci = i / (9 * kNetC), t = (i / kNetC) % 9, co = i % kNetC;
+    wt[i] = w[((size_t)co * 9 + (8 - t)) * kNetC + ci];
+}
+
+// First layer (1 -> 32): one thread per pixel.
+__global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__ w1, __bf16 *__restrict__ out,
+                          int nb, int dil) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * kNetG * kNetG) return;
+    const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, y = rem / kNetG, xx = rem % kNetG;
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+        v[t] = x[((size_t)b * kNetG + wrapg(y + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))];
+    // weights pass through BF16 like every other layer's
+    for (int co = 0; co < kNetC; ++co) {
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w1[co * 9 + t] * (float)(__bf16)v[t];
+        out[(size_t)q * kNetC + co] = (__bf16)s;
+    }
+}
+
+// Last layer (32 -> 1): one thread per pixel, FP32 output.
+__global__ void k_conv_out(const __bf16 *__restrict__ in, const float *__restrict__ w6, float *__restrict__ y,
+                           int nb, int dil) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * kNetG * kNetG) return;
+    const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, yy = rem / kNetG, xx = rem % kNetG;
+    float s = 0.f;
+    for (int t = 0; t < 9; ++t) {
+        const __bf16 *px =
+            in + (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))) * kNetC;
+        for (int ci = 0; ci < kNetC; ++ci) s += (float)(__bf16)w6[t * kNetC + ci] * (float)px[ci];
+    }
+    y[q] = s;
+}
+
+// Input gradient of the last layer: g[b][p][ci] = sum_tap w6[tap][ci] * dy[b][p - off(tap)].
+__global__ void k_conv_out_bwd(const float *__restrict__ dy, const float *__restrict__ w6, __bf16 *__restrict__ g,
+                               int nb, int dil) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nb * kNetG * kNetG) return;
+    const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, yy = rem / kNetG, xx = rem % kNetG;
+    float d[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+        d[t] = (float)(__bf16)dy[((size_t)b * kNetG + wrapg(yy - tap_dy(t, dil))) * kNetG + wrapg(xx - tap_dx(t, dil))];
+    for (int ci = 0; ci < kNetC; ++ci) {
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w6[t * kNetC + ci] * d[t];
+        g[(size_t)q * kNetC + ci] = (__bf16)s;
+    }
+}
+
+// Weight gradients of the 1-channel layers, per-block partials:
+//   mode 0 (first layer): part[blk][co][tap] = sum_p g[p][co] * x[p + off(tap)]
+//   mode 1 (last layer):  part[blk][tap][ci] = sum_p dy[p] * in[p + off(tap)][ci]
+// 256 threads: channel c = thread % 32, pixel group = thread / 32 (8 groups).
+__global__ __launch_bounds__(256) void k_wgrad_small(int mode, const __bf16 *__restrict__ act,
+                                                     const float *__restrict__ vec, float *__restrict__ part,
+                                                     int npix, int chunk, int dil) {
+    __shared__ float red[8][9 * kNetC];
+    const int c = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int p0 = blockIdx.x * chunk, p1 = min(p0 + chunk, npix);
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.f;
+    for (int q = p0 + grp; q < p1; q += 8) {
+        const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, yy = rem / kNetG, xx = rem % kNetG;
+        if (mode == 0) {
+            const float gv = (float)act[(size_t)q * kNetC + c];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                acc[t] += gv * (float)(__bf16)vec[((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
+                                                   wrapg(xx + tap_dx(t, dil))];
+        } else {
+            const float dv = (float)(__bf16)vec[q];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                acc[t] += dv * (float)act[(((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
+                                           wrapg(xx + tap_dx(t, dil))) * kNetC + c];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) red[grp][t * kNetC + c] = acc[t];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 9 * kNetC; i += 256) {
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) s += red[k][i];
+        const int t = i / kNetC, ch = i % kNetC;
+        // mode 0 stores [co][tap], mode 1 [tap][ci]
+        part[(size_t)blockIdx.x * 9 * kNetC + (mode == 0 ? ch * 9 + t : t * kNetC + ch)] = s;
+    }
+}
+
+// Mean squared error: dy = 2 (y - t) / count, and per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y, const float *__restrict__ t,
+                                             float *__restrict__ dy, double *__restrict__ part, int count) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const float e = y[i] - t[i];
+        dy[i] = 2.f * e / (float)count;
+        s += (double)e * (double)e;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_finish(const double *__restrict__ part, int blocks, int count, float *__restrict__ loss) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < blocks; ++i) s += part[i];
+        *loss = (float)(s / count);
+    }
+}
+
+// Adam on FP32 master weights; refreshes the BF16 copy of the 32 -> 32 layers.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, __bf16 *__restrict__ w16, int count, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    w16[i] = (__bf16)wi;
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, __bf16 *__restrict__ b, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) b[i] = (__bf16)a[i];
+}
+
+// Scale of a right-hand side: its RMS over the valid cells, sqrt(sum f^2 / n^2).
+__device__ __forceinline__ double rms_scale(const double *sumsq, int n) {
+    const double s = sqrt(*sumsq / ((double)n * (double)n));
+    return s > 0.0 ? s : 1.0;
+}
+
+// Encoder: out[y][x] = mean of the r x r block of f (FP64, ghosted, pitch) / scale,
+// with r = n / G (a mean of four-cell means is this block mean).
+__global__ void k_encode(const double *__restrict__ f, long pitch, int n, const double *__restrict__ sumsq,
+                         float *__restrict__ out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kNetG * kNetG) return;
+    const int r = n / kNetG;
+    const int y = q / kNetG, x = q % kNetG;
+    double s = 0.0;
+    for (int j = 0; j < r; ++j) {
+        const double *row = f + (long)(y * r + j + 1) * pitch + 1 + x * r;
+        for (int i = 0; i < r; ++i) s += row[i];
+    }
+    out[q] = (float)(s / ((double)r * r) / rms_scale(sumsq, n));
+}
+
+// Decoder, first step: the network output on the G x G grid in physical units
+// (times the RMS of f and the square of the domain side), then `iters`
+// red-black Gauss-Seidel iterations of the periodic Poisson problem
+// Lap u = f on that grid against the encoded right-hand side (x times the
+// RMS), red ((row + column) even) first, which remove the
+// grid-scale noise of the network output.  FP32 (it is only a guess); one
+// workgroup of 1024 threads, the solution in LDS, each thread owning one
+// red-black column pair in eight rows.  Writes FP64 for the prolongations.
+__global__ __launch_bounds__(1024) void k_coarse_relax(const float *__restrict__ y, const float *__restrict__ x,
+                                                       const double *__restrict__ sumsq, int nfine, double length,
+                                                       int iters, double *__restrict__ out) {
+    __shared__ float u[kNetG][kNetG];
+    const int t = threadIdx.x;
+    const int c0 = 2 * (t & 63), r0 = t >> 6;  // column pair, first row (rows r0 + 16 i)
+    const double rms = rms_scale(sumsq, nfine);
+    const float su = (float)(rms * length * length);
+    const float h2 = (float)(length * length / ((double)kNetG * kNetG));
+    float hf[8][2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = r0 + 16 * i;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int q = r * kNetG + c0 + k;
+            u[r][c0 + k] = y[q] * su;
+            hf[i][k] = -h2 * (float)(x[q] * rms);
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = r0 + 16 * i;
+                const int k = (r + colour) & 1;  // the cell of this pair with (row + column) % 2 == colour
+                const int c = c0 + k;
+                const float s = (u[r][(c + 1) & (kNetG - 1)] + u[r][(c - 1) & (kNetG - 1)]) +
+                                (u[(r + 1) & (kNetG - 1)][c] + u[(r - 1) & (kNetG - 1)][c]);
+                u[r][c] = 0.25f * (hf[i][k] + s);  // Lap u = f:  u = (sum of neighbours - h^2 f) / 4
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = r0 + 16 * i;
+        out[r * kNetG + c0] = (double)u[r][c0];
+        out[r * kNetG + c0 + 1] = (double)u[r][c0 + 1];
+    }
+}
+
+// Decoder step: one multigrid prolongation (centred slopes, no xy term,
+// periodic) from an nc x nc FP64 grid (no ghosts) to 2nc x 2nc.
+__global__ void k_decode_step(const double *__restrict__ c, int nc, double *__restrict__ fine) {
+    const int n = 2 * nc;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * n) return;
+    const int y = q / n, x = q % n, I = x >> 1, J = y >> 1, m = nc - 1;
+    auto at = [&](int jj, int ii) -> double { return c[(jj & m) * nc + (ii & m)]; };
+    const double e = at(J, I);
+    const double mx = 0.5 * (at(J, I + 1) - at(J, I - 1)), my = 0.5 * (at(J + 1, I) - at(J - 1, I));
+    const double dx = (x & 1) ? 0.25 : -0.25, dy = (y & 1) ? 0.25 : -0.25;
+    fine[q] = (e + dx * mx) + dy * my;
+}
+
+// Copy an n x n grid (no ghosts) into the valid cells of a ghosted field.
+__global__ void k_place(const double *__restrict__ src, int n, double *__restrict__ dst, long pitch) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * n) return;
+    const int y = q / n, x = q % n;
+    dst[(long)(y + 1) * pitch + 1 + x] = src[q];
+}
+
+}  // namespace ccmg

@@ -209,6 +209,10 @@ struct ccmg_plan {
     int *done() const { return at<int>(lay.flags); }
 };
 
+hipStream_t ccmg::plan_stream(const ccmg_plan *P) { return P->stream; }
+int ccmg::plan_n(const ccmg_plan *P) { return P->lay.lev[0].n; }
+const ccmg_problem *ccmg::plan_problem(const ccmg_plan *P) { return &P->p; }
+
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? CCMG_OK : CCMG_EHIP; }
@@ -933,8 +937,13 @@ int ccmg_vcycle(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch)
     return hip_status(e);
 }
 
-int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
-               ccmg_result *out) {
+}  // extern "C"
+
+// ccmg_solve, and the learned solve's first attempt: with use_guess and a
+// finite guess_reject, a guess whose relative residual is not finite or above
+// guess_reject returns kGuessRejected before any cycle runs.
+int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+                     ccmg_result *out, double guess_reject) {
     ccmg_result local;
     ccmg_result *R = out ? out : &local;
     std::memset(R, 0, sizeof(*R));
@@ -987,6 +996,7 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     const double rho0 = (use_guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
+    if (use_guess && std::isfinite(guess_reject) && !(rho0 <= guess_reject)) return R->status = kGuessRejected;
     if (!std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
     int status = CCMG_NOT_CONVERGED;
     int cycles = 0;
@@ -1049,6 +1059,13 @@ int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, 
     R->rel_resid = rho;
     R->status = status;
     return status;
+}
+
+extern "C" {
+
+int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+               ccmg_result *out) {
+    return solve_impl(P, d_f, d_phi, pitch, use_guess, out, INFINITY);
 }
 
 // ---- single steps -----------------------------------------------------------

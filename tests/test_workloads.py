@@ -41,3 +41,13 @@ def test_batch_sizes_and_bcs():
     assert ns <= {32, 64, 128, 256, 512, 1024} and len(ns) == 6
     for _, bc in items:
         assert bc[0] == bc[1] and bc[2] == bc[3] and set(bc) <= {"P", "D"}
+
+
+def test_blob_fields_built_with_torch_match_numpy():
+    """The batched torch generator gives the same fields as the numpy one."""
+    import workloads as W
+    F = W.gaussian_blobs_torch(64, [3, 4, 100000], device="cpu").numpy()
+    for k, s in enumerate([3, 4, 100000]):
+        ref = W.gaussian_blobs(64, s)
+        assert np.max(np.abs(F[k] - ref)) <= 1e-13 * np.max(np.abs(ref))
+        assert abs(F[k].mean()) < 1e-15

@@ -80,14 +80,21 @@ def gaussian_random_field(n: int, seed: int = 0, corr: float = 0.05) -> np.ndarr
     return (g - g.mean()) / g.std()
 
 
-def gaussian_blobs(n: int, seed: int) -> np.ndarray:
-    """Periodic sum of 1-8 Gaussian blobs (uniform centres, widths U[0.01, 0.1],
-    amplitudes N(0, 1)), minimum-image distance, zero mean."""
+def blob_params(seed: int):
+    """(centres [nb, 2], widths [nb], amplitudes [nb]) of the blob workload."""
     r = rng(W_BLOBS, seed)
     nb = int(r.integers(1, 9))
     c = r.uniform(0.0, 1.0, size=(nb, 2))
     w = r.uniform(0.01, 0.1, size=nb)
     a = r.normal(0.0, 1.0, size=nb)
+    return c, w, a
+
+
+def gaussian_blobs(n: int, seed: int) -> np.ndarray:
+    """Periodic sum of 1-8 Gaussian blobs (uniform centres, widths U[0.01, 0.1],
+    amplitudes N(0, 1)), minimum-image distance, zero mean."""
+    c, w, a = blob_params(seed)
+    nb = len(a)
     x = centres(n)
     f = np.zeros((n, n))
     for b in range(nb):
@@ -97,6 +104,31 @@ def gaussian_blobs(n: int, seed: int) -> np.ndarray:
         dy -= np.round(dy)
         f += a[b] * np.outer(np.exp(-dy**2 / (2 * w[b] ** 2)), np.exp(-dx**2 / (2 * w[b] ** 2)))
     return f - f.mean()
+
+
+def gaussian_blobs_torch(n: int, seeds, device="cuda"):
+    """gaussian_blobs for several seeds at once, built on a torch device:
+    a [len(seeds), n, n] float64 tensor (the same fields up to rounding)."""
+    import torch
+
+    ps = [blob_params(s) for s in seeds]
+    m = max(len(p[2]) for p in ps)
+    C = np.zeros((len(ps), m, 2))
+    Wd = np.ones((len(ps), m))
+    A = np.zeros((len(ps), m))
+    for i, (c, w, a) in enumerate(ps):
+        C[i, :len(a)], Wd[i, :len(a)], A[i, :len(a)] = c, w, a
+    dev = torch.device(device)
+    C, Wd, A = (torch.as_tensor(v, device=dev) for v in (C, Wd, A))
+    x = torch.as_tensor(centres(n), device=dev)
+    dx = x[None, None, :] - C[:, :, 0:1]
+    dx = dx - torch.round(dx)
+    dy = x[None, None, :] - C[:, :, 1:2]
+    dy = dy - torch.round(dy)
+    gx = torch.exp(-dx**2 / (2 * Wd[:, :, None] ** 2))                 # [B, m, n]
+    gy = torch.exp(-dy**2 / (2 * Wd[:, :, None] ** 2)) * A[:, :, None]
+    f = torch.bmm(gy.transpose(1, 2).contiguous(), gx.contiguous())    # [B, n(y), n(x)]
+    return f - f.mean(dim=(1, 2), keepdim=True)
 
 
 @dataclass
