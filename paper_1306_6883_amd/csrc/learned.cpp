@@ -19,7 +19,8 @@ namespace {
 
 constexpr int kPix = kNetG * kNetG;
 constexpr int kWgChunk = 1024;    // pixels per wavefront of the MFMA weight gradient
-constexpr int kSmallChunk = 4096; // pixels per workgroup of the 1-channel weight gradients
+constexpr int kSmallChunk = 512;  // pixels per workgroup of the 1-channel weight gradients
+constexpr int kSumGroups = 32;    // first-stage groups of the partial-sum reduction
 constexpr int kLossBlocks = 256;
 // A guess whose relative residual exceeds this is discarded (zero guess instead).
 constexpr double kGuessReject = 1e6;
@@ -27,7 +28,7 @@ constexpr double kGuessReject = 1e6;
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct NetLayout {
-    size_t w, m, v, grad, w16, wt16, act, g0, g1, y, dy, part, lpart, loss, x1, y1, dec0, dec1, stats, fpart;
+    size_t w, m, v, grad, w16, wt16, act, g0, g1, y, dy, part, part2, lpart, loss, x1, y1, dec0, dec1, stats, fpart;
     size_t total;
 };
 
@@ -54,6 +55,7 @@ NetLayout net_layout(int batch, int nmax) {
     const size_t wg_waves = (npix + kWgChunk - 1) / kWgChunk;
     const size_t sm_blocks = (npix + kSmallChunk - 1) / kSmallChunk;
     L.part = take(sizeof(float) * std::max(wg_waves * kWmid, sm_blocks * kW0));
+    L.part2 = take(sizeof(float) * kSumGroups * kWmid);
     L.lpart = take(sizeof(double) * kLossBlocks);
     L.loss = take(sizeof(float) * 4);
     L.x1 = take(sizeof(float) * kPix);
@@ -112,6 +114,15 @@ hipError_t forward(ccmg_net *N, const float *x, float *y, int nb) {
     return hipGetLastError();
 }
 
+// out[len] = sum of `count` partial vectors, in a fixed order (two stages).
+void sum_partials(ccmg_net *N, const float *part, int count, int len, float *out) {
+    const int groups = std::min(count, kSumGroups);
+    float *p2 = N->at<float>(N->L.part2);
+    hipLaunchKernelGGL(k_sum_partials_grouped, dim3((len + 255) / 256, groups), dim3(256), 0, N->stream, part, count,
+                       len, groups, p2);
+    hipLaunchKernelGGL(k_sum_partials, dim3((len + 255) / 256), dim3(256), 0, N->stream, p2, groups, len, out);
+}
+
 // Loss and gradients of all parameters into N->grad (after forward() on x).
 hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
     hipStream_t s = N->stream;
@@ -126,8 +137,7 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
     // last layer: weights, then the gradient of a5
     hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 1, N->act(4), dy, part, npix, kSmallChunk,
                        net_dilation(5));
-    hipLaunchKernelGGL(k_sum_partials, dim3((kW5 + 255) / 256), dim3(256), 0, s, part, sm_blocks, kW5,
-                       grad + net_param_offset(5));
+    sum_partials(N, part, sm_blocks, kW5, grad + net_param_offset(5));
     __bf16 *gcur = N->at<__bf16>(N->L.g0), *gnext = N->at<__bf16>(N->L.g1);
     hipLaunchKernelGGL(k_conv_out_bwd, dim3((npix + 255) / 256), dim3(256), 0, s, dy, N->w() + net_param_offset(5),
                        gcur, nb, net_dilation(5));
@@ -135,10 +145,9 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
     const int wg_waves = (npix + kWgChunk - 1) / kWgChunk;
     const int cv_waves = nb * kNetG * (kNetG / 32);
     for (int l = 4; l >= 1; --l) {
-        hipLaunchKernelGGL(k_conv32_wgrad, dim3((wg_waves + 3) / 4), dim3(256), 0, s, gcur, N->act(l - 1), part, npix,
+        hipLaunchKernelGGL(k_conv32_wgrad, dim3((3 * wg_waves + 3) / 4), dim3(256), 0, s, gcur, N->act(l - 1), part, npix,
                            kWgChunk, net_dilation(l));
-        hipLaunchKernelGGL(k_sum_partials, dim3((kWmid + 255) / 256), dim3(256), 0, s, part, wg_waves, kWmid,
-                           grad + net_param_offset(l));
+        sum_partials(N, part, wg_waves, kWmid, grad + net_param_offset(l));
         hipLaunchKernelGGL(k_conv32, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur,
                            N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, (float *)nullptr, gnext, nb,
                            net_dilation(l));
@@ -147,8 +156,7 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
     // first layer: weights only (its input is data)
     hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 0, gcur, x, part, npix, kSmallChunk,
                        net_dilation(0));
-    hipLaunchKernelGGL(k_sum_partials, dim3((kW0 + 255) / 256), dim3(256), 0, s, part, sm_blocks, kW0,
-                       grad + net_param_offset(0));
+    sum_partials(N, part, sm_blocks, kW0, grad + net_param_offset(0));
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ inline int net_dilation(int layer) { return 1 << layer; }
 __global__ void k_conv32(const __bf16 *in, const __bf16 *w, float *out32, __bf16 *out16, int nb, int dil);
 __global__ void k_conv32_wgrad(const __bf16 *g, const __bf16 *in, float *part, int npix, int chunk, int dil);
 __global__ void k_sum_partials(const float *part, int count, int len, float *out);
+__global__ void k_sum_partials_grouped(const float *part, int count, int len, int groups, float *out);
 __global__ void k_transpose_flip(const __bf16 *w, __bf16 *wt);
 __global__ void k_conv_in(const float *x, const float *w1, __bf16 *out, int nb, int dil);
 __global__ void k_conv_out(const __bf16 *in, const float *w6, float *y, int nb, int dil);

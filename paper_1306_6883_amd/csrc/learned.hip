@@ -77,48 +77,84 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
 
 // Weight gradient of a 32 -> 32 layer:
 //   dw[co][tap][ci] = sum_{b, y, x} g[b][y][x][co] * in[b][y + dy][x + dx][ci]
-// K runs over pixels.  Each wavefront sums `chunk` consecutive pixels (a
-// multiple of 16) and writes its 9 x 32 x 32 partial sums.
+// K runs over pixels, which are the strided dimension of the pixel-major
+// layout, so each operand tile (16 pixels x 32 channels, 1 KB) is loaded with
+// one 16-byte load per lane (pixel l / 4, channels 8 (l % 4) ..), stored
+// transposed in the wave's own LDS slot ([channel][pixel]) and read back as one
+// 16-byte LDS load per lane (channel l % 32, pixels 8 (l / 32) ..).  Runs of 16
+// pixels start at multiples of 16, so a run lies in one row; shifted runs wrap
+// pixel by pixel.  Three wavefronts share a chunk of `chunk` pixels (a
+// multiple of 16), one per row of three taps, and write the chunk's
+// 9 x 32 x 32 partial sums; the next run's tiles load during this run's
+// products.
+namespace {
+// Order this wave's LDS writes before its later LDS reads of other lanes'
+// data (a wave's LDS operations complete in issue order; this keeps the
+// compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ void store_transposed(__bf16 (*tile)[16], int px, int cg, bf16x8 v) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) tile[cg + j][px] = v[j];
+}
+}  // namespace
+
 __global__ __launch_bounds__(256) void k_conv32_wgrad(const __bf16 *__restrict__ g, const __bf16 *__restrict__ in,
                                                       float *__restrict__ part, int npix, int chunk, int dil) {
+    __shared__ __attribute__((aligned(16))) __bf16 lds[4][4][kNetC][16];
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwaves = (npix + chunk - 1) / chunk;
-    if (wave >= nwaves) return;
-    const int r = lane & 31, hk = lane >> 5;
-    f32x16 acc[9];
+    const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = blockIdx.x * 4 + wl;
+    const int nchunks = (npix + chunk - 1) / chunk;
+    if (wave >= 3 * nchunks) return;
+    const int ck = wave / 3, trow = wave - 3 * ck;  // pixel chunk, tap row (taps 3 trow .. 3 trow + 2)
+    __bf16(*tl)[kNetC][16] = lds[wl];              // tile 0: g, tiles 1..3: shifted inputs
+    const int r = lane & 31, hk = lane >> 5;        // operand lane roles
+    const int px = lane >> 2, cg = 8 * (lane & 3);  // loader lane roles
+    f32x16 acc[3];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
-    const int p0 = wave * chunk;
+    for (int t = 0; t < 3; ++t) acc[t] = f32x16{};
+    const int p0 = ck * chunk;
     const int p1 = min(p0 + chunk, npix);
+    bf16x8 v[4];
+    auto load_run = [&](int p) {
+        const int bb = p / (kNetG * kNetG);
+        const int rem = p - bb * kNetG * kNetG;
+        const int y = rem / kNetG, x0 = rem % kNetG;
+        const __bf16 *img = in + (size_t)bb * kNetG * kNetG * kNetC;
+        v[0] = load8(g + (size_t)(p + px) * kNetC + cg);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int t = 3 * trow + k;
+            const int ys = wrapg(y + tap_dy(t, dil));
+            const int xs = wrapg(x0 + px + tap_dx(t, dil));
+            v[1 + k] = load8(img + ((size_t)ys * kNetG + xs) * kNetC + cg);
+        }
+    };
+    load_run(p0);
     for (int p = p0; p < p1; p += 16) {
-        // A (32 co x 16 px): lane holds co = r, pixels p + 8 hk + i
-        bf16x8 av;
+        wave_lds_sync();  // the previous run's operand reads are done before the tiles are rewritten
 #pragma unroll
-        for (int i = 0; i < 8; ++i) av[i] = g[(size_t)(p + 8 * hk + i) * kNetC + r];
+        for (int k = 0; k < 4; ++k) store_transposed(tl[k], px, cg, v[k]);
+        if (p + 16 < p1) load_run(p + 16);  // next run's tiles in flight during this run's products
+        wave_lds_sync();
+        const bf16x8 av = load8(&tl[0][r][8 * hk]);  // A (32 co x 16 px)
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            // B (16 px x 32 ci): lane holds ci = r, the same pixels shifted by the tap
-            bf16x8 bv;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int q = p + 8 * hk + i;
-                const int bb = q / (kNetG * kNetG);
-                const int rem = q - bb * kNetG * kNetG;
-                const int yy = wrapg(rem / kNetG + tap_dy(t, dil));
-                const int xx = wrapg(rem % kNetG + tap_dx(t, dil));
-                bv[i] = in[(((size_t)bb * kNetG + yy) * kNetG + xx) * kNetC + r];
-            }
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+        for (int k = 0; k < 3; ++k) {
+            const bf16x8 bv = load8(&tl[1 + k][r][8 * hk]);  // B (16 px x 32 ci)
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[k], 0, 0, 0);
         }
     }
-    float *o = part + (size_t)wave * 9 * kNetC * kNetC;
+    float *o = part + (size_t)ck * 9 * kNetC * kNetC;
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int co = 8 * (j / 4) + 4 * hk + (j % 4);
-            o[((size_t)co * 9 + t) * kNetC + r] = acc[t][j];
+            o[((size_t)co * 9 + 3 * trow + k) * kNetC + r] = acc[k][j];
         }
 }
 
@@ -129,6 +165,18 @@ __global__ void k_sum_partials(const float *__restrict__ part, int count, int le
     float s = 0.f;
     for (int k = 0; k < count; ++k) s += part[(size_t)k * len + i];
     out[i] = s;
+}
+
+// Partial sums, first stage: out[grp][i] = sum of partials k = grp, grp + groups, ...
+// (grid: x over i, y over groups); the second stage is k_sum_partials over the groups.
+__global__ void k_sum_partials_grouped(const float *__restrict__ part, int count, int len, int groups,
+                                       float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int grp = blockIdx.y;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int k = grp; k < count; k += groups) s += part[(size_t)k * len + i];
+    out[(size_t)grp * len + i] = s;
 }
 
 // wt[ci][tap][co] = w[co][8 - tap][ci]: the input gradient of a layer is the

@@ -30,7 +30,7 @@ def test_header_declares_entry_points():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(LIB)
+    lib = ctypes.CDLL(LIB, mode=os.RTLD_NOW)  # resolve every symbol now: a missing one fails here
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
 
