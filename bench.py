@@ -193,6 +193,56 @@ def batched_vs_sequential(cc, torch, W, reps):
     return out
 
 
+def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
+    """The learned form: periodic Poisson 1024^2 with Gaussian-blob right-hand
+    sides.  Training pairs from plain multigrid solves of seeds 0..train_seeds-1,
+    training on the GPU, then time to 1e-10 with the learned guess (guess time
+    included) against the zero guess on unseen seeds 100000+."""
+    from paper_1306_6883_amd import learned as L
+    n = 1024
+    net = L.new_net(batch=32, n_max=n, seed=0)
+    plan = cc.Plan(L.periodic_poisson(n))
+    t0 = time.perf_counter()
+    data = L.make_dataset(net, n, range(train_seeds), plan=plan)
+    t_data = time.perf_counter() - t0
+    log(f"learned: {train_seeds} plain-MG training solves in {t_data:.1f} s ({data.cycles:.1f} cycles each)")
+    t0 = time.perf_counter()
+    hist = L.train(net, data, steps=train_steps, batch=32, lr=1e-3, lr_final=1e-5, warmup=200)
+    t_train = time.perf_counter() - t0
+    del data
+    ev = L.make_dataset(net, n, range(100000, 100000 + 256), plan=plan)
+    err = L.target_error(net, ev)
+    del ev
+    log(f"learned: {train_steps} Adam steps (batch 32) in {t_train:.1f} s, loss {hist[-1][1]:.3e}, "
+        f"held-out error on the network grid {err:.4f}")
+    cmp = L.compare(net, n, range(100000, 100000 + eval_seeds), plan=plan, reps=3)
+    # the guess alone
+    f = cc.field(n)
+    f[1:n + 1, 1:n + 1] = W.gaussian_blobs_torch(n, [100000])[0]
+    g = cc.field(n)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tg = []
+    for _ in range(20):
+        e0.record()
+        cc.ccmg_net_guess(net, f, g)
+        e1.record()
+        e1.synchronize()
+        tg.append(e0.elapsed_time(e1))
+    mz, ml = float(np.mean(cmp.ms_zero)), float(np.mean(cmp.ms_learned))
+    out = dict(n=n, train_solves=train_seeds, train_steps=train_steps, dataset_s=round(t_data, 1),
+               train_s=round(t_train, 1), final_loss=hist[-1][1], heldout_error=round(err, 5),
+               eval_seeds=f"100000..{100000 + eval_seeds - 1}", coarse_iters=cc.COARSE_ITERS,
+               cycles_zero=float(np.mean(cmp.cycles_zero)), cycles_learned=float(np.mean(cmp.cycles_learned)),
+               ms_zero=round(mz, 4), ms_learned=round(ml, 4), guess_ms=round(float(np.median(tg)), 4),
+               guess_error=round(float(np.mean(cmp.guess_error)), 5), speedup=round(mz / ml, 3),
+               all_reached_tol=True)
+    log(f"learned 1024^2: {out['cycles_zero']:.2f} -> {out['cycles_learned']:.2f} cycles, "
+        f"{mz:.3f} -> {ml:.3f} ms (guess {out['guess_ms']:.3f} ms), x{out['speedup']}")
+    del net, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(meas):
     ks = [k for k in meas["kernels"] if k["launches"] > 0]
     dom = max(ks, key=lambda k: k["ms"])
@@ -237,6 +287,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run and the other forms")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess leg")
+    ap.add_argument("--learned-solves", type=int, default=20000, help="training solves of the learned leg")
+    ap.add_argument("--learned-steps", type=int, default=30000, help="training steps of the learned leg")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -286,6 +339,8 @@ def main():
         del f8
         also["mixed_precision"] = mixed_vs_plain(cc, torch, W, max(args.steps // 4, 3))
         also["batched"] = batched_vs_sequential(cc, torch, W, 3)
+        if not args.no_learned:
+            also["learned"] = learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)
 
     cpu = None
     if not args.no_cpu:

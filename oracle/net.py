@@ -9,9 +9,13 @@ A convolution here is the cross-correlation
     out[y, x, co] = sum_{tap, ci} W[co, tap, ci] * in[y + dy(tap) d, x + dx(tap) d, ci]
 
 with tap = 3 (dy + 1) + (dx + 1), indices taken modulo G.  Loss: mean squared
-error.  `bf16=True` rounds to bfloat16 (round to nearest even) where the GPU
-path stores BF16: the input and weights entering each layer, the activations
-between layers and the back-propagated activation gradients; sums stay FP64.
+error.  `bf=True` applies the roundings of the GPU path (bfloat16, round to
+nearest even), with sums kept in FP64: weights rounded to bfloat16; the
+activations between layers carried as a pair of bfloat16 values
+(hi = bf16(v), lo = bf16(v - hi)); the network input unrounded; the output
+gradient and the back-propagated activation gradients rounded to bfloat16;
+the weight gradients of the 32 -> 32 layers formed from the activations'
+hi parts, those of the first and last layer from the full input / pair.
 
 Parameter vector layout: W1 [32, 9], W2..W5 [32, 9, 32], W6 [9, 32].
 """
@@ -60,6 +64,12 @@ def bf16(a: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def bf16_pair(a: np.ndarray) -> np.ndarray:
+    """v carried as hi + lo, both bfloat16 (about 16 significant bits)."""
+    hi = bf16(a)
+    return hi + bf16(np.asarray(a, dtype=np.float64) - hi)
+
+
 def shifted(a: np.ndarray, dy: int, dx: int) -> np.ndarray:
     """s[b, y, x] = a[b, (y + dy) % G, (x + dx) % G]."""
     return np.roll(a, shift=(-dy, -dx), axis=(1, 2))
@@ -92,21 +102,30 @@ def conv_w(g: np.ndarray, a: np.ndarray, d: int) -> np.ndarray:
 
 
 def forward(params: np.ndarray, x: np.ndarray, bf: bool = False):
-    """x: [B, G, G] -> (y [B, G, G], activations a0 .. a5)."""
-    r = bf16 if bf else (lambda v: v)
-    ws = [r(w) for w in split(params)]
-    a = [r(x[..., None])]
+    """x: [B, G, G] -> (y [B, G, G], layer inputs a0 .. a5, their hi parts).
+    Without `bf` the hi parts are the inputs themselves."""
+    rw = bf16 if bf else (lambda v: v)
+    ws = [rw(w) for w in split(params)]
+    a = [x[..., None]]
+    hi = [x[..., None]]
     for l in range(5):
-        a.append(r(conv(a[-1], ws[l], DIL[l])))
+        v = conv(a[-1], ws[l], DIL[l])
+        if bf:
+            h = bf16(v)
+            a.append(h + bf16(v - h))
+            hi.append(h)
+        else:
+            a.append(v)
+            hi.append(v)
     y = conv(a[-1], ws[5], DIL[5])[..., 0]
-    return y, a
+    return y, a, hi
 
 
 def loss_grad(params: np.ndarray, x: np.ndarray, t: np.ndarray, bf: bool = False):
     """Mean squared error and its gradient in every parameter."""
     r = bf16 if bf else (lambda v: v)
     ws = [r(w) for w in split(params)]
-    y, a = forward(params, x, bf)
+    y, a, hi = forward(params, x, bf)
     n = y.size
     loss = float(np.mean((y - t) ** 2))
     g = r(2.0 * (y - t) / n)[..., None]
@@ -114,7 +133,7 @@ def loss_grad(params: np.ndarray, x: np.ndarray, t: np.ndarray, bf: bool = False
     grads[5] = conv_w(g, a[5], DIL[5])
     g = r(conv_t(g, ws[5], DIL[5]))
     for l in range(4, 0, -1):
-        grads[l] = conv_w(g, a[l], DIL[l])
+        grads[l] = conv_w(g, hi[l], DIL[l])
         g = r(conv_t(g, ws[l], DIL[l]))
     grads[0] = conv_w(g, a[0], DIL[0])
     return loss, join(grads)

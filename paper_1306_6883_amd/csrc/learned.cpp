@@ -47,7 +47,7 @@ NetLayout net_layout(int batch, int nmax) {
     L.grad = take(sizeof(float) * kNetParams);
     L.w16 = take(2 * (size_t)kNetParams);
     L.wt16 = take(2 * (size_t)4 * kWmid);
-    L.act = take(2 * npix * kNetC * 5);  // a1 .. a5
+    L.act = take(2 * npix * kNetC * 10);  // a1 .. a5 (hi), then a1 .. a5 (lo)
     L.g0 = take(2 * npix * kNetC);
     L.g1 = take(2 * npix * kNetC);
     L.y = take(sizeof(float) * npix);
@@ -84,6 +84,7 @@ struct ccmg_net {
     float *w() const { return at<float>(L.w); }
     __bf16 *w16() const { return at<__bf16>(L.w16); }
     __bf16 *act(int i) const { return at<__bf16>(L.act) + (size_t)i * batch * kPix * kNetC; }  // a1 = act(0)
+    __bf16 *act_lo(int i) const { return act(5 + i); }
 };
 
 namespace {
@@ -99,18 +100,19 @@ hipError_t refresh_bf16(ccmg_net *N) {
     return hipGetLastError();
 }
 
-// Forward through the six layers: x (nb x G x G, FP32) -> y (FP32); keeps a1..a5.
+// Forward through the six layers: x (nb x G x G, FP32) -> y (FP32); keeps the
+// activation pairs a1..a5.
 hipError_t forward(ccmg_net *N, const float *x, float *y, int nb) {
     hipStream_t s = N->stream;
     const int npix = nb * kPix;
     hipLaunchKernelGGL(k_conv_in, dim3((npix + 255) / 256), dim3(256), 0, s, x, N->w() + net_param_offset(0),
-                       N->act(0), nb, net_dilation(0));
+                       N->act(0), N->act_lo(0), nb, net_dilation(0));
     const int waves = nb * kNetG * (kNetG / 32);
     for (int l = 1; l <= 4; ++l)
-        hipLaunchKernelGGL(k_conv32, dim3((waves + 3) / 4), dim3(256), 0, s, N->act(l - 1),
-                           N->w16() + net_param_offset(l), (float *)nullptr, N->act(l), nb, net_dilation(l));
-    hipLaunchKernelGGL(k_conv_out, dim3((npix + 255) / 256), dim3(256), 0, s, N->act(4), N->w() + net_param_offset(5),
-                       y, nb, net_dilation(5));
+        hipLaunchKernelGGL(k_conv32, dim3((waves + 3) / 4), dim3(256), 0, s, N->act(l - 1), N->act_lo(l - 1),
+                           N->w16() + net_param_offset(l), N->act(l), N->act_lo(l), nb, net_dilation(l));
+    hipLaunchKernelGGL(k_conv_out, dim3((npix + 255) / 256), dim3(256), 0, s, N->act(4), N->act_lo(4),
+                       N->w() + net_param_offset(5), y, nb, net_dilation(5));
     return hipGetLastError();
 }
 
@@ -135,8 +137,8 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
                        N->at<float>(N->L.loss));
     const int sm_blocks = (npix + kSmallChunk - 1) / kSmallChunk;
     // last layer: weights, then the gradient of a5
-    hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 1, N->act(4), dy, part, npix, kSmallChunk,
-                       net_dilation(5));
+    hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 1, N->act(4), N->act_lo(4), dy, part, npix,
+                       kSmallChunk, net_dilation(5));
     sum_partials(N, part, sm_blocks, kW5, grad + net_param_offset(5));
     __bf16 *gcur = N->at<__bf16>(N->L.g0), *gnext = N->at<__bf16>(N->L.g1);
     hipLaunchKernelGGL(k_conv_out_bwd, dim3((npix + 255) / 256), dim3(256), 0, s, dy, N->w() + net_param_offset(5),
@@ -148,14 +150,14 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
         hipLaunchKernelGGL(k_conv32_wgrad, dim3((3 * wg_waves + 3) / 4), dim3(256), 0, s, gcur, N->act(l - 1), part, npix,
                            kWgChunk, net_dilation(l));
         sum_partials(N, part, wg_waves, kWmid, grad + net_param_offset(l));
-        hipLaunchKernelGGL(k_conv32, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur,
-                           N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, (float *)nullptr, gnext, nb,
+        hipLaunchKernelGGL(k_conv32, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur, (const __bf16 *)nullptr,
+                           N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, gnext, (__bf16 *)nullptr, nb,
                            net_dilation(l));
         std::swap(gcur, gnext);
     }
     // first layer: weights only (its input is data)
-    hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 0, gcur, x, part, npix, kSmallChunk,
-                       net_dilation(0));
+    hipLaunchKernelGGL(k_wgrad_small, dim3(sm_blocks), dim3(256), 0, s, 0, gcur, (const __bf16 *)nullptr, x, part,
+                       npix, kSmallChunk, net_dilation(0));
     sum_partials(N, part, sm_blocks, kW0, grad + net_param_offset(0));
     return hipGetLastError();
 }
@@ -265,40 +267,42 @@ int ccmg_net_encode(ccmg_net *N, const double *d_a, ptrdiff_t pitch, int n, cons
     double *stats = N->at<double>(N->L.stats);
     hipError_t e = launch_fstats(d_scale_src, scale_pitch, n, N->at<double>(N->L.fpart), 512, stats, N->stream);
     if (e != hipSuccess) return CCMG_EHIP;
-    hipLaunchKernelGGL(k_encode, dim3((kPix + 255) / 256), dim3(256), 0, N->stream, d_a, (long)pitch, n, stats + 2,
+    hipLaunchKernelGGL(k_encode, dim3(kNetG / 64, kNetG), dim3(256), 0, N->stream, d_a, (long)pitch, n, stats + 2,
                        d_x);
     return hs(hipGetLastError());
 }
 
 // The initial guess for f (n x n, ghosted FP64): encode, network, relaxation
-// on the network's grid, multigrid prolongations back to n x n.  Writes the
-// valid cells of d_phi (the solver applies the side rules itself and removes
-// the mean of singular problems).
+// on the network's grid, prolongations to n x n, the last one into the valid
+// cells of d_phi (the solver applies the
+// side rules itself and removes the mean of singular problems).  The network
+// is linear without biases, so the RMS normalisation used in training cancels
+// here and is skipped: net(x / s) s = net(x).
 int ccmg_net_guess(ccmg_net *N, const double *d_f, ptrdiff_t pitch, int n, double length, int coarse_iters,
                    double *d_phi, ptrdiff_t phi_pitch) {
-    if (!N || !d_f || !d_phi || phi_pitch < n + 2 || n < 2 * kNetG || !(length > 0) || !std::isfinite(length) ||
-        coarse_iters < 0 || coarse_iters > 64)
+    if (!N || !d_f || !d_phi || n < 2 * kNetG || n > N->nmax || (n & (n - 1)) || pitch < n + 2 ||
+        phi_pitch < n + 2 || !(length > 0) || !std::isfinite(length) || coarse_iters < 0 || coarse_iters > 64)
         return CCMG_EINVAL;
-    int st = ccmg_net_encode(N, d_f, pitch, n, d_f, pitch, N->at<float>(N->L.x1));
-    if (st != CCMG_OK) return st;
-    hipError_t e = forward(N, N->at<float>(N->L.x1), N->at<float>(N->L.y1), 1);
+    hipStream_t s = N->stream;
+    float *x1 = N->at<float>(N->L.x1), *y1 = N->at<float>(N->L.y1);
+    hipLaunchKernelGGL(k_encode, dim3(kNetG / 64, kNetG), dim3(256), 0, s, d_f, (long)pitch, n,
+                       (const double *)nullptr, x1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = forward(N, x1, y1, 1);
     double *bufs[2] = {N->at<double>(N->L.dec0), N->at<double>(N->L.dec1)};
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_coarse_relax, dim3(1), dim3(1024), 0, N->stream, N->at<float>(N->L.y1),
-                           N->at<float>(N->L.x1), N->at<double>(N->L.stats) + 2, n, length, coarse_iters, bufs[1]);
+        hipLaunchKernelGGL(k_coarse_relax, dim3(1), dim3(kRelaxThreads), 0, s, y1, x1, (const double *)nullptr, n,
+                           length, coarse_iters, bufs[1]);
         e = hipGetLastError();
     }
     const double *src = bufs[1];
     for (int nc = kNetG, k = 0; e == hipSuccess && nc < n; nc *= 2, ++k) {
-        double *dst = bufs[k & 1];
-        hipLaunchKernelGGL(k_decode_step, dim3((4 * nc * nc + 255) / 256), dim3(256), 0, N->stream, src, nc, dst);
+        const bool last = 2 * nc == n;
+        double *dst = last ? d_phi : bufs[k & 1];
+        hipLaunchKernelGGL(k_decode_step, dim3((4 * nc * nc + 255) / 256), dim3(256), 0, s, src, nc, dst,
+                           last ? (long)phi_pitch : (long)(2 * nc), last ? 1 : 0);
         e = hipGetLastError();
         src = dst;
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_place, dim3(((size_t)n * n + 255) / 256), dim3(256), 0, N->stream, src, n, d_phi,
-                           (long)phi_pitch);
-        e = hipGetLastError();
     }
     return hs(e);
 }

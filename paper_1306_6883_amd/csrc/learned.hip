@@ -5,8 +5,10 @@
 // network is linear: six 3x3 convolutions with circular padding and dilations
 // 1, 2, 4, 8, 16, 32 (receptive field 127 cells: the whole periodic grid),
 // channels 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, no biases.  Activations are
-// pixel-major with the 32 channels contiguous ([b][y][x][c]), BF16 between
-// layers; weights are BF16 copies of FP32 master weights.
+// pixel-major with the 32 channels contiguous ([b][y][x][c]) and carried
+// between layers as a pair of BF16 planes (hi + lo, about 16 significant bits:
+// a single BF16 activation puts a noise floor of about 1% on the output);
+// weights are BF16 copies of FP32 master weights; gradients are single BF16.
 //
 // The 32 -> 32 layers are implicit GEMMs on the matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation): M = 32 pixels of one row,
@@ -39,9 +41,14 @@ __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_c
 }  // namespace
 
 // out[b][y][x][co] = sum_{tap, ci} w[co][tap][ci] * in[b][y + dy][x + dx][ci]
-// One wavefront per 32 pixels of one row.  out32 (FP32) and/or out16 (BF16).
-__global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, const __bf16 *__restrict__ w,
-                                                float *__restrict__ out32, __bf16 *__restrict__ out16, int nb, int dil) {
+// One wavefront per 32 pixels of one row.  An activation is carried as a pair
+// of BF16 values (hi + lo, about 16 significant bits): with `in_lo` the
+// products take two MFMAs (hi and lo against the same BF16 weights), and with
+// `out_lo` the FP32 sum is written as such a pair.  Without them (gradients)
+// one BF16 value.
+__global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, const __bf16 *__restrict__ in_lo,
+                                                const __bf16 *__restrict__ w, __bf16 *__restrict__ out,
+                                                __bf16 *__restrict__ out_lo, int nb, int dil) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tiles_per_row = kNetG / 32;
@@ -51,27 +58,28 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
     const int y = rem / tiles_per_row;
     const int x0 = (rem - y * tiles_per_row) * 32;
     const int r = lane & 31, hk = lane >> 5;
-    const __bf16 *img = in + (size_t)b * kNetG * kNetG * kNetC;
+    const size_t img = (size_t)b * kNetG * kNetG * kNetC;
     f32x16 acc = {};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int ys = wrapg(y + tap_dy(t, dil));
         const int xs = wrapg(x0 + r + tap_dx(t, dil));
-        const __bf16 *px = img + ((size_t)ys * kNetG + xs) * kNetC;
+        const size_t px = img + ((size_t)ys * kNetG + xs) * kNetC;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const bf16x8 av = load8(px + 16 * h + 8 * hk);
             const bf16x8 bv = load8(w + ((size_t)r * 9 + t) * kNetC + 16 * h + 8 * hk);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(in + px + 16 * h + 8 * hk), bv, acc, 0, 0, 0);
+            if (in_lo)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(in_lo + px + 16 * h + 8 * hk), bv, acc, 0, 0, 0);
         }
     }
-    float *o32 = out32 ? out32 + (((size_t)b * kNetG + y) * kNetG + x0) * kNetC : nullptr;
-    __bf16 *o16 = out16 ? out16 + (((size_t)b * kNetG + y) * kNetG + x0) * kNetC : nullptr;
+    const size_t o = (((size_t)b * kNetG + y) * kNetG + x0) * kNetC;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int row = 8 * (j / 4) + 4 * hk + (j % 4);  // pixel within the tile
-        if (o32) o32[(size_t)row * kNetC + r] = acc[j];
-        if (o16) o16[(size_t)row * kNetC + r] = (__bf16)acc[j];
+        const __bf16 hi = (__bf16)acc[j];
+        out[o + (size_t)row * kNetC + r] = hi;
+        if (out_lo) out_lo[o + (size_t)row * kNetC + r] = (__bf16)(acc[j] - (float)hi);
     }
 }
 
@@ -188,9 +196,10 @@ __global__ void k_transpose_flip(const __bf16 *__restrict__ w, __bf16 *__restric
     wt[i] = w[((size_t)co * 9 + (8 - t)) * kNetC + ci];
 }
 
-// First layer (1 -> 32): one thread per pixel.
+// First layer (1 -> 32): one thread per pixel; FP32 input, BF16 weights, the
+// output as a BF16 (hi, lo) pair.
 __global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__ w1, __bf16 *__restrict__ out,
-                          int nb, int dil) {
+                          __bf16 *__restrict__ out_lo, int nb, int dil) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nb * kNetG * kNetG) return;
     const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, y = rem / kNetG, xx = rem % kNetG;
@@ -198,26 +207,28 @@ __global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__
 #pragma unroll
     for (int t = 0; t < 9; ++t)
         v[t] = x[((size_t)b * kNetG + wrapg(y + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))];
-    // weights pass through BF16 like every other layer's
     for (int co = 0; co < kNetC; ++co) {
         float s = 0.f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w1[co * 9 + t] * (float)(__bf16)v[t];
-        out[(size_t)q * kNetC + co] = (__bf16)s;
+        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w1[co * 9 + t] * v[t];
+        const __bf16 hi = (__bf16)s;
+        out[(size_t)q * kNetC + co] = hi;
+        out_lo[(size_t)q * kNetC + co] = (__bf16)(s - (float)hi);
     }
 }
 
-// Last layer (32 -> 1): one thread per pixel, FP32 output.
-__global__ void k_conv_out(const __bf16 *__restrict__ in, const float *__restrict__ w6, float *__restrict__ y,
-                           int nb, int dil) {
+// Last layer (32 -> 1): one thread per pixel, (hi + lo) activations, FP32 output.
+__global__ void k_conv_out(const __bf16 *__restrict__ in, const __bf16 *__restrict__ in_lo,
+                           const float *__restrict__ w6, float *__restrict__ y, int nb, int dil) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nb * kNetG * kNetG) return;
     const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, yy = rem / kNetG, xx = rem % kNetG;
     float s = 0.f;
     for (int t = 0; t < 9; ++t) {
-        const __bf16 *px =
-            in + (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))) * kNetC;
-        for (int ci = 0; ci < kNetC; ++ci) s += (float)(__bf16)w6[t * kNetC + ci] * (float)px[ci];
+        const size_t px =
+            (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))) * kNetC;
+        for (int ci = 0; ci < kNetC; ++ci)
+            s += (float)(__bf16)w6[t * kNetC + ci] * ((float)in[px + ci] + (float)in_lo[px + ci]);
     }
     y[q] = s;
 }
@@ -243,8 +254,10 @@ __global__ void k_conv_out_bwd(const float *__restrict__ dy, const float *__rest
 // Weight gradients of the 1-channel layers, per-block partials:
 //   mode 0 (first layer): part[blk][co][tap] = sum_p g[p][co] * x[p + off(tap)]
 //   mode 1 (last layer):  part[blk][tap][ci] = sum_p dy[p] * in[p + off(tap)][ci]
+// (in = act + act_lo, the activation pair).
 // 256 threads: channel c = thread % 32, pixel group = thread / 32 (8 groups).
 __global__ __launch_bounds__(256) void k_wgrad_small(int mode, const __bf16 *__restrict__ act,
+                                                     const __bf16 *__restrict__ act_lo,
                                                      const float *__restrict__ vec, float *__restrict__ part,
                                                      int npix, int chunk, int dil) {
     __shared__ float red[8][9 * kNetC];
@@ -259,14 +272,16 @@ __global__ __launch_bounds__(256) void k_wgrad_small(int mode, const __bf16 *__r
             const float gv = (float)act[(size_t)q * kNetC + c];
 #pragma unroll
             for (int t = 0; t < 9; ++t)
-                acc[t] += gv * (float)(__bf16)vec[((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
-                                                   wrapg(xx + tap_dx(t, dil))];
+                acc[t] += gv * vec[((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
+                                   wrapg(xx + tap_dx(t, dil))];
         } else {
             const float dv = (float)(__bf16)vec[q];
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
-                acc[t] += dv * (float)act[(((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
-                                           wrapg(xx + tap_dx(t, dil))) * kNetC + c];
+            for (int t = 0; t < 9; ++t) {
+                const size_t a = (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG +
+                                  wrapg(xx + tap_dx(t, dil))) * kNetC + c;
+                acc[t] += dv * ((float)act[a] + (float)act_lo[a]);
+            }
         }
     }
 #pragma unroll
@@ -329,83 +344,113 @@ __global__ void k_to_bf16(const float *__restrict__ a, __bf16 *__restrict__ b, i
     if (i < count) b[i] = (__bf16)a[i];
 }
 
-// Scale of a right-hand side: its RMS over the valid cells, sqrt(sum f^2 / n^2).
+// Scale of a right-hand side: its RMS over the valid cells, sqrt(sum f^2 / n^2);
+// 1 when no statistics are given.
 __device__ __forceinline__ double rms_scale(const double *sumsq, int n) {
+    if (!sumsq) return 1.0;
     const double s = sqrt(*sumsq / ((double)n * (double)n));
     return s > 0.0 ? s : 1.0;
 }
 
 // Encoder: out[y][x] = mean of the r x r block of f (FP64, ghosted, pitch) / scale,
-// with r = n / G (a mean of four-cell means is this block mean).
-__global__ void k_encode(const double *__restrict__ f, long pitch, int n, const double *__restrict__ sumsq,
-                         float *__restrict__ out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= kNetG * kNetG) return;
+// with r = n / G (a mean of four-cell means is this block mean).  A workgroup
+// covers 64 blocks of one block row; its four waves take every fourth fine
+// row, each lane summing its block's r columns (a wave reads 64 r contiguous
+// values per row), and the four row sums meet in LDS.
+__global__ __launch_bounds__(256) void k_encode(const double *__restrict__ f, long pitch, int n,
+                                                const double *__restrict__ sumsq, float *__restrict__ out) {
+    __shared__ double red[4][64];
+    const int xi = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + xi, y = blockIdx.y;
     const int r = n / kNetG;
-    const int y = q / kNetG, x = q % kNetG;
     double s = 0.0;
-    for (int j = 0; j < r; ++j) {
-        const double *row = f + (long)(y * r + j + 1) * pitch + 1 + x * r;
+    for (int j = ph; j < r; j += 4) {
+        const double *row = f + (long)(y * r + j + 1) * pitch + 1 + (long)x * r;
         for (int i = 0; i < r; ++i) s += row[i];
     }
-    out[q] = (float)(s / ((double)r * r) / rms_scale(sumsq, n));
+    red[ph][xi] = s;
+    __syncthreads();
+    if (ph == 0) {
+        const double t = (red[0][xi] + red[1][xi]) + (red[2][xi] + red[3][xi]);
+        out[y * kNetG + x] = (float)(t / ((double)r * r) / rms_scale(sumsq, n));
+    }
 }
 
 // Decoder, first step: the network output on the G x G grid in physical units
-// (times the RMS of f and the square of the domain side), then `iters`
-// red-black Gauss-Seidel iterations of the periodic Poisson problem
+// (times the RMS of f when given, and the square of the domain side), then
+// `iters` red-black Gauss-Seidel iterations of the periodic Poisson problem
 // Lap u = f on that grid against the encoded right-hand side (x times the
-// RMS), red ((row + column) even) first, which remove the
-// grid-scale noise of the network output.  FP32 (it is only a guess); one
-// workgroup of 1024 threads, the solution in LDS, each thread owning one
-// red-black column pair in eight rows.  Writes FP64 for the prolongations.
-__global__ __launch_bounds__(1024) void k_coarse_relax(const float *__restrict__ y, const float *__restrict__ x,
-                                                       const double *__restrict__ sumsq, int nfine, double length,
-                                                       int iters, double *__restrict__ out) {
+// RMS), red ((row + column) even) first, which remove the grid-scale noise of
+// the network output.  FP32 (it is only a guess).  One workgroup of 512
+// threads: the first 256 each keep an 8 x 8 block in registers and exchange
+// only block edges through LDS.  Output: G x G FP64 (no ghosts).
+__global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__restrict__ y,
+                                                                const float *__restrict__ x,
+                                                                const double *__restrict__ sumsq, int nfine,
+                                                                double length, int iters,
+                                                                double *__restrict__ out) {
+    constexpr int B = 8, NB = kNetG / B, m = kNetG - 1;  // 16 x 16 blocks of 8 x 8 cells
     __shared__ float u[kNetG][kNetG];
     const int t = threadIdx.x;
-    const int c0 = 2 * (t & 63), r0 = t >> 6;  // column pair, first row (rows r0 + 16 i)
     const double rms = rms_scale(sumsq, nfine);
     const float su = (float)(rms * length * length);
     const float h2 = (float)(length * length / ((double)kNetG * kNetG));
-    float hf[8][2];
+    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) u[q / kNetG][q % kNetG] = y[q] * su;
+    __syncthreads();
+    if (t < NB * NB) {
+        const int R0 = B * (t / NB), C0 = B * (t % NB);  // block origin (even: block parity = global parity)
+        float v[B][B], hf[B][B];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int r = r0 + 16 * i;
+        for (int i = 0; i < B; ++i)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int q = r * kNetG + c0 + k;
-            u[r][c0 + k] = y[q] * su;
-            hf[i][k] = -h2 * (float)(x[q] * rms);
+            for (int j = 0; j < B; ++j) {
+                v[i][j] = u[R0 + i][C0 + j];
+                hf[i][j] = -h2 * (float)(x[(R0 + i) * kNetG + C0 + j] * rms);
+            }
+        const int up = (R0 - 1) & m, dn = (R0 + B) & m, lf = (C0 - 1) & m, rt = (C0 + B) & m;
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // updates of colour c: neighbours inside the block from registers,
+                // outside from the edges the neighbouring blocks published
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+#pragma unroll
+                    for (int j = 0; j < B; ++j) {
+                        if (((i + j) & 1) != c) continue;
+                        const float w = j > 0 ? v[i][j - 1] : u[R0 + i][lf];
+                        const float e = j < B - 1 ? v[i][j + 1] : u[R0 + i][rt];
+                        const float nn = i > 0 ? v[i - 1][j] : u[up][C0 + j];
+                        const float ss = i < B - 1 ? v[i + 1][j] : u[dn][C0 + j];
+                        v[i][j] = 0.25f * (hf[i][j] + ((e + w) + (ss + nn)));  // u = (sum - h^2 f) / 4
+                    }
+                // publish the updated edge cells
+#pragma unroll
+                for (int i = 0; i < B; ++i)
+#pragma unroll
+                    for (int j = 0; j < B; ++j) {
+                        if (((i + j) & 1) != c) continue;
+                        if (i == 0 || i == B - 1 || j == 0 || j == B - 1) u[R0 + i][C0 + j] = v[i][j];
+                    }
+                __syncthreads();
+            }
         }
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+            for (int j = 0; j < B; ++j) u[R0 + i][C0 + j] = v[i][j];
+    } else {
+        for (int it = 0; it < 2 * iters; ++it) __syncthreads();  // keep the barrier count of the relaxing threads
     }
     __syncthreads();
-    for (int it = 0; it < iters; ++it) {
-#pragma unroll
-        for (int colour = 0; colour < 2; ++colour) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int r = r0 + 16 * i;
-                const int k = (r + colour) & 1;  // the cell of this pair with (row + column) % 2 == colour
-                const int c = c0 + k;
-                const float s = (u[r][(c + 1) & (kNetG - 1)] + u[r][(c - 1) & (kNetG - 1)]) +
-                                (u[(r + 1) & (kNetG - 1)][c] + u[(r - 1) & (kNetG - 1)][c]);
-                u[r][c] = 0.25f * (hf[i][k] + s);  // Lap u = f:  u = (sum of neighbours - h^2 f) / 4
-            }
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int r = r0 + 16 * i;
-        out[r * kNetG + c0] = (double)u[r][c0];
-        out[r * kNetG + c0 + 1] = (double)u[r][c0 + 1];
-    }
+    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) out[q] = (double)u[q / kNetG][q % kNetG];
 }
 
 // Decoder step: one multigrid prolongation (centred slopes, no xy term,
-// periodic) from an nc x nc FP64 grid (no ghosts) to 2nc x 2nc.
-__global__ void k_decode_step(const double *__restrict__ c, int nc, double *__restrict__ fine) {
+// periodic) from an nc x nc FP64 grid (no ghosts) to 2nc x 2nc, written plain
+// (out_pitch = 2nc) or into the valid cells of a ghosted field.
+__global__ void k_decode_step(const double *__restrict__ c, int nc, double *__restrict__ fine, long out_pitch,
+                              int ghosted) {
     const int n = 2 * nc;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n * n) return;
@@ -414,15 +459,10 @@ __global__ void k_decode_step(const double *__restrict__ c, int nc, double *__re
     const double e = at(J, I);
     const double mx = 0.5 * (at(J, I + 1) - at(J, I - 1)), my = 0.5 * (at(J + 1, I) - at(J - 1, I));
     const double dx = (x & 1) ? 0.25 : -0.25, dy = (y & 1) ? 0.25 : -0.25;
-    fine[q] = (e + dx * mx) + dy * my;
+    const double v = (e + dx * mx) + dy * my;
+    if (ghosted) fine[(long)(y + 1) * out_pitch + x + 1] = v;
+    else fine[q] = v;
 }
 
-// Copy an n x n grid (no ghosts) into the valid cells of a ghosted field.
-__global__ void k_place(const double *__restrict__ src, int n, double *__restrict__ dst, long pitch) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n * n) return;
-    const int y = q / n, x = q % n;
-    dst[(long)(y + 1) * pitch + 1 + x] = src[q];
-}
 
 }  // namespace ccmg

@@ -49,13 +49,13 @@ def test_forward_matches_oracle(M):
     net = M.Net(batch=4, n_max=256)
     M.ccmg_net_set_params(net, dev(p))
     y = M.ccmg_net_forward(net, dev(x)).cpu().numpy()
-    yb, _ = ON.forward(p.astype(np.float64), x.astype(np.float64), bf=True)
-    y64, _ = ON.forward(p.astype(np.float64), x.astype(np.float64), bf=False)
+    yb = ON.forward(p.astype(np.float64), x.astype(np.float64), bf=True)[0]
+    y64 = ON.forward(p.astype(np.float64), x.astype(np.float64), bf=False)[0]
     e_bf, e_64 = rel(y, yb), rel(y, y64)
     print(f"forward: rel err vs BF16-emulated oracle {e_bf:.2e}, vs FP64 oracle {e_64:.2e}")
-    # same rounding points: differences only from FP32 sums flipping a BF16 rounding
-    assert e_bf < 2e-3
-    # BF16 operands through six layers: a few 2^-9 relative errors
+    # same rounding points: differences only from FP32 sums flipping a rounding
+    assert e_bf < 2e-4
+    # BF16 weights (the activation pairs keep about 16 bits)
     assert e_64 < 3e-2
 
 
@@ -148,20 +148,36 @@ def test_guess_is_relaxed_prolonged_network_output(M, n, iters, length):
     f = M.to_field(fv)
     phi = M.field(n)
     M.ccmg_net_guess(net, f, phi, length=length, coarse_iters=iters)
-    x = M.ccmg_net_encode(net, f, f)
+    # the guess skips the RMS normalisation (it cancels in a linear network):
+    # encode against a scale field of RMS exactly 1
+    ones = M.to_field(np.ones((n, n)))
+    x = M.ccmg_net_encode(net, f, ones)
     y = M.ccmg_net_forward(net, x[None].contiguous())[0].cpu().numpy().astype(np.float64)
-    rms = math.sqrt(np.mean(fv ** 2))
-    c = y * rms * length ** 2
+    c = y * length ** 2
     if iters:
         prob = oracle.Problem(n=G, h=length / G, alpha=0.0, beta=-1.0, bc="PPPP")
         cf = oracle.embed(c)
-        oracle.smooth(prob, cf, oracle.embed(x.cpu().numpy().astype(np.float64) * rms), iters)
+        oracle.smooth(prob, cf, oracle.embed(x.cpu().numpy().astype(np.float64)), iters)
         c = oracle.interior(cf).copy()
     while c.shape[0] < n:
         c = ON.prolong_periodic(c)
     got = phi[1:n + 1, 1:n + 1].cpu().numpy()
     # FP32 scaling and relaxation on the device
     assert np.max(np.abs(got - c)) <= 2e-6 * np.max(np.abs(c))
+
+
+def test_guess_ignores_the_scale_of_f(M):
+    """Scaling f by a power of two scales the guess exactly (linear network,
+    no normalisation at inference, every rounding scale-invariant)."""
+    p, _, _ = make_inputs(1, 7)
+    net = M.Net(batch=1, n_max=512)
+    M.ccmg_net_set_params(net, dev(p))
+    fv = W.gaussian_blobs(512, 11)
+    g1, g2 = M.field(512), M.field(512)
+    M.ccmg_net_guess(net, M.to_field(fv), g1)
+    M.ccmg_net_guess(net, M.to_field(fv * 2.0 ** -10), g2)
+    a, b = g2.cpu().numpy() * 2.0 ** 10, g1.cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
 
 
 def test_learned_solve_converges_with_untrained_and_broken_weights(M):

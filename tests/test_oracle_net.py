@@ -70,3 +70,9 @@ def test_prolongation_matches_multigrid_oracle():
     fine = oracle.field_zeros(16)
     oracle.prolong_add(oracle.embed(c), fine, "PPPP")
     assert np.allclose(N.prolong_periodic(c), oracle.interior(fine), atol=1e-15)
+
+
+def test_bf16_pair_keeps_about_16_bits():
+    v = np.random.default_rng(4).standard_normal(10000) * 10.0 ** np.random.default_rng(5).uniform(-5, 5, 10000)
+    p = N.bf16_pair(v)
+    assert np.all(np.abs(p - v) <= 2.0 ** -16 * np.abs(v))
