@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -243,14 +244,41 @@ def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
     return out
 
 
-def roofline_of(meas):
+PMC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                           "march_finest_post_poisson4096_pmc.md")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
+    None when there is none or the kernel's sources changed since."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^\s+(\w+): (.+)$", text, flags=re.M))
+    if fields.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in fields.get("source_files", "").split():
+        with open(os.path.join(root, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != fields.get("source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def roofline_of(meas, n_expected=None):
     ks = [k for k in meas["kernels"] if k["launches"] > 0]
     dom = max(ks, key=lambda k: k["ms"])
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom["name"]) if n_expected == 4096 else None
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom["name"],
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["name"],
                 avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_per_launch,
                 all_kernels=[dict(name=k["name"], launches=k["launches"],
                                   avg_ms=round(k["ms"] / k["launches"], 5),
@@ -288,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run and the other forms")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess leg")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-guess leg and print its result (profiling aid)")
     ap.add_argument("--learned-solves", type=int, default=20000, help="training solves of the learned leg")
     ap.add_argument("--learned-steps", type=int, default=30000, help="training steps of the learned leg")
     ap.add_argument("--probe-copy", action="store_true",
@@ -302,6 +332,10 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.learned_only:
+        print(json.dumps({"learned": learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)}),
+              flush=True)
+        return
     n = 4096
     log("generating inputs")
     f4096 = W.fourier_modes(n, seed=0, count=64, kmax=32)
@@ -320,7 +354,7 @@ def main():
     m = measure(cc, torch, n, "P", f4096, args.steps, args.warmup)
     log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
         f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
-    rl = roofline_of(m)
+    rl = roofline_of(m, n_expected=n)
     log(f"dominant kernel {rl['kernel']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s ({rl['frac']:.3f})")
 
     also = {}
