@@ -8,13 +8,30 @@
 // nu1 red-black Gauss-Seidel iterations, residual and four-cell restriction,
 // recursion, centred-slope prolongation without the xy term, nu2 iterations;
 // on the 2 x 2 grid nu_bottom relaxations, done in FP64 whatever T is.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace ccmg {
 
 namespace {
 
-constexpr int kThreads = 512;  // one thread per cell of a colour on the 32 x 32 level
+// Workgroup size NT (a template parameter, 64 .. 512): 512 gives one thread per
+// cell of a colour on the 32 x 32 level.  With NT = 64 (one wavefront) no
+// workgroup barrier is needed -- a wave's LDS operations complete in issue
+// order, so ordering the compiler's code is enough between phases.
+constexpr int kDefaultCoarseThreads = 512;
+
+template <int NT>
+__device__ __forceinline__ void sync() {
+    if constexpr (NT == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 // Side rules, held in scalar registers for the whole kernel.
 struct Sides {
@@ -49,25 +66,30 @@ __device__ __forceinline__ void neighbours(const T *A, int lg, int x, int y, con
 
 // Block-wide sum in a fixed order (per-thread strided sums, per-wave butterfly,
 // then the wave totals in order).  All threads get the result.
+template <int NT>
 __device__ double block_sum(double v, double *red) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
+    if constexpr (NT == 64) {
+        return v;
+    } else {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = v;
+        __syncthreads();
+        double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < kThreads / 64; ++i) t += red[i];
-    __syncthreads();
-    return t;
+        for (int i = 0; i < NT / 64; ++i) t += red[i];
+        __syncthreads();
+        return t;
+    }
 }
 
-template <typename T>
+template <int NT, typename T>
 __device__ void relax(T *P, const T *F, int lg, const Sides &sd, T cc, T invd, int iters) {
     const int n = 1 << lg, half = (n * n) >> 1, lgh = lg - 1;
     for (int it = 0; it < iters; ++it) {
         for (int colour = 0; colour < 2; ++colour) {
-            for (int i = threadIdx.x; i < half; i += kThreads) {
+            for (int i = threadIdx.x; i < half; i += NT) {
                 const int y = i >> lgh;
                 const int x = 2 * (i - (y << lgh)) + ((y + colour) & 1);
                 const T self = P[(y << lg) + x];
@@ -75,17 +97,17 @@ __device__ void relax(T *P, const T *F, int lg, const Sides &sd, T cc, T invd, i
                 neighbours(P, lg, x, y, sd, self, e, w, nn, s);
                 P[(y << lg) + x] = (F[(y << lg) + x] + cc * (((e + w) + nn) + s)) * invd;
             }
-            __syncthreads();
+            sync<NT>();
         }
     }
 }
 
 // Fc = four-cell average of r = F - A P (fine level of n = 1 << lg cells per side).
-template <typename T>
+template <int NT, typename T>
 __device__ void restrict_residual(const T *P, const T *F, T *Fc, int lg, const Sides &sd, T alpha, T beta,
                                   T ih2) {
     const int lgc = lg - 1, nc = 1 << lgc;
-    for (int i = threadIdx.x; i < nc * nc; i += kThreads) {
+    for (int i = threadIdx.x; i < nc * nc; i += NT) {
         const int J = i >> lgc, I = i - (J << lgc);
         T r[4];
 #pragma unroll
@@ -99,24 +121,24 @@ __device__ void restrict_residual(const T *P, const T *F, T *Fc, int lg, const S
         }
         Fc[i] = T(0.25) * (((r[0] + r[1]) + r[2]) + r[3]);
     }
-    __syncthreads();
+    sync<NT>();
 }
 
-template <typename T>
+template <int NT, typename T>
 __device__ void remove_mean(T *A, int lg, double *red) {
     const int nn = 1 << (2 * lg);
     double s = 0.0;
-    for (int i = threadIdx.x; i < nn; i += kThreads) s += (double)A[i];
-    const T m = T(block_sum(s, red) / (double)nn);
-    for (int i = threadIdx.x; i < nn; i += kThreads) A[i] -= m;
-    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += NT) s += (double)A[i];
+    const T m = T(block_sum<NT>(s, red) / (double)nn);
+    for (int i = threadIdx.x; i < nn; i += NT) A[i] -= m;
+    sync<NT>();
 }
 
 // P (fine, n = 1 << lg per side) += prolongation of E (coarse, n/2 per side).
-template <typename T>
+template <int NT, typename T>
 __device__ void prolong_add(const T *E, T *P, int lg, const Sides &sd) {
     const int n = 1 << lg, lgc = lg - 1;
-    for (int i = threadIdx.x; i < n * n; i += kThreads) {
+    for (int i = threadIdx.x; i < n * n; i += NT) {
         const int y = i >> lg, x = i - (y << lg);
         const int I = x >> 1, J = y >> 1;
         const T e = E[(J << lgc) + I];
@@ -126,16 +148,16 @@ __device__ void prolong_add(const T *E, T *P, int lg, const Sides &sd) {
         const T dx = (x & 1) ? T(0.25) : T(-0.25), dy = (y & 1) ? T(0.25) : T(-0.25);
         P[i] = P[i] + ((e + dx * mx) + dy * my);
     }
-    __syncthreads();
+    sync<NT>();
 }
 
 }  // namespace
 
-template <typename T>
+template <int NT, typename T>
 __device__ void coarse_body(const CoarseArgs<T> &a) {
     __shared__ T sP[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ T sF[kCoarseMax * kCoarseMax * 4 / 3 + 8];
-    __shared__ double red[kThreads / 64];
+    __shared__ double red[NT / 64];
     if (a.skip && *a.skip) return;  // uniform over the workgroup
 
     Sides sd;
@@ -155,23 +177,23 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
 
     // top level in
     const T shift = (a.load_phi && a.phi_shift) ? T(*a.phi_shift) : T(0);
-    for (int i = threadIdx.x; i < n0 * n0; i += kThreads) {
+    for (int i = threadIdx.x; i < n0 * n0; i += NT) {
         const int y = i >> lg0, x = i - (y << lg0);
         sF[i] = a.f[(long)(y + 1) * a.pf + 1 + x];
         sP[i] = a.load_phi ? a.phi_in[(long)(y + 1) * a.pin + 1 + x] - shift : T(0);
     }
-    __syncthreads();
-    if (a.sub_top_mean) remove_mean(sF, lg0, red);
+    sync<NT>();
+    if (a.sub_top_mean) remove_mean<NT>(sF, lg0, red);
 
     // down
     for (int l = 0; l + 1 < L; ++l) {
         const int lg = lg0 - l;
-        relax(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu1);
-        restrict_residual(sP + off[l], sF + off[l], sF + off[l + 1], lg, sd, T(a.alpha), T(a.beta),
+        relax<NT>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu1);
+        restrict_residual<NT>(sP + off[l], sF + off[l], sF + off[l + 1], lg, sd, T(a.alpha), T(a.beta),
                           T(a.ih2[l]));
-        if (a.singular) remove_mean(sF + off[l + 1], lg - 1, red);
-        for (int i = threadIdx.x; i < (1 << (2 * (lg - 1))); i += kThreads) sP[off[l + 1] + i] = T(0);
-        __syncthreads();
+        if (a.singular) remove_mean<NT>(sF + off[l + 1], lg - 1, red);
+        for (int i = threadIdx.x; i < (1 << (2 * (lg - 1))); i += NT) sP[off[l + 1] + i] = T(0);
+        sync<NT>();
     }
     // bottom: 2 x 2 grid, relaxation only, in FP64 registers of one thread.
     // Cell q = 2y + x; its x-neighbour is q^1 and its y-neighbour q^2.  On a
@@ -193,39 +215,55 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
             return (f + c * (((e + w) + nn) + s)) * invd;
         };
         for (int it = 0; it < a.nu_bottom; ++it) {
-            p0 = upd(p0, p1, p2, f0, true, true);    // red (0,0)
-            p3 = upd(p3, p2, p1, f3, false, false);  // red (1,1)
-            p1 = upd(p1, p0, p3, f1, false, true);   // black (1,0)
-            p2 = upd(p2, p3, p0, f2, true, false);   // black (0,1)
+            const double q0 = upd(p0, p1, p2, f0, true, true);    // red (0,0)
+            const double q3 = upd(p3, p2, p1, f3, false, false);  // red (1,1)
+            const double q1 = upd(p1, q0, q3, f1, false, true);   // black (1,0)
+            const double q2 = upd(p2, q3, q0, f2, true, false);   // black (0,1)
+            // an iteration that changes nothing is a fixed point: the remaining
+            // iterations would return exactly these values
+            const bool same = q0 == p0 && q1 == p1 && q2 == p2 && q3 == p3;
+            p0 = q0, p1 = q1, p2 = q2, p3 = q3;
+            if (same) break;
         }
         sP[off[l] + 0] = T(p0);
         sP[off[l] + 1] = T(p1);
         sP[off[l] + 2] = T(p2);
         sP[off[l] + 3] = T(p3);
     }
-    __syncthreads();
+    sync<NT>();
     // up
     for (int l = L - 2; l >= 0; --l) {
         const int lg = lg0 - l;
-        prolong_add(sP + off[l + 1], sP + off[l], lg, sd);
-        relax(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu2);
+        prolong_add<NT>(sP + off[l + 1], sP + off[l], lg, sd);
+        relax<NT>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu2);
     }
     // top level out
-    for (int i = threadIdx.x; i < n0 * n0; i += kThreads) {
+    for (int i = threadIdx.x; i < n0 * n0; i += NT) {
         const int y = i >> lg0, x = i - (y << lg0);
         a.phi_out[(long)(y + 1) * a.pout + 1 + x] = sP[i];
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse(const CoarseArgs<T> a) {
-    coarse_body(a);
+template <int NT, typename T>
+__global__ __launch_bounds__(NT) void k_coarse(const CoarseArgs<T> a) {
+    coarse_body<NT>(a);
 }
 
 // Batches: one workgroup per problem.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_list(const CoarseArgs<T> *__restrict__ list) {
-    coarse_body(list[blockIdx.x]);
+template <int NT, typename T>
+__global__ __launch_bounds__(NT) void k_coarse_list(const CoarseArgs<T> *__restrict__ list) {
+    coarse_body<NT>(list[blockIdx.x]);
+}
+
+// Workgroup size of the tail: CCMG_COARSE_THREADS (64, 128, 256 or 512) if
+// set, else the default.
+int coarse_threads() {
+    static int nt = [] {
+        const char *e = std::getenv("CCMG_COARSE_THREADS");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 64 || v == 128 || v == 256 || v == 512) ? v : kDefaultCoarseThreads;
+    }();
+    return nt;
 }
 
 template <typename T>
@@ -244,14 +282,24 @@ hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
     if (a0.n_top < 2 || a0.n_top > kCoarseMax || (a0.n_top & (a0.n_top - 1))) return hipErrorInvalidValue;
     CoarseArgs<T> a = a0;
     coarse_fill_consts(a);
-    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kThreads), 0, s, a);
+    switch (coarse_threads()) {
+        case 64: hipLaunchKernelGGL((k_coarse<64, T>), dim3(1), dim3(64), 0, s, a); break;
+        case 128: hipLaunchKernelGGL((k_coarse<128, T>), dim3(1), dim3(128), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((k_coarse<256, T>), dim3(1), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_coarse<512, T>), dim3(1), dim3(512), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_coarse_list(const CoarseArgs<T> *list, int count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_list<T>, dim3(count), dim3(kThreads), 0, s, list);
+    switch (coarse_threads()) {
+        case 64: hipLaunchKernelGGL((k_coarse_list<64, T>), dim3(count), dim3(64), 0, s, list); break;
+        case 128: hipLaunchKernelGGL((k_coarse_list<128, T>), dim3(count), dim3(128), 0, s, list); break;
+        case 256: hipLaunchKernelGGL((k_coarse_list<256, T>), dim3(count), dim3(256), 0, s, list); break;
+        default: hipLaunchKernelGGL((k_coarse_list<512, T>), dim3(count), dim3(512), 0, s, list); break;
+    }
     return hipGetLastError();
 }
 

@@ -68,9 +68,16 @@ struct WorkItem {
 
 // Launch description chosen by the host for one level.
 struct MarchShape {
-    int ty;       // rows per tile (even)
+    int ty;       // rows per tile (even); 0: the 2-D LDS tile kernel (tile.hip)
     int wpb;      // waves per workgroup
 };
+
+// The 2-D LDS tile kernel (levels below the finest, n >= kTileMinN): the same
+// launches as the row march for POST_NONE / POST_RESTRICT without a phi shift.
+constexpr int kTileMinN = 64;
+template <typename T>
+hipError_t launch_tile(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post, hipStream_t s,
+                       int *ntiles_out);
 
 // Host launchers (march.hip).  nu in {0,1,2}; load_phi=false means phi starts at 0.
 // *ntiles_out receives the number of tiles (= partial-sum slots) of the launch.

@@ -7,6 +7,7 @@ namespace ccmg {
 template <typename T>
 hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post,
                         MarchShape shape, hipStream_t s, int *nt) {
+    if (shape.ty == 0) return launch_tile<T>(a, nu, load_phi, prolong, post, s, nt);
     if (shape.ty < 2 || (shape.ty & 1) || shape.wpb < 1 || shape.wpb > 4) return hipErrorInvalidValue;
     switch (nu) {
         case 0: return dispatch_nu<T, 0>(a, load_phi, prolong, post, shape, s, nt);

@@ -715,7 +715,7 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
     // the workspace is scratch between calls: start from zeros (values do not
     // change the timing, but keep them finite)
     hipError_t err = hipMemsetAsync(P->ws, 0, lay.total, s);
-    const int tys[] = {8, 16, 32, 64, 128, 256};
+    const int tys[] = {0, 8, 16, 32, 64, 128, 256};
     const int wpbs[] = {1, 2, 4};
     const int reps = 4;
     for (int l = 0; l < lay.lt && err == hipSuccess; ++l) {
@@ -774,10 +774,15 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             }
             float best = 1e30f;
             MarchShape bs = kind == 0 ? P->shp_pre[l] : P->shp_post[l];
+            // candidates: row-march shapes, and (levels below the finest) the
+            // 2-D LDS tile kernel, written as ty = 0
+            const bool tile_ok = l > 0 && n >= kTileMinN;
             for (int ty : tys) {
-                if (ty > n && ty != tys[0]) continue;
+                if (ty > n && ty != tys[0] && !(ty == tys[0] && tile_ok)) continue;
                 for (int wpb : wpbs) {
-                    MarchShape sh{ty < n ? ty : n, wpb};
+                    if (ty == 0 && wpb != wpbs[0]) continue;
+                    MarchShape sh{ty == 0 ? 0 : (ty < n ? ty : n), wpb};
+                    if (ty == 0 && !tile_ok) continue;
                     int nt;
                     err = launch_march<T>(a, nu, load_phi, prolong, post, sh, s, &nt);  // warm-up
                     if (err == hipSuccess) err = hipEventRecord(e0, s);
@@ -818,6 +823,12 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
 
 int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || (kind != 0 && kind != 1)) return CCMG_EINVAL;
+    if (ty == 0) {  // the 2-D LDS tile kernel: levels below the finest that are not in the tail
+        if (level == 0 || level >= P->lay.lt || P->lay.lev[level].n < kTileMinN) return CCMG_EINVAL;
+        if (kind == 0) P->shp_pre[level] = MarchShape{0, 1};
+        else P->shp_post[level] = MarchShape{0, 1};
+        return CCMG_OK;
+    }
     if (ty < 2 || (ty & 1) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
     // the partial-sum buffers are sized for bands of at least kMinTy rows
     const int n = P->lay.lev[level].n;
@@ -1018,14 +1029,29 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
             return x;
         };
+        // Cycle k+1 is queued before cycle k's residual is read, so the GPU
+        // never waits for the host; if cycle k converges, k+1 runs as no-ops
+        // (each launch still costs a dispatch).  When the last two residuals
+        // predict that cycle k converges, k+1 is queued only after the check.
+        std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
+        rhos[0] = rho0;
         e = enqueue(1);
+        int queued = 1;
         for (int k = 1; e == hipSuccess; ++k) {
-            if (k < P->p.max_cycles) e = enqueue(k + 1);  // runs as no-ops if step k converges
+            if (queued == k && k < P->p.max_cycles) {
+                const bool likely_last =
+                    k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol;
+                if (!likely_last) {
+                    e = enqueue(k + 1);
+                    queued = k + 1;
+                }
+            }
             if (e != hipSuccess) break;
             e = hipEventSynchronize(P->ev_sync[k & 1]);
             if (e != hipSuccess) break;
             rho = P->hrho[k];  // written by the step's last kernel (host-mapped)
             R->history[k] = rho;
+            rhos[k] = rho;
             cycles = k;
             if (!std::isfinite(rho)) {
                 status = CCMG_ENONFINITE;
@@ -1036,6 +1062,10 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 break;
             }
             if (k >= P->p.max_cycles) break;
+            if (queued == k) {  // the prediction was wrong: queue the next cycle now
+                e = enqueue(k + 1);
+                queued = k + 1;
+            }
         }
         if (e != hipSuccess) return R->status = CCMG_EHIP;
     }

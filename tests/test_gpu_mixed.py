@@ -119,3 +119,33 @@ def test_mixed_guess_and_history():
     plan1 = mixed_plan(n, "DDDD", max_cycles=2)
     r3 = cc.ccmg_solve(plan1, d_f, dev_field(oracle.field_zeros(n)))
     assert r3.status == cc.NOT_CONVERGED and r3.cycles == 2
+
+
+@pytest.mark.parametrize("bc", ["DDDD", "PPPP", "DNPP"])
+def test_mixed_tile_kernel_matches_row_march(bc):
+    """The FP32 inner cycles give the same iterate whether the levels below the
+    finest run as row-march bands or as 2-D LDS tiles (bitwise; singular
+    problems to rounding, their coarse means being sums grouped by tile)."""
+    n = 512
+    fv = np.random.default_rng(33).standard_normal((n, n))
+    if exact.is_singular(0.0, bc):
+        fv -= fv.mean()
+    outs = []
+    for mode in ("march", "tile"):
+        plan = mixed_plan(n, bc)
+        for level in range(1, 4):  # 256, 128, 64 (32 and below run in the tail)
+            for kind in (0, 1):
+                if mode == "tile":
+                    cc.ccmg_plan_set_shape(plan, level, kind, 0, 1)
+                else:
+                    cc.ccmg_plan_set_shape(plan, level, kind, 16, 1)
+        d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
+        r = cc.ccmg_solve(plan, d_f, d_phi)
+        assert r.status == cc.OK and r.rel_resid <= 1e-10
+        outs.append((host(d_phi), r.cycles))
+    assert outs[0][1] == outs[1][1]
+    if exact.is_singular(0.0, bc):
+        a, b = outs[0][0], outs[1][0]
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+    else:
+        assert np.array_equal(outs[0][0], outs[1][0])

@@ -264,7 +264,8 @@ def test_deterministic_bitwise():
 @pytest.mark.parametrize("bc", ["PPPP", "DNDD"])
 def test_tile_shape_invariance(bc):
     """Every cell's arithmetic is independent of how a level is cut into tiles:
-    three V-cycles give bitwise-identical iterates for any launch shapes, and
+    three V-cycles give bitwise-identical iterates for any launch shapes (row
+    march bands, or the 2-D LDS tile kernel below the finest level), and
     after autotuning.  Singular problems (all periodic) also remove the mean of
     each coarse right-hand side, a sum whose grouping follows the tiles, so
     there the iterates agree to rounding instead."""
@@ -274,9 +275,16 @@ def test_tile_shape_invariance(bc):
     f = dev_field(oracle.embed(fv))
     start = rand(n, 17)
     outs = []
-    for shapes in ([(8, 1), (8, 4)], [(64, 2), (16, 1)], [(256, 4), (128, 2)], "auto"):
+    for shapes in ([(8, 1), (8, 4)], [(64, 2), (16, 1)], [(256, 4), (128, 2)], "tile", "auto"):
         if shapes == "auto":
             cc.ccmg_plan_autotune(plan, f, dev_field(start))
+        elif shapes == "tile":  # the 2-D LDS tile kernel on every level below the finest
+            cc.ccmg_plan_set_shape(plan, 0, 0, 64, 1)
+            cc.ccmg_plan_set_shape(plan, 0, 1, 128, 1)
+            for level in range(1, 5):
+                cc.ccmg_plan_set_shape(plan, level, 0, 0, 1)
+                cc.ccmg_plan_set_shape(plan, level, 1, 0, 1)
+            assert [s[0] for s in cc.ccmg_plan_shapes(plan)[1:5]] == [0] * 4
         else:
             for level in range(5):
                 cc.ccmg_plan_set_shape(plan, level, 0, *shapes[0])
