@@ -18,7 +18,11 @@ enum Post {
     POST_RESID = 3,     // residual -> aux
     POST_IR = 4,        // (float launches) relaxed e -> phi64_out = phi64_in + e, FP64 residual
                         // of phi64_out -> r32 (+ sum r^2, sum phi64, sum r32 per tile)
-    POST_R32 = 5        // (double launches) residual -> r32 (+ the same three sums)
+    POST_R32 = 5,       // (double launches) residual -> r32 (+ the same three sums)
+    POST_FUSED = 6      // (double, finest level, NU = 4) the post-smoothing of one cycle and the
+                        // pre-smoothing of the next in one launch: after the first two iterations
+                        // the residual norm (sum r^2, sum phi per tile -> partial_norm) and the
+                        // iterate (-> phi_mid, if set); after all four, RESTRICT as above
 };
 
 // Arguments of one row-march launch over one grid level (see march.hip).
@@ -58,6 +62,10 @@ struct MarchArgs {
     double alpha64, beta64, ih2_64;
     int q_zero;          // POST_IR: the FP64 iterate is zero (q_in is not used)
     int *count_out;      // if set, receives ntiles (producers of per-tile sums)
+    // POST_FUSED: the iterate after the post-smoothing and its per-tile norm sums
+    T *phi_mid;
+    long pmid;
+    double *partial_norm;
 };
 
 // One unit of work of a batched launch: tile `tile` of level descriptor `desc`.
@@ -84,6 +92,8 @@ hipError_t launch_tile(const MarchArgs<T> &a, int nu, bool load_phi, bool prolon
 template <typename T>
 hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post,
                         MarchShape shape, hipStream_t s, int *ntiles_out);
+// The fused finest-level launch (POST_FUSED; march_f64_fused.hip).
+hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 // One march variant family with NU fused iterations; defined in march_impl.h and
 // instantiated per (T, NU) in the march_*.hip files.
 template <typename T, int NU>

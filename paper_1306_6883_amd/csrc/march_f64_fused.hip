@@ -1,0 +1,9 @@
+// The fused finest-level row march (double): post-smoothing of one V-cycle,
+// its residual norm, and the pre-smoothing and restriction of the next.
+#include "march_impl.h"
+
+namespace ccmg {
+hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt) {
+    return go<double, 4, true, true, POST_FUSED>(a, sh, s, nt);
+}
+}  // namespace ccmg

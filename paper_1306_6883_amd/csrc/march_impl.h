@@ -91,7 +91,7 @@ struct Cfg {
     static constexpr int HXC = 2 * NU + (POST ? 1 : 0) + (PROLONG ? 2 : 0);
     static constexpr int HX = (HXC + 1) & ~1;
     static constexpr int HY = (LAST + 1) & ~1;  // halo rows (even: rows start on red parity)
-    static constexpr int W = 10;                // register window (rows), even
+    static constexpr int W = LAST >= 7 ? 14 : 10;  // register window (rows), even
     static constexpr int D = W - LAST - 2;      // prefetch distance (rows)
     static constexpr int WC = W / 2;            // coarse-row window
     static constexpr int DC = WC - 3;           // coarse prefetch distance
@@ -185,6 +185,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
 
     double acc0 = 0.0, acc1 = 0.0;
     T rprev0 = T(0), rprev1 = T(0);
+    // POST_FUSED: norm sums after the post-smoothing, and that state of the
+    // previous row (the row below the one whose residual is taken)
+    constexpr bool FUSED = POST == POST_FUSED;
+    static_assert(!FUSED || NU == 4, "the fused launch runs 2 + 2 iterations");
+    double accN0 = 0.0, accN1 = 0.0;
+    T SA[2] = {T(0), T(0)}, SB[2] = {T(0), T(0)};
 
     static_for<0, D>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
@@ -260,7 +266,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             // Unconditional: a stage on a row outside [ys, ye) writes a slot that
             // either is reloaded before it is read again (rows below ys) or only
             // feeds halo rows (rows at or past ye).
-            static_for<1, 2 * NU + 1>([&](auto sc) {
+            auto stage = [&](auto sc) {
                 constexpr int s = decltype(sc)::value;
                 const int y = t - s;
                 constexpr int kk = (k - s + 2 * W) % W;
@@ -295,7 +301,57 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     }
                     P1[kk] = (F1[kk] + cc * (((e + w) + nn) + ss)) * invd;
                 }
-            });
+            };
+            if constexpr (FUSED) {
+                // stages 1-4 finish the post-smoothing of row t-4; before stage 5
+                // touches row t-5, take the residual norm of row t-5 (rows t-6
+                // .. t-4 all after stage 4; row t-6 from the copy saved one step
+                // ago) and store / save it
+                static_for<1, 5>(stage);
+                {
+                    const int y = t - 5;
+                    constexpr int kk = (k - 5 + 2 * W) % W;
+                    constexpr int kp = (k - 4 + 2 * W) % W;
+                    constexpr int sv = (k + 1) & 1;  // parity of row t-5 (t - k is even)
+                    const T p0 = P0[kk], p1 = P1[kk];
+                    T w0 = from_left(P1[kk]);
+                    T e1 = from_right(P0[kk]);
+                    if constexpr (XB) {
+                        if (tl.wedge) w0 = sxl * p0;
+                        if (tl.eedge) e1 = sxh * p1;
+                    }
+                    T n0 = P0[kp], n1 = P1[kp], s0 = SA[1 - sv], s1 = SB[1 - sv];
+                    if constexpr (YB) {
+                        if (y == nm) {
+                            n0 = syh * p0;
+                            n1 = syh * p1;
+                        }
+                        if (y == 0) {
+                            s0 = syl * p0;
+                            s1 = syl * p1;
+                        }
+                    }
+                    if (y >= y0 && y < y1 && tl.outl) {
+                        const T ih2 = a.ih2;
+                        const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                        const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                        const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
+                        const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
+                        accN0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                        accN1 += (double)p0 + (double)p1;
+                        if (a.phi_mid) {
+                            T *o = a.phi_mid + (long)(y + 1) * a.pmid;
+                            o[1 + tl.x0] = p0;
+                            o[2 + tl.x0] = p1;
+                        }
+                    }
+                    SA[sv] = p0;
+                    SB[sv] = p1;
+                }
+                static_for<5, 2 * NU + 1>(stage);
+            } else {
+                static_for<1, 2 * NU + 1>(stage);
+            }
             // 4. store the finished row (POST_IR: add it to the FP64 iterate and store that)
             {
                 const int y = t - 2 * NU;
@@ -383,7 +439,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
                     const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
                     const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
-                    if constexpr (POST == POST_RESTRICT) {
+                    if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
                         if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
                             const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
                             if (tl.outl) {
@@ -421,9 +477,16 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
         });
     }
 
-    if constexpr (POST == POST_RESTRICT) {
+    if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
+        if constexpr (FUSED) {
+            const double s0 = wave_sum(accN0), s1 = wave_sum(accN1);
+            if (lane == 0) {
+                a.partial_norm[2 * tile] = s0;
+                a.partial_norm[2 * tile + 1] = s1;
+            }
+        }
     } else if constexpr (POST == POST_NORM || POST == POST_IR || POST == POST_R32) {
         const double s0 = wave_sum(acc0), s1 = wave_sum(acc1);
         double s2 = 0.0;

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -28,7 +29,7 @@ using namespace ccmg;
 namespace {
 
 constexpr int kMinTy = 8;       // smallest rows-per-tile the shape picker uses
-constexpr int kMinOutw = 112;   // narrowest output width of any march variant
+constexpr int kMinOutw = 104;   // narrowest output width of any march variant (the fused one)
 constexpr int kStatBlocks = 512;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -47,6 +48,7 @@ struct LevelLay {
     double h = 0;
     long pitch = 0;        // pitch of the workspace arrays of this level
     size_t a = 0, b = 0, f = 0;  // byte offsets of phi (two buffers) and f in the level's precision
+    size_t c = 0;          // FP64 level 0 (below the tail): the post-smoothed iterate of a fused launch
     size_t f2 = 0;         // MIXED level 0: second FP32 residual buffer
     size_t fpart = 0;      // partial sums of this level's rhs
     int fpart_cap = 0;
@@ -96,6 +98,7 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
         const size_t bytes = lay.elem * (size_t)(v.n + 2) * (size_t)v.pitch;
         if (l == 0 && !mixed) {
             v.b = take(bytes);  // the caller's phi is buffer a, its f the rhs
+            if (lay.lt > 0) v.c = take(bytes);
         } else if (l == 0) {
             v.a = take(bytes);  // FP32 correction e (two buffers)
             v.b = take(bytes);
@@ -150,15 +153,15 @@ MarchShape shape_for(int n) {
 
 // Events bracketing finest-level launches while profiling is on.
 struct KernelTimer {
-    static constexpr int kKinds = 4;
+    static constexpr int kKinds = 5;
     static constexpr int kPairs = 1024;
     bool on = false;
     std::vector<hipEvent_t> ev;          // 2 * kPairs
     int used = 0;
     int kind[kPairs];
     double bytes[kPairs];
-    int launches[kKinds] = {0, 0, 0, 0};
-    double ms[kKinds] = {0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0};
+    int launches[kKinds] = {0, 0, 0, 0, 0};
+    double ms[kKinds] = {0, 0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0, 0};
 };
 
 constexpr int kMaxLevels = 16;
@@ -167,6 +170,7 @@ struct ccmg_plan {
     ccmg_problem p;
     KernelTimer timer;
     MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
+    MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
     double *drho = nullptr;   // ... its device address
     Layout lay;
@@ -212,6 +216,25 @@ struct ccmg_plan {
 hipStream_t ccmg::plan_stream(const ccmg_plan *P) { return P->stream; }
 int ccmg::plan_n(const ccmg_plan *P) { return P->lay.lev[0].n; }
 const ccmg_problem *ccmg::plan_problem(const ccmg_plan *P) { return &P->p; }
+
+namespace {
+// Tuning knobs, read at every solve: CCMG_FUSED=0 turns the fused launches
+// off; CCMG_FUSED_KEEP (default 1e4) is how far above the tolerance the
+// extrapolated residual of a cycle may be for its post-smoothed iterate to be
+// kept.
+bool fused_eligible(const ccmg_plan *P) {
+    const char *e = std::getenv("CCMG_FUSED");
+    const bool off = e && e[0] == '0';
+    return !off && P->p.prec == CCMG_FP64 && P->lay.lt >= 1 && P->p.nu1 == 2 && P->p.nu2 == 2;
+}
+double fused_keep_factor() {
+    const char *e = std::getenv("CCMG_FUSED_KEEP");
+    if (!e) return 1e4;
+    const double v = std::atof(e);
+    return v >= 0.0 ? v : 1e4;
+}
+
+}  // namespace
 
 namespace {
 
@@ -277,6 +300,10 @@ struct CycleIO {
     bool q_zero = false;           // the FP64 iterate is zero (first step without a guess)
     const double *q_shift = nullptr;  // subtracted from the FP64 iterate as it is read
     double *partial3_out = nullptr;   // per-tile sums of the new FP32 residual
+    // levels >= 1 only (the fused FP64 driver runs the level-0 launches itself)
+    bool coarse_only = false;
+    int f1_count = 0;                 // partial sums of the level-1 rhs already restricted
+    Buf<T> *l1_out = nullptr;         // receives the buffer holding level 1's final iterate
 };
 
 template <typename T>
@@ -348,7 +375,8 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     };
 
     // down
-    for (int l = 0; l < lay.lt; ++l) {
+    if (io.coarse_only) fpart_count[1] = io.f1_count;
+    for (int l = io.coarse_only ? 1 : 0; l < lay.lt; ++l) {
         setup_bufs(l);
         const MarchShape sh = P->shp_pre[l];
         const std::vector<int> chain = split_nu(P->p.nu1);
@@ -409,7 +437,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         if (e != hipSuccess) return e;
     }
     // up
-    for (int l = lay.lt - 1; l >= 0; --l) {
+    for (int l = lay.lt - 1; l >= (io.coarse_only ? 1 : 0); --l) {
         const MarchShape sh = P->shp_post[l];
         const std::vector<int> chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
@@ -448,6 +476,10 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
             if (post != POST_NONE) *norm_tiles = nt;
             std::swap(cur[l], other[l]);
         }
+    }
+    if (io.coarse_only) {
+        if (io.l1_out) *io.l1_out = cur[1];
+        return hipSuccess;
     }
     // the result must end in phi0
     if (lay.lt > 0 && io.post0 != POST_IR && cur[0].p != io.phi0) {
@@ -677,6 +709,7 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     P->singular = p->alpha == 0.0 && p->bc[0] != CCMG_BC_DIRICHLET && p->bc[1] != CCMG_BC_DIRICHLET &&
                   p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
     for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
+    P->shp_fused = shape_for(P->lay.lev[0].n);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
     if (e == hipSuccess)
@@ -804,6 +837,52 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             else P->shp_post[l] = bs;
         }
     }
+    // the fused finest launch (FP64 plans that use it)
+    if constexpr (std::is_same<T, double>::value) {
+        if (err == hipSuccess && fused_eligible(P)) {
+            MarchArgs<double> a{};
+            level_consts(P, 0, a);
+            a.f = d_f;
+            a.pf = pitch;
+            a.phi_in = d_phi;  // read only
+            a.pin = pitch;
+            a.phi_out = P->at<double>(lay.lev[0].b);
+            a.pout = lay.lev[0].pitch;
+            a.phi_mid = P->at<double>(lay.lev[0].c);
+            a.pmid = lay.lev[0].pitch;
+            a.ec = P->at<double>(lay.lev[1].a);
+            a.pc = lay.lev[1].pitch;
+            a.aux = P->at<double>(lay.lev[1].f);
+            a.paux = lay.lev[1].pitch;
+            a.partial = P->at<double>(lay.lev[1].fpart);
+            a.partial_norm = P->at<double>(lay.normpart);
+            const int n = lay.lev[0].n;
+            float best = 1e30f;
+            MarchShape bs = P->shp_fused;
+            for (int ty : {16, 32, 64, 128, 256}) {
+                if (ty > n && ty != 16) continue;
+                for (int wpb : {1, 2}) {
+                    const MarchShape sh{ty < n ? ty : n, wpb};
+                    int nt;
+                    err = launch_march<double>(a, 4, true, true, POST_FUSED, sh, s, &nt);  // warm-up
+                    if (err == hipSuccess) err = hipEventRecord(e0, s);
+                    for (int r = 0; r < reps && err == hipSuccess; ++r)
+                        err = launch_march<double>(a, 4, true, true, POST_FUSED, sh, s, &nt);
+                    if (err == hipSuccess) err = hipEventRecord(e1, s);
+                    if (err == hipSuccess) err = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                    if (err != hipSuccess) break;
+                    if (ms < best) {
+                        best = ms;
+                        bs = sh;
+                    }
+                }
+                if (err != hipSuccess) break;
+            }
+            P->shp_fused = bs;
+        }
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     return err;
@@ -872,7 +951,7 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     if (hipStreamSynchronize(P->stream) != hipSuccess) return CCMG_EHIP;
     P->tcollect();
     static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post", "mixed_finest_pre",
-                                                      "mixed_finest_post_ir"};
+                                                      "mixed_finest_post_ir", "finest_fused"};
     *count = KernelTimer::kKinds;
     for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
         std::memset(&out[k], 0, sizeof(out[k]));
@@ -923,6 +1002,117 @@ hipError_t copy_valid(double *dst, long pd, const double *src, long ps, int n, h
     if (dst == src) return hipSuccess;
     return hipMemcpy2DAsync(dst + pd + 1, sizeof(double) * pd, src + ps + 1, sizeof(double) * ps,
                             sizeof(double) * n, n, hipMemcpyDeviceToDevice, s);
+}
+
+// ---- FP64 solves with fused finest-level launches ----------------------------
+// The post-smoothing of cycle k and the pre-smoothing (and restriction) of
+// cycle k+1 touch the same finest-level data back to back, so one launch does
+// both (POST_FUSED): per cycle the finest level is read once instead of twice.
+// The norm of cycle k is taken inside that launch, after the post-smoothing;
+// its post-smoothed iterate is kept (phi_mid) whenever cycle k may be the last.
+// The arithmetic of every cell is that of the unfused cycle.
+
+struct FusedCtx {
+    Buf<double> cur;     // level-0 buffer the next level-0 launch reads
+    bool pre_done;       // the next cycle's pre-smoothing and level-1 rhs are done
+    bool first_zero;     // the first pre-smoothing starts from zero
+    int f1_count;        // partial sums of the level-1 rhs
+    Buf<double> res;     // where the last enqueued cycle's post-smoothed iterate is (p = null: not kept)
+    Buf<double> next;    // the pre-smoothed iterate of the following cycle (fused end)
+};
+
+// One V-cycle of the fused driver: [level-0 pre] + levels >= 1 + level-0 end
+// (fused or plain post) + stop test -> hist[slot].
+hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, long pf, Buf<double> A, int slot,
+                               bool end_fused, bool with_mid) {
+    const Layout &lay = P->lay;
+    hipStream_t s = P->stream;
+    const Buf<double> B{P->at<double>(lay.lev[0].b), lay.lev[0].pitch};
+    const Buf<double> C{P->at<double>(lay.lev[0].c), lay.lev[0].pitch};
+    auto other = [&](const Buf<double> &x) { return x.p == A.p ? B : A; };
+    const double nn = (double)lay.lev[0].n * lay.lev[0].n;
+    hipError_t e = hipSuccess;
+    int nt = 0;
+    if (!cx.pre_done) {
+        const Buf<double> out = other(cx.cur);
+        MarchArgs<double> a{};
+        level_consts(P, 0, a);
+        a.f = d_f;
+        a.pf = pf;
+        a.phi_in = cx.cur.p;
+        a.pin = cx.cur.pitch;
+        a.phi_out = out.p;
+        a.pout = out.pitch;
+        a.phi_shift = (!cx.first_zero && P->singular) ? P->scal() + S_PHIMEAN : nullptr;
+        a.skip = P->done();
+        a.aux = P->at<double>(lay.lev[1].f);
+        a.paux = lay.lev[1].pitch;
+        a.partial = P->at<double>(lay.lev[1].fpart);
+        const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? 2.0 : 3.0) + 0.25));
+        e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
+        P->tstop(ti);
+        if (e != hipSuccess) return e;
+        cx.f1_count = nt;
+        cx.cur = out;
+        cx.first_zero = false;
+    }
+    CycleIO<double> io;
+    io.f0 = d_f;
+    io.pf0 = pf;
+    io.phi0 = A.p;
+    io.pp0 = A.pitch;
+    io.phi0b = B.p;
+    io.pp0b = B.pitch;
+    io.skip = P->done();
+    io.coarse_only = true;
+    io.f1_count = cx.f1_count;
+    Buf<double> l1{nullptr, 0};
+    io.l1_out = &l1;
+    int dummy = 0;
+    e = enqueue_cycle<double>(P, io, &dummy);
+    if (e != hipSuccess) return e;
+
+    const Buf<double> out = other(cx.cur);
+    MarchArgs<double> a{};
+    level_consts(P, 0, a);
+    a.f = d_f;
+    a.pf = pf;
+    a.phi_in = cx.cur.p;
+    a.pin = cx.cur.pitch;
+    a.phi_out = out.p;
+    a.pout = out.pitch;
+    a.ec = l1.p;
+    a.pc = l1.pitch;
+    a.skip = P->done();
+    if (end_fused) {
+        a.phi_mid = with_mid ? C.p : nullptr;
+        a.pmid = C.pitch;
+        a.aux = P->at<double>(lay.lev[1].f);
+        a.paux = lay.lev[1].pitch;
+        a.partial = P->at<double>(lay.lev[1].fpart);
+        a.partial_norm = P->at<double>(lay.normpart);
+        const int ti = P->tstart(4, sizeof(double) * nn * (3.0 + 0.5 + (with_mid ? 1.0 : 0.0)));
+        e = launch_march<double>(a, 4, true, true, POST_FUSED, P->shp_fused, s, &nt);
+        P->tstop(ti);
+        if (e != hipSuccess) return e;
+        cx.f1_count = nt;
+        cx.pre_done = true;
+        cx.res = with_mid ? C : Buf<double>{nullptr, 0};
+        cx.next = out;
+        cx.cur = out;
+    } else {
+        a.partial = P->at<double>(lay.normpart);
+        const int ti = P->tstart(1, sizeof(double) * nn * 3.25);
+        e = launch_march<double>(a, 2, true, true, POST_NORM, P->shp_post[0], s, &nt);
+        P->tstop(ti);
+        if (e != hipSuccess) return e;
+        cx.pre_done = false;
+        cx.res = out;
+        cx.next = Buf<double>{nullptr, 0};
+        cx.cur = out;
+    }
+    return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0, P->scal() + S_F2,
+                            P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(), P->drho + slot, s);
 }
 }  // namespace
 
@@ -1014,15 +1204,38 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     double rho = rho0;
     // MIXED: where the iterate is after each step (steps queued past convergence do nothing)
     std::vector<MixedState> after(P->p.max_cycles + 2, st);
+    // FP64 with fused finest launches: the driver's state after each cycle
+    const bool fused = !mixed && fused_eligible(P);
+    const double keep = fused_keep_factor();
+    FusedCtx fx{Buf<double>{d_phi, pitch}, false, !use_guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
+    std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;
     } else if (P->p.max_cycles > 0) {
         const double *shift = P->singular ? scal + S_PHIMEAN : nullptr;
+        std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
+        rhos[0] = rho0;
+        int checked = 0;  // cycles whose residual the host has read
+        // residual of cycle j extrapolated from the last two that were read
+        auto predict = [&](int j) -> double {
+            const int m = checked;
+            if (m < 1 || !(rhos[m - 1] > 0.0)) return INFINITY;
+            return rhos[m] * std::pow(rhos[m] / rhos[m - 1], (double)(j - m));
+        };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
             hipError_t x;
             if (mixed) {
                 x = enqueue_mixed_step(P, d_f, pitch, st, P->done(), k);
                 after[k] = st;
+            } else if (fused) {
+                // the end of cycle k also pre-smooths cycle k+1 unless k is
+                // expected to be the last; its post-smoothed iterate is kept
+                // while k may be the last
+                const double pred = predict(k);
+                const bool end_fused = k < P->p.max_cycles && !(pred <= 0.5 * P->p.rtol);
+                const bool with_mid = !std::isfinite(pred) || pred <= keep * P->p.rtol;
+                x = enqueue_fused_cycle(P, fx, d_f, pitch, Buf<double>{d_phi, pitch}, k, end_fused, with_mid);
+                fafter[k] = fx;
             } else {
                 x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
             }
@@ -1033,8 +1246,6 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         // never waits for the host; if cycle k converges, k+1 runs as no-ops
         // (each launch still costs a dispatch).  When the last two residuals
         // predict that cycle k converges, k+1 is queued only after the check.
-        std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
-        rhos[0] = rho0;
         e = enqueue(1);
         int queued = 1;
         for (int k = 1; e == hipSuccess; ++k) {
@@ -1052,6 +1263,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             rho = P->hrho[k];  // written by the step's last kernel (host-mapped)
             R->history[k] = rho;
             rhos[k] = rho;
+            checked = k;
             cycles = k;
             if (!std::isfinite(rho)) {
                 status = CCMG_ENONFINITE;
@@ -1068,6 +1280,53 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             }
         }
         if (e != hipSuccess) return R->status = CCMG_EHIP;
+        if (fused && cycles > 0) {
+            const FusedCtx &fc = fafter[cycles];
+            if (fc.res.p) {
+                e = copy_valid(d_phi, pitch, fc.res.p, fc.res.pitch, n, s);
+            } else {
+                // the last cycle ended in a fused launch whose post-smoothed
+                // iterate was not kept (it was not expected to be the last):
+                // take the next cycle's pre-smoothed iterate (two more sweeps)
+                // with its own residual, and continue plainly if that is short
+                const int slot = std::min(cycles + 1, CCMG_HISTORY - 1);
+                e = copy_valid(d_phi, pitch, fc.next.p, fc.next.pitch, n, s);
+                if (e == hipSuccess) e = launch_set_int(P->done(), 1, 0, s);
+                MarchArgs<double> a{};
+                level_consts(P, 0, a);
+                a.f = d_f;
+                a.pf = pitch;
+                a.phi_in = d_phi;
+                a.pin = pitch;
+                a.partial = P->at<double>(lay.normpart);
+                int nt = 0;
+                if (e == hipSuccess) e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(n), s, &nt);
+                if (e == hipSuccess)
+                    e = launch_cycle_end(P->at<double>(lay.normpart), nt, n, P->singular ? 1 : 0, scal + S_F2,
+                                         P->p.rtol, P->hist() + slot, scal + S_PHIMEAN, P->done(), P->drho + slot, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e == hipSuccess) {
+                    rho = P->hrho[slot];
+                    if (!std::isfinite(rho)) status = CCMG_ENONFINITE;
+                    else if (rho <= P->p.rtol) status = CCMG_OK;
+                    else status = CCMG_NOT_CONVERGED;
+                }
+                for (int k = cycles + 1; e == hipSuccess && status == CCMG_NOT_CONVERGED && k <= P->p.max_cycles;
+                     ++k) {
+                    const int sl = std::min(k, CCMG_HISTORY - 1);
+                    e = launch_set_int(P->done(), 1, 0, s);
+                    if (e == hipSuccess) e = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, false, shift, true, sl);
+                    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                    if (e != hipSuccess) break;
+                    rho = P->hrho[sl];
+                    R->history[sl] = rho;
+                    cycles = k;
+                    if (!std::isfinite(rho)) status = CCMG_ENONFINITE;
+                    else if (rho <= P->p.rtol) status = CCMG_OK;
+                }
+            }
+            if (e != hipSuccess) return R->status = CCMG_EHIP;
+        }
     }
     if (mixed) {
         // the FP64 iterate of the last step that ran (or the guess / zero)

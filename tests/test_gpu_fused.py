@@ -1,0 +1,128 @@
+"""FP64 solves whose finest level runs the post-smoothing of one V-cycle and
+the pre-smoothing of the next in one launch: the same iterates, residual
+history and result as the unfused cycles, for every side type, plus the path
+where the last cycle's post-smoothed iterate was not kept."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import exact
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_1306_6883_amd")
+
+
+def dev_field(a):
+    n = a.shape[0] - 2
+    t = torch.zeros((n + 2, n + 2 + 5), dtype=torch.float64, device="cuda")
+    t[:, :n + 2] = torch.from_numpy(a).cuda()
+    return t
+
+
+def valid(t):
+    n = t.shape[0] - 2
+    return t[1:n + 1, 1:n + 1].cpu().numpy()
+
+
+class env:
+    def __init__(self, **kv):
+        self.kv = kv
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kv}
+        os.environ.update({k: str(v) for k, v in self.kv.items()})
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def solve(n, bc, fv, guess=None, **kw):
+    plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc), rtol=1e-10, **kw))
+    f = dev_field(oracle.embed(fv))
+    phi = dev_field(oracle.embed(guess) if guess is not None else oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, f, phi, use_guess=guess is not None)
+    return r, phi, plan
+
+
+@pytest.mark.parametrize("bc", ["DDDD", "NNDD", "DNPP", "PPDD", "PPPP", "NNNN"])
+@pytest.mark.parametrize("n", [64, 512])
+def test_fused_solve_matches_unfused(bc, n):
+    fv = W.fourier_modes(n, seed=4, count=16, kmax=8)
+    if not exact.is_singular(0.0, bc):
+        fv = fv + 0.3  # a mean, where the problem allows one
+    with env(CCMG_FUSED="0"):
+        r0, p0, _ = solve(n, bc, fv)
+    r1, p1, plan = solve(n, bc, fv)
+    assert r0.status == r1.status == cc.OK
+    assert r0.cycles == r1.cycles
+    a, b = valid(p0), valid(p1)
+    if exact.is_singular(0.0, bc):
+        # the unfused cycles shift phi by its mean between cycles: rounding only
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+        assert np.allclose(r0.history, r1.history, rtol=1e-4, atol=0)  # residuals near the FP64 floor
+    else:
+        assert np.array_equal(a, b)
+        # the norm's per-tile sums follow the tiles of a different launch
+        assert np.allclose(r0.history, r1.history, rtol=1e-12, atol=0)
+    cc.ccmg_plan_profile(plan, True)
+    phi = dev_field(oracle.field_zeros(n))
+    cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
+    stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+    cc.ccmg_plan_profile(plan, False)
+    assert stats["finest_fused"]["launches"] >= r1.cycles - 2
+    assert 1 <= stats["finest_pre"]["launches"] <= 2
+
+
+@pytest.mark.parametrize("bc", ["DDDD", "PPPP"])
+def test_fused_solve_with_guess_and_helmholtz(bc):
+    n = 256
+    fv = W.gaussian_random_field(n, seed=3)
+    fv -= fv.mean()
+    guess = 0.01 * np.random.default_rng(2).standard_normal((n, n))
+    for kw in ({}, {"alpha": 1.0, "beta": 0.5 / (n * n)}):
+        with env(CCMG_FUSED="0"):
+            r0, p0, _ = solve(n, bc, fv, guess, **kw)
+        r1, p1, _ = solve(n, bc, fv, guess, **kw)
+        assert r0.status == r1.status == cc.OK and r0.cycles == r1.cycles
+        a, b = valid(p0), valid(p1)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("bc", ["DDDD", "PPPP", "DNPP"])
+def test_fused_solve_when_last_iterate_was_not_kept(bc):
+    """With no post-smoothed iterate kept past the first cycles, the solve
+    returns the next cycle's pre-smoothed iterate, checked by its own residual."""
+    n = 512
+    fv = W.fourier_modes(n, seed=9, count=16, kmax=8)
+    with env(CCMG_FUSED_KEEP="0"):
+        r, p, _ = solve(n, bc, fv)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10
+    got = valid(p)
+    h = 1.0 / n
+    assert exact.relative_residual(got, fv, h, 0.0, -1.0, bc) <= 1e-10
+    r2, p2, _ = solve(n, bc, fv)
+    ref = valid(p2)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-9
+    if exact.is_singular(0.0, bc):
+        assert abs(got.mean()) < 1e-13 * np.abs(got).max()
+
+
+def test_fused_not_used_for_other_smoothing_counts():
+    n = 256
+    fv = W.fourier_modes(n, seed=1, count=8, kmax=4)
+    r, p, plan = solve(n, "DDDD", fv, nu1=1, nu2=3)
+    assert r.status == cc.OK
+    cc.ccmg_plan_profile(plan, True)
+    cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n)))
+    stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+    cc.ccmg_plan_profile(plan, False)
+    assert stats["finest_fused"]["launches"] == 0
