@@ -245,7 +245,7 @@ def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
 
 
 PMC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                           "march_finest_post_poisson4096_pmc.md")
+                           "march_finest_fused_poisson4096_pmc.md")
 
 
 def measured_traffic(kernel: str):

@@ -219,7 +219,7 @@ const ccmg_problem *ccmg::plan_problem(const ccmg_plan *P) { return &P->p; }
 
 namespace {
 // Tuning knobs, read at every solve: CCMG_FUSED=0 turns the fused launches
-// off; CCMG_FUSED_KEEP (default 1e4) is how far above the tolerance the
+// off; CCMG_FUSED_KEEP (default 100) is how far above the tolerance the
 // extrapolated residual of a cycle may be for its post-smoothed iterate to be
 // kept.
 bool fused_eligible(const ccmg_plan *P) {
@@ -229,9 +229,9 @@ bool fused_eligible(const ccmg_plan *P) {
 }
 double fused_keep_factor() {
     const char *e = std::getenv("CCMG_FUSED_KEEP");
-    if (!e) return 1e4;
+    if (!e) return 100.0;
     const double v = std::atof(e);
-    return v >= 0.0 ? v : 1e4;
+    return v >= 0.0 ? v : 100.0;
 }
 
 }  // namespace
@@ -1029,7 +1029,11 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
     hipStream_t s = P->stream;
     const Buf<double> B{P->at<double>(lay.lev[0].b), lay.lev[0].pitch};
     const Buf<double> C{P->at<double>(lay.lev[0].c), lay.lev[0].pitch};
-    auto other = [&](const Buf<double> &x) { return x.p == A.p ? B : A; };
+    // A (the caller's array) is written only by launches that produce a
+    // cycle's final iterate (the kept post-smoothed iterate, or a plain post),
+    // so a converged solve ends in A without a copy; intermediate iterates
+    // alternate between B and C
+    auto other = [&](const Buf<double> &x) { return x.p == B.p ? C : B; };
     const double nn = (double)lay.lev[0].n * lay.lev[0].n;
     hipError_t e = hipSuccess;
     int nt = 0;
@@ -1085,8 +1089,8 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
     a.pc = l1.pitch;
     a.skip = P->done();
     if (end_fused) {
-        a.phi_mid = with_mid ? C.p : nullptr;
-        a.pmid = C.pitch;
+        a.phi_mid = with_mid ? A.p : nullptr;  // the input is B or C here
+        a.pmid = A.pitch;
         a.aux = P->at<double>(lay.lev[1].f);
         a.paux = lay.lev[1].pitch;
         a.partial = P->at<double>(lay.lev[1].fpart);
@@ -1097,19 +1101,21 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
         if (e != hipSuccess) return e;
         cx.f1_count = nt;
         cx.pre_done = true;
-        cx.res = with_mid ? C : Buf<double>{nullptr, 0};
+        cx.res = with_mid ? A : Buf<double>{nullptr, 0};
         cx.next = out;
         cx.cur = out;
     } else {
+        a.phi_out = A.p;
+        a.pout = A.pitch;
         a.partial = P->at<double>(lay.normpart);
         const int ti = P->tstart(1, sizeof(double) * nn * 3.25);
         e = launch_march<double>(a, 2, true, true, POST_NORM, P->shp_post[0], s, &nt);
         P->tstop(ti);
         if (e != hipSuccess) return e;
         cx.pre_done = false;
-        cx.res = out;
+        cx.res = A;
         cx.next = Buf<double>{nullptr, 0};
-        cx.cur = out;
+        cx.cur = A;
     }
     return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0, P->scal() + S_F2,
                             P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(), P->drho + slot, s);
@@ -1216,10 +1222,12 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
         rhos[0] = rho0;
         int checked = 0;  // cycles whose residual the host has read
-        // residual of cycle j extrapolated from the last two that were read
+        // residual of cycle j extrapolated from the last two that were read;
+        // before two are known, a lower bound: no V-cycle here contracts the
+        // residual by more than 100x
         auto predict = [&](int j) -> double {
             const int m = checked;
-            if (m < 1 || !(rhos[m - 1] > 0.0)) return INFINITY;
+            if (m < 1 || !(rhos[m - 1] > 0.0)) return rhos[m] * std::pow(0.01, (double)(j - m));
             return rhos[m] * std::pow(rhos[m] / rhos[m - 1], (double)(j - m));
         };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
@@ -1232,7 +1240,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 // expected to be the last; its post-smoothed iterate is kept
                 // while k may be the last
                 const double pred = predict(k);
-                const bool end_fused = k < P->p.max_cycles && !(pred <= 0.5 * P->p.rtol);
+                const bool end_fused = k < P->p.max_cycles && !(pred <= 0.5 * P->p.rtol && checked >= 2);
                 const bool with_mid = !std::isfinite(pred) || pred <= keep * P->p.rtol;
                 x = enqueue_fused_cycle(P, fx, d_f, pitch, Buf<double>{d_phi, pitch}, k, end_fused, with_mid);
                 fafter[k] = fx;
