@@ -64,27 +64,32 @@ def _lib():
     if _lib_handle is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int)
-        lib.og_fill.argtypes = [ctypes.c_int, ip, dp]
-        lib.og_smooth.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                  ip, dp, dp, ctypes.c_int]
-        lib.og_residual.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ip, dp, dp, dp]
-        lib.og_restrict.argtypes = [ctypes.c_int, dp, dp]
-        lib.og_prolong_add.argtypes = [ctypes.c_int, ip, dp, dp]
-        lib.og_norm.argtypes = [ctypes.c_int, ctypes.c_double, dp]
-        lib.og_norm.restype = ctypes.c_double
-        lib.og_mean.argtypes = [ctypes.c_int, dp]
-        lib.og_mean.restype = ctypes.c_double
-        lib.og_vcycle.argtypes = [ctypes.POINTER(_Params), dp, dp]
-        lib.og_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
-                                 ctypes.POINTER(_Result)]
-        lib.og_smooth_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
-                                        ctypes.POINTER(_Result)]
-        _lib_handle = lib
+        _lib_handle = _load(_LIB)
     return _lib_handle
+
+
+def _load(path: str):
+    """Load a compiled oracle library and declare its entry points."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.og_fill.argtypes = [ctypes.c_int, ip, dp]
+    lib.og_smooth.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                              ip, dp, dp, ctypes.c_int]
+    lib.og_residual.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ip, dp, dp, dp]
+    lib.og_restrict.argtypes = [ctypes.c_int, dp, dp]
+    lib.og_prolong_add.argtypes = [ctypes.c_int, ip, dp, dp]
+    lib.og_norm.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+    lib.og_norm.restype = ctypes.c_double
+    lib.og_mean.argtypes = [ctypes.c_int, dp]
+    lib.og_mean.restype = ctypes.c_double
+    lib.og_vcycle.argtypes = [ctypes.POINTER(_Params), dp, dp]
+    lib.og_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
+                             ctypes.POINTER(_Result)]
+    lib.og_smooth_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
+                                    ctypes.POINTER(_Result)]
+    return lib
 
 
 def bc_codes(bc) -> tuple:

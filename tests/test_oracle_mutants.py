@@ -1,0 +1,99 @@
+"""The oracle's pins catch plausible mistakes (CPU): each mutant below plants
+one mistake in a copy of the C oracle (a wrong sign, index, weight, side
+rule, colour order or grid spacing), the copy is compiled and swapped in, and
+at least one pin of tests/test_oracle_pins.py must fail on it."""
+import importlib.util
+import os
+import shutil
+import subprocess
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ORACLE_DIR = os.path.dirname(oracle.__file__)
+
+
+def _pins():
+    spec = importlib.util.spec_from_file_location("oracle_pins", os.path.join(HERE, "test_oracle_pins.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+P = _pins()
+
+# name -> (text in mg_oracle.c, replacement); each text occurs exactly once
+MUTANTS = {
+    "relaxation_sign": ("(f[IDX(n, i, j)] + c * nb) / diag", "(f[IDX(n, i, j)] - c * nb) / diag"),
+    "dirichlet_ghost_sign": ("(bc[OG_XLO] == OG_DIRICHLET ? -lo : lo)", "(bc[OG_XLO] == OG_DIRICHLET ? lo : lo)"),
+    "neumann_ghost_sign": ("(bc[OG_YHI] == OG_DIRICHLET ? -hi : hi)", "(bc[OG_YHI] == OG_DIRICHLET ? -hi : -hi)"),
+    "periodic_wrap_side": ("bc[OG_YHI] == OG_PERIODIC ? lo :", "bc[OG_YHI] == OG_PERIODIC ? hi :"),
+    "residual_dropped_term": (" + (phi[IDX(n, i, j - 1)] - p)) * ih2;", ") * ih2;"),
+    "residual_sign": ("f[IDX(n, i, j)] - (alpha * p - beta * lap)", "f[IDX(n, i, j)] - (alpha * p + beta * lap)"),
+    "restriction_weight": ("0.25 * (fine[IDX(n, 2 * I, 2 * J)]", "0.5 * (fine[IDX(n, 2 * I, 2 * J)]"),
+    "restriction_index": ("fine[IDX(n, 2 * I + 1, 2 * J + 1)]", "fine[IDX(n, 2 * I + 1, 2 * J)]"),
+    "prolongation_slope_sign": ("double dx = a ? 0.25 : -0.25", "double dx = a ? -0.25 : 0.25"),
+    "prolongation_slope_axis": ("0.5 * (coarse[IDX(nc, I + 1, J)] - coarse[IDX(nc, I - 1, J)])",
+                                "0.5 * (coarse[IDX(nc, I, J + 1)] - coarse[IDX(nc, I, J - 1)])"),
+    "coarse_spacing": ("double h = p->h * (double)(1 << lev);", "double h = p->h;"),
+    "colour_order": ("relax_colour(n, h, alpha, beta, bc, phi, f, 0); /* red   */",
+                     "relax_colour(n, h, alpha, beta, bc, phi, f, 1); /* red   */"),
+}
+# Not a mutant: dropping the removal of each restricted right-hand side's mean
+# (singular problems) changes the iterates only by rounding -- the residual of
+# a compatible periodic problem has zero sum and restriction keeps sums, so the
+# removal only stops rounding drift (checked: 3e-16 relative at 64^2 and 256^2).
+
+# a compact set of pins (each a call with fixed arguments)
+BATTERY = [
+    (P.test_mg_converges_to_dense_solution, ("DDDD", (0.0, -1.0), 8)),
+    (P.test_mg_converges_to_dense_solution, ("NNNN", (0.0, -1.0), 8)),
+    (P.test_mg_converges_to_dense_solution, ("PPPP", (0.0, -1.0), 8)),
+    (P.test_mg_converges_to_dense_solution, ("DNPP", (1.0, 0.5 / 64), 8)),
+    (P.test_mg_converges_to_dense_solution, ("PPND", (0.0, -1.0), 8)),
+    (P.test_smoother_black_residual_zero, ("DNPP",)),
+    (P.test_restriction_conserves_and_keeps_constants, ()),
+    (P.test_prolongation_constants_and_linears, ()),
+    (P.test_residual_matches_assembled_matrix, ()),
+    (P.test_vcycle_convergence_factor_h_independent, ("PPPP",)),
+    (P.test_vcycle_convergence_factor_h_independent, ("DDDD",)),
+    (P.test_mg_matches_transform_solution_n128, ("PPPP",)),
+]
+
+
+def _build(src_text: str, out_dir: str) -> str:
+    shutil.copy(os.path.join(ORACLE_DIR, "mg_oracle.h"), out_dir)
+    src = os.path.join(out_dir, "mg_oracle.c")
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    lib = os.path.join(out_dir, "libmutant.so")
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-o", lib,
+                    src, "-lm"], check=True, cwd=out_dir, capture_output=True)
+    return lib
+
+
+def _failures(monkeypatch, lib_path):
+    monkeypatch.setattr(oracle, "_lib_handle", oracle._load(lib_path))
+    failed = []
+    for fn, args in BATTERY:
+        try:
+            fn(*args)
+        except Exception:  # an assertion, or a solve that stopped with an error
+            failed.append(f"{fn.__name__}{args}")
+    return failed
+
+
+def test_unmutated_copy_passes_the_battery(tmp_path, monkeypatch):
+    src = open(os.path.join(ORACLE_DIR, "mg_oracle.c")).read()
+    assert _failures(monkeypatch, _build(src, str(tmp_path))) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path, monkeypatch):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ORACLE_DIR, "mg_oracle.c")).read()
+    assert src.count(old) == 1, name
+    failed = _failures(monkeypatch, _build(src.replace(old, new), str(tmp_path)))
+    assert failed, f"no pin caught the mutant {name}"
