@@ -114,7 +114,12 @@ int ccmg_plan_destroy(ccmg_plan *plan);
  * until the result is known (the stop test needs it).  Singular problems
  * (alpha == 0, no Dirichlet side) are checked for compatibility and return
  * the zero-mean solution.  ||f|| == 0 gives phi = 0 and CCMG_OK.
- * `out` may be NULL. */
+ * `out` may be NULL.  FP64 plans with nu1 = nu2 = 2 and more than 32 cells
+ * per side run the finest level's post-smoothing of one cycle and
+ * pre-smoothing of the next in one launch (the same iterates; environment
+ * CCMG_FUSED=0 turns this off, CCMG_FUSED_KEEP sets how far above the
+ * tolerance the extrapolated residual may be for a cycle's own iterate to be
+ * kept, default 100). */
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 
@@ -233,14 +238,18 @@ int ccmg_solve_learned(ccmg_plan *plan, ccmg_net *net, const double *d_f, double
 
 /* ---- launch-shape autotuning.
  * Times every candidate tile shape (rows per wavefront band x wavefronts per
- * workgroup) of the two row-march launches of each level on the given data and
- * keeps the fastest for this plan.  d_f and d_phi are only read (finest level,
+ * workgroup, or the 2-D tile kernel below the finest level) of the two
+ * launches of each level, and of the fused finest launch, on the given data
+ * and keeps the fastest for this plan.  d_f and d_phi are only read (finest level,
  * same layout as ccmg_solve); blocks until done.  Optional: untuned plans use
  * a fixed size-based choice. */
 int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
 /* Set one launch shape by hand: kind 0 = the nu1 (restricting) launch of
  * `level`, 1 = the nu2 (prolongating) launch; ty even, >= 8 unless it covers
- * the level; 1 <= wpb <= 4.  Results do not depend on the shape. */
+ * the level; 1 <= wpb <= 4.  ty = 0 selects the 2-D LDS tile kernel instead
+ * of the row march (levels below the finest with at least 64 cells per side
+ * that are not in the one-workgroup tail).  Results do not depend on the
+ * shape. */
 int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
 /* The plan's launch shapes per level (arrays of max_levels entries). */
 int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, int *wpb_post,
@@ -253,7 +262,9 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  *   "finest_post": prolongation + nu2 relaxations (+ residual norm);
  * MIXED plans: "mixed_finest_pre" (the same in FP32) and "mixed_finest_post_ir"
  * (FP32 prolongation + relaxations, then the FP64 update of the iterate and
- * its FP64 residual, rounded to FP32 for the next step).
+ * its FP64 residual, rounded to FP32 for the next step); FP64 solves with
+ * fused launches: "finest_fused" (prolongation + 2 relaxations + residual
+ * norm [+ that iterate kept], then 2 relaxations + residual + restriction).
  * `bytes` is the algorithmic traffic of one launch: each valid cell of each
  * array the launch reads or writes, counted once (ghost cells and halo
  * re-reads excluded). */
