@@ -43,7 +43,12 @@ enum { CCMG_XLO = 0, CCMG_XHI = 1, CCMG_YLO = 2, CCMG_YHI = 3 };
  *   CCMG_MIXED: iterative refinement -- the FP64 residual of the FP64 iterate
  *               is rounded to FP32, FP32 V-cycles solve for the correction
  *               (2x2 bottom solve in FP64), the correction is added in FP64,
- *               and the stop test always uses the FP64 residual. */
+ *               and the stop test always uses the FP64 residual.  With
+ *               nu1 = nu2 = 2 a refinement step runs up to 3 FP32 V-cycles
+ *               from a zero correction (environment CCMG_MIXED_INNER, 1..8),
+ *               as many as the measured contraction says the tolerance
+ *               needs; the finest level's post-smoothing of one inner cycle
+ *               and pre-smoothing of the next share one launch. */
 enum { CCMG_FP64 = 0, CCMG_MIXED = 1 };
 
 /* Status codes */
@@ -264,7 +269,9 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  * (FP32 prolongation + relaxations, then the FP64 update of the iterate and
  * its FP64 residual, rounded to FP32 for the next step); FP64 solves with
  * fused launches: "finest_fused" (prolongation + 2 relaxations + residual
- * norm [+ that iterate kept], then 2 relaxations + residual + restriction).
+ * norm [+ that iterate kept], then 2 relaxations + residual + restriction);
+ * MIXED steps with several inner cycles: "mixed_finest_fused" (the same in
+ * FP32 between two inner cycles, without norm or kept iterate).
  * `bytes` is the algorithmic traffic of one launch: each valid cell of each
  * array the launch reads or writes, counted once (ghost cells and halo
  * re-reads excluded). */

@@ -19,9 +19,9 @@ enum Post {
     POST_IR = 4,        // (float launches) relaxed e -> phi64_out = phi64_in + e, FP64 residual
                         // of phi64_out -> r32 (+ sum r^2, sum phi64, sum r32 per tile)
     POST_R32 = 5,       // (double launches) residual -> r32 (+ the same three sums)
-    POST_FUSED = 6      // (double, finest level, NU = 4) the post-smoothing of one cycle and the
+    POST_FUSED = 6      // (finest level, NU = 4) the post-smoothing of one cycle and the
                         // pre-smoothing of the next in one launch: after the first two iterations
-                        // the residual norm (sum r^2, sum phi per tile -> partial_norm) and the
+                        // the residual norm (sum r^2, sum phi per tile -> partial_norm, if set) and the
                         // iterate (-> phi_mid, if set); after all four, RESTRICT as above
 };
 
@@ -94,6 +94,7 @@ hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolo
                         MarchShape shape, hipStream_t s, int *ntiles_out);
 // The fused finest-level launch (POST_FUSED; march_f64_fused.hip).
 hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
+hipError_t dispatch_fused(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
 // One march variant family with NU fused iterations; defined in march_impl.h and
 // instantiated per (T, NU) in the march_*.hip files.
 template <typename T, int NU>

@@ -10,10 +10,8 @@ template <typename T>
 hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post,
                         MarchShape shape, hipStream_t s, int *nt) {
     if (post == POST_FUSED) {
-        if constexpr (std::is_same<T, double>::value) {
-            if (nu == 4 && load_phi && prolong && shape.ty >= 2 && !(shape.ty & 1) && shape.wpb >= 1 && shape.wpb <= 4)
-                return dispatch_fused(a, shape, s, nt);
-        }
+        if (nu == 4 && load_phi && prolong && shape.ty >= 2 && !(shape.ty & 1) && shape.wpb >= 1 && shape.wpb <= 4)
+            return dispatch_fused(a, shape, s, nt);
         return hipErrorInvalidValue;
     }
     if (shape.ty == 0) return launch_tile<T>(a, nu, load_phi, prolong, post, s, nt);

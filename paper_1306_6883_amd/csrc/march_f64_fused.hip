@@ -1,9 +1,13 @@
-// The fused finest-level row march (double): post-smoothing of one V-cycle,
-// its residual norm, and the pre-smoothing and restriction of the next.
+// The fused finest-level row march: post-smoothing of one V-cycle, its
+// residual norm, and the pre-smoothing and restriction of the next (double:
+// plain solves; float: the inner cycles of a mixed-precision step).
 #include "march_impl.h"
 
 namespace ccmg {
 hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt) {
     return go<double, 4, true, true, POST_FUSED>(a, sh, s, nt);
+}
+hipError_t dispatch_fused(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt) {
+    return go<float, 4, true, true, POST_FUSED>(a, sh, s, nt);
 }
 }  // namespace ccmg

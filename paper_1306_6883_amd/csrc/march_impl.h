@@ -482,7 +482,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
         if (lane == 0) a.partial[tile] = s;
         if constexpr (FUSED) {
             const double s0 = wave_sum(accN0), s1 = wave_sum(accN1);
-            if (lane == 0) {
+            if (lane == 0 && a.partial_norm) {
                 a.partial_norm[2 * tile] = s0;
                 a.partial_norm[2 * tile + 1] = s1;
             }

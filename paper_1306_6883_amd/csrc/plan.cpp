@@ -153,15 +153,15 @@ MarchShape shape_for(int n) {
 
 // Events bracketing finest-level launches while profiling is on.
 struct KernelTimer {
-    static constexpr int kKinds = 5;
+    static constexpr int kKinds = 6;
     static constexpr int kPairs = 1024;
     bool on = false;
     std::vector<hipEvent_t> ev;          // 2 * kPairs
     int used = 0;
     int kind[kPairs];
     double bytes[kPairs];
-    int launches[kKinds] = {0, 0, 0, 0, 0};
-    double ms[kKinds] = {0, 0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0, 0};
+    int launches[kKinds] = {0, 0, 0, 0, 0, 0};
+    double ms[kKinds] = {0, 0, 0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0, 0, 0};
 };
 
 constexpr int kMaxLevels = 16;
@@ -171,6 +171,7 @@ struct ccmg_plan {
     KernelTimer timer;
     MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
+    MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
     double *drho = nullptr;   // ... its device address
     Layout lay;
@@ -226,6 +227,15 @@ bool fused_eligible(const ccmg_plan *P) {
     const char *e = std::getenv("CCMG_FUSED");
     const bool off = e && e[0] == '0';
     return !off && P->p.prec == CCMG_FP64 && P->lay.lt >= 1 && P->p.nu1 == 2 && P->p.nu2 == 2;
+}
+// Mixed-precision steps with several FP32 V-cycles per FP64 refinement: the
+// most inner cycles per step (CCMG_MIXED_INNER, default 3; 1 = one cycle per
+// step).  Needs the same cycle shape as the fused FP64 launch.
+int mixed_inner_max(const ccmg_plan *P) {
+    if (P->p.prec != CCMG_MIXED || P->lay.lt < 1 || P->p.nu1 != 2 || P->p.nu2 != 2) return 1;
+    const char *e = std::getenv("CCMG_MIXED_INNER");
+    const int v = e ? std::atoi(e) : 3;
+    return v < 1 ? 1 : (v > 8 ? 8 : v);
 }
 double fused_keep_factor() {
     const char *e = std::getenv("CCMG_FUSED_KEEP");
@@ -610,6 +620,117 @@ hipError_t enqueue_mixed_step(ccmg_plan *P, const double *d_f, long pf, MixedSta
                             skip ? P->drho + slot : nullptr, P->stream);
 }
 
+// A refinement step with m >= 2 FP32 V-cycles for A e = r32 (e from zero):
+// level-0 pre-smoothing of the first cycle, then m - 1 fused level-0
+// launches (post-smoothing of one inner cycle, pre-smoothing and restriction
+// of the next; no norm, nothing kept), levels >= 1 after each, and the last
+// cycle's post-smoothing with the FP64 update and residual (POST_IR).
+hipError_t enqueue_mixed_step_inner(ccmg_plan *P, const double *d_f, long pf, MixedState &st, const int *skip,
+                                   int slot, int m) {
+    const Layout &lay = P->lay;
+    hipStream_t s = P->stream;
+    const double nn = (double)lay.lev[0].n * lay.lev[0].n;
+    Buf<float> cur{P->at<float>(lay.lev[0].a), lay.lev[0].pitch};
+    Buf<float> oth{P->at<float>(lay.lev[0].b), lay.lev[0].pitch};
+    auto l0_args = [&](MarchArgs<float> &a) {
+        level_consts(P, 0, a);
+        a.f = st.r;
+        a.pf = st.pr;
+        if (P->singular) {  // the FP32 residual's mean (its per-tile sums) is removed as it is read
+            a.fmean_part = st.s3;
+            a.fmean_count = st.r_tiles;
+        }
+        a.skip = skip;
+    };
+    auto coarse = [&](int f1_count, Buf<float> &l1) -> hipError_t {
+        CycleIO<float> io;
+        io.f0 = st.r;
+        io.pf0 = st.pr;
+        io.phi0 = cur.p;
+        io.pp0 = cur.pitch;
+        io.phi0b = oth.p;
+        io.pp0b = oth.pitch;
+        io.skip = skip;
+        io.coarse_only = true;
+        io.f1_count = f1_count;
+        io.l1_out = &l1;
+        int dummy = 0;
+        return enqueue_cycle<float>(P, io, &dummy);
+    };
+    int nt = 0;
+    MarchArgs<float> a{};
+    l0_args(a);
+    a.phi_in = cur.p;
+    a.pin = cur.pitch;
+    a.phi_out = cur.p;  // from zero: nothing is read
+    a.pout = cur.pitch;
+    a.aux = P->at<float>(lay.lev[1].f);
+    a.paux = lay.lev[1].pitch;
+    a.partial = P->at<double>(lay.lev[1].fpart);
+    int ti = P->tstart(2, sizeof(float) * nn * 2.25);
+    hipError_t e = launch_march<float>(a, 2, false, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
+    P->tstop(ti);
+    Buf<float> l1{nullptr, 0};
+    if (e == hipSuccess) e = coarse(nt, l1);
+    for (int i = 2; i <= m && e == hipSuccess; ++i) {
+        MarchArgs<float> b{};
+        l0_args(b);
+        b.phi_in = cur.p;
+        b.pin = cur.pitch;
+        b.phi_out = oth.p;
+        b.pout = oth.pitch;
+        b.ec = l1.p;
+        b.pc = l1.pitch;
+        b.aux = P->at<float>(lay.lev[1].f);
+        b.paux = lay.lev[1].pitch;
+        b.partial = P->at<double>(lay.lev[1].fpart);
+        ti = P->tstart(5, sizeof(float) * nn * 3.5);
+        e = launch_march<float>(b, 4, true, true, POST_FUSED, P->shp_fused32, s, &nt);
+        P->tstop(ti);
+        std::swap(cur, oth);
+        if (e == hipSuccess) e = coarse(nt, l1);
+    }
+    if (e != hipSuccess) return e;
+    // the last inner cycle's post-smoothing, the FP64 update and the FP64 residual
+    MarchArgs<float> c{};
+    l0_args(c);
+    c.phi_in = cur.p;
+    c.pin = cur.pitch;
+    c.phi_out = oth.p;  // not written: POST_IR stores the FP64 iterate
+    c.pout = oth.pitch;
+    c.ec = l1.p;
+    c.pc = l1.pitch;
+    c.q_in = st.q;
+    c.pq_in = st.pq;
+    c.q_out = st.qo;
+    c.pq_out = st.pqo;
+    c.g = d_f;
+    c.pg = pf;
+    c.r_out = st.ro;
+    c.pr = st.pr;
+    c.q_zero = st.q_zero ? 1 : 0;
+    c.phi_shift = P->singular ? P->scal() + S_PHIMEAN : nullptr;
+    c.partial = P->at<double>(lay.normpart);
+    c.partial3 = st.s3o;
+    const double h = lay.lev[0].h;
+    c.alpha64 = P->p.alpha;
+    c.beta64 = P->p.beta;
+    c.ih2_64 = 1.0 / (h * h);
+    ti = P->tstart(3, sizeof(float) * nn * 3.25 + nn * (3.0 * sizeof(double) + sizeof(float)));
+    e = launch_march<float>(c, 2, true, true, POST_IR, P->shp_post[0], s, &nt);
+    P->tstop(ti);
+    if (e != hipSuccess) return e;
+    std::swap(st.q, st.qo);
+    std::swap(st.pq, st.pqo);
+    std::swap(st.r, st.ro);
+    std::swap(st.s3, st.s3o);
+    st.r_tiles = nt;
+    st.q_zero = false;
+    return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0, P->scal() + S_F2,
+                            P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, skip ? P->done() : nullptr,
+                            skip ? P->drho + slot : nullptr, s);
+}
+
 int check_pitch(const ccmg_plan *P, int level, ptrdiff_t pitch) {
     if (level < 0 || level >= P->lay.L) return CCMG_EINVAL;
     if (pitch < (ptrdiff_t)(P->lay.lev[level].n + 2)) return CCMG_EINVAL;
@@ -710,6 +831,7 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
                   p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
     for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
     P->shp_fused = shape_for(P->lay.lev[0].n);
+    P->shp_fused32 = shape_for(P->lay.lev[0].n);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
     if (e == hipSuccess)
@@ -837,51 +959,59 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             else P->shp_post[l] = bs;
         }
     }
-    // the fused finest launch (FP64 plans that use it)
-    if constexpr (std::is_same<T, double>::value) {
-        if (err == hipSuccess && fused_eligible(P)) {
-            MarchArgs<double> a{};
-            level_consts(P, 0, a);
-            a.f = d_f;
+    // the fused finest launch (FP64 plans that use it; MIXED plans with
+    // several inner cycles per step, in FP32 without norm or kept iterate)
+    const bool tune_fused = f64 ? fused_eligible(P) : mixed_inner_max(P) > 1;
+    if (err == hipSuccess && tune_fused) {
+        MarchArgs<T> a{};
+        level_consts(P, 0, a);
+        if (f64) {
+            a.f = reinterpret_cast<const T *>(d_f);
             a.pf = pitch;
-            a.phi_in = d_phi;  // read only
+            a.phi_in = reinterpret_cast<T *>(d_phi);  // read only
             a.pin = pitch;
-            a.phi_out = P->at<double>(lay.lev[0].b);
-            a.pout = lay.lev[0].pitch;
-            a.phi_mid = P->at<double>(lay.lev[0].c);
+            a.phi_mid = P->at<T>(lay.lev[0].c);
             a.pmid = lay.lev[0].pitch;
-            a.ec = P->at<double>(lay.lev[1].a);
-            a.pc = lay.lev[1].pitch;
-            a.aux = P->at<double>(lay.lev[1].f);
-            a.paux = lay.lev[1].pitch;
-            a.partial = P->at<double>(lay.lev[1].fpart);
             a.partial_norm = P->at<double>(lay.normpart);
-            const int n = lay.lev[0].n;
-            float best = 1e30f;
-            MarchShape bs = P->shp_fused;
-            for (int ty : {16, 32, 64, 128, 256}) {
-                if (ty > n && ty != 16) continue;
-                for (int wpb : {1, 2}) {
-                    const MarchShape sh{ty < n ? ty : n, wpb};
-                    int nt;
-                    err = launch_march<double>(a, 4, true, true, POST_FUSED, sh, s, &nt);  // warm-up
-                    if (err == hipSuccess) err = hipEventRecord(e0, s);
-                    for (int r = 0; r < reps && err == hipSuccess; ++r)
-                        err = launch_march<double>(a, 4, true, true, POST_FUSED, sh, s, &nt);
-                    if (err == hipSuccess) err = hipEventRecord(e1, s);
-                    if (err == hipSuccess) err = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-                    if (err != hipSuccess) break;
-                    if (ms < best) {
-                        best = ms;
-                        bs = sh;
-                    }
-                }
-                if (err != hipSuccess) break;
-            }
-            P->shp_fused = bs;
+        } else {
+            a.f = P->at<T>(lay.lev[0].f);
+            a.pf = lay.lev[0].pitch;
+            a.phi_in = P->at<T>(lay.lev[0].a);
+            a.pin = lay.lev[0].pitch;
         }
+        a.phi_out = P->at<T>(lay.lev[0].b);
+        a.pout = lay.lev[0].pitch;
+        a.ec = P->at<T>(lay.lev[1].a);
+        a.pc = lay.lev[1].pitch;
+        a.aux = P->at<T>(lay.lev[1].f);
+        a.paux = lay.lev[1].pitch;
+        a.partial = P->at<double>(lay.lev[1].fpart);
+        const int n = lay.lev[0].n;
+        float best = 1e30f;
+        MarchShape bs = f64 ? P->shp_fused : P->shp_fused32;
+        for (int ty : {16, 32, 64, 128, 256}) {
+            if (ty > n && ty != 16) continue;
+            for (int wpb : {1, 2}) {
+                const MarchShape sh{ty < n ? ty : n, wpb};
+                int nt;
+                err = launch_march<T>(a, 4, true, true, POST_FUSED, sh, s, &nt);  // warm-up
+                if (err == hipSuccess) err = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && err == hipSuccess; ++r)
+                    err = launch_march<T>(a, 4, true, true, POST_FUSED, sh, s, &nt);
+                if (err == hipSuccess) err = hipEventRecord(e1, s);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (err != hipSuccess) break;
+                if (ms < best) {
+                    best = ms;
+                    bs = sh;
+                }
+            }
+            if (err != hipSuccess) break;
+        }
+        if (f64) P->shp_fused = bs;
+        else P->shp_fused32 = bs;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -951,7 +1081,8 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     if (hipStreamSynchronize(P->stream) != hipSuccess) return CCMG_EHIP;
     P->tcollect();
     static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post", "mixed_finest_pre",
-                                                      "mixed_finest_post_ir", "finest_fused"};
+                                                      "mixed_finest_post_ir", "finest_fused",
+                                                      "mixed_finest_fused"};
     *count = KernelTimer::kKinds;
     for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
         std::memset(&out[k], 0, sizeof(out[k]));
@@ -1210,6 +1341,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     double rho = rho0;
     // MIXED: where the iterate is after each step (steps queued past convergence do nothing)
     std::vector<MixedState> after(P->p.max_cycles + 2, st);
+    std::vector<int> inner_used(P->p.max_cycles + 2, 1);  // ... and its FP32 V-cycles
     // FP64 with fused finest launches: the driver's state after each cycle
     const bool fused = !mixed && fused_eligible(P);
     const double keep = fused_keep_factor();
@@ -1222,6 +1354,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
         rhos[0] = rho0;
         int checked = 0;  // cycles whose residual the host has read
+        const int inner_max = mixed ? mixed_inner_max(P) : 1;
+        std::vector<int> &inner = inner_used;
         // residual of cycle j extrapolated from the last two that were read;
         // before two are known, a lower bound: no V-cycle here contracts the
         // residual by more than 100x
@@ -1230,10 +1364,35 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             if (m < 1 || !(rhos[m - 1] > 0.0)) return rhos[m] * std::pow(0.01, (double)(j - m));
             return rhos[m] * std::pow(rhos[m] / rhos[m - 1], (double)(j - m));
         };
+        // MIXED with several FP32 cycles per step: the per-cycle contraction of
+        // the last step read (0.1 before one is known), the residual it
+        // predicts at the start of step j, and the inner cycles that step j
+        // needs to reach the tolerance (at most inner_max)
+        auto mixed_rate = [&]() -> double {
+            const int m = checked;
+            if (m < 1 || !(rhos[m - 1] > 0.0) || !(rhos[m] > 0.0)) return 0.1;
+            const double r = std::pow(rhos[m] / rhos[m - 1], 1.0 / inner[m]);
+            return (r > 0.0 && r < 0.9) ? r : 0.9;
+        };
+        auto mixed_pred = [&](int j) -> double {  // residual after step j - 1
+            const double rate = mixed_rate();
+            double r = rhos[checked];
+            for (int i = checked + 1; i < j; ++i) r *= std::pow(rate, inner[i]);
+            return r;
+        };
+        auto inner_for = [&](int j) -> int {
+            if (inner_max <= 1) return 1;
+            const double r = mixed_pred(j);
+            if (!(r > P->p.rtol)) return 1;
+            const double need = std::log(P->p.rtol / r) / std::log(mixed_rate());
+            return std::max(1, std::min(inner_max, (int)std::ceil(need)));
+        };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
             hipError_t x;
             if (mixed) {
-                x = enqueue_mixed_step(P, d_f, pitch, st, P->done(), k);
+                inner[k] = inner_for(k);
+                x = inner[k] >= 2 ? enqueue_mixed_step_inner(P, d_f, pitch, st, P->done(), k, inner[k])
+                                  : enqueue_mixed_step(P, d_f, pitch, st, P->done(), k);
                 after[k] = st;
             } else if (fused) {
                 // the end of cycle k also pre-smooths cycle k+1 unless k is
@@ -1259,7 +1418,9 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         for (int k = 1; e == hipSuccess; ++k) {
             if (queued == k && k < P->p.max_cycles) {
                 const bool likely_last =
-                    k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol;
+                    (mixed && inner_max > 1)
+                        ? (k >= 2 && mixed_pred(k + 1) <= 0.5 * P->p.rtol)
+                        : (k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol);
                 if (!likely_last) {
                     e = enqueue(k + 1);
                     queued = k + 1;
@@ -1342,7 +1503,9 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         if (fin.q_zero) e = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
         else e = copy_valid(d_phi, pitch, fin.q, fin.pq, n, s);
         if (e != hipSuccess) return R->status = CCMG_EHIP;
-        R->inner_cycles = cycles;
+        int total = 0;
+        for (int k = 1; k <= cycles; ++k) total += inner_used[k];
+        R->inner_cycles = total;
     }
     // output: zero-mean representative for singular problems, ghost cells filled
     e = launch_fill_ghosts_f64(d_phi, pitch, n, P->p.bc, P->singular ? scal + S_PHIMEAN : nullptr, s);

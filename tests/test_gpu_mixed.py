@@ -149,3 +149,65 @@ def test_mixed_tile_kernel_matches_row_march(bc):
         assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
     else:
         assert np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("bc", ["PPPP", "DDDD", "DNPP"])
+@pytest.mark.parametrize("m", [2, 3])
+def test_mixed_step_with_inner_cycles_matches_oracle(bc, m, monkeypatch):
+    """A refinement step of m FP32 V-cycles from a zero correction: from
+    phi = 0 the first step gives m oracle V-cycles for A e = f from zero, to
+    FP32 rounding of the correction."""
+    n = 256
+    h = 1.0 / n
+    sing = exact.is_singular(0.0, bc)
+    fv = np.random.default_rng(41).standard_normal((n, n))
+    if sing:
+        fv -= fv.mean()
+    monkeypatch.setenv("CCMG_MIXED_INNER", str(m))
+    plan = mixed_plan(n, bc, max_cycles=1, rtol=1e-14)  # the tolerance asks for more than m cycles
+    d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, d_f, d_phi)
+    assert r.status == cc.NOT_CONVERGED and r.cycles == 1 and r.inner_cycles == m
+    ref = oracle.field_zeros(n)
+    for _ in range(m):
+        oracle.vcycle(oracle.Problem(n=n, h=h, bc=bc), ref, oracle.embed(fv))
+    got, want = oracle.interior(host(d_phi)), oracle.interior(ref)
+    if sing:
+        got, want = got - got.mean(), want - want.mean()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("bc", ["PPPP", "DDDD", "NNNN", "DNPP"])
+def test_mixed_inner_cycles_against_one_cycle_steps(bc, monkeypatch):
+    """Several FP32 cycles per refinement step reach the same FP64 tolerance
+    and the same solution as one cycle per step, in fewer steps and about the
+    same number of FP32 cycles; the fused launch joins the inner cycles."""
+    n = 1024
+    h = 1.0 / n
+    sing = exact.is_singular(0.0, bc)
+    fv = W.gaussian_random_field(n, seed=5)
+    if sing:
+        fv -= fv.mean()
+    outs = {}
+    for m in ("1", "3"):
+        monkeypatch.setenv("CCMG_MIXED_INNER", m)
+        plan = mixed_plan(n, bc)
+        d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
+        r = cc.ccmg_solve(plan, d_f, d_phi)
+        assert r.status == cc.OK and r.rel_resid <= 1e-10
+        got = oracle.interior(host(d_phi))
+        assert exact.relative_residual(got, fv, h, 0.0, -1.0, bc) <= 1.5e-10
+        cc.ccmg_plan_profile(plan, True)
+        cc.ccmg_solve(plan, d_f, dev_field(oracle.field_zeros(n)))
+        stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+        cc.ccmg_plan_profile(plan, False)
+        outs[m] = (r, got, stats)
+    (r1, g1, s1), (r3, g3, s3) = outs["1"], outs["3"]
+    assert r1.inner_cycles == r1.cycles and s1["mixed_finest_fused"]["launches"] == 0
+    assert r3.cycles < r1.cycles
+    assert r3.inner_cycles <= r1.inner_cycles + 3
+    assert s3["mixed_finest_fused"]["launches"] >= r3.inner_cycles - r3.cycles
+    assert np.linalg.norm(g3 - g1) / np.linalg.norm(g1) < 1e-9
+    if sing:
+        assert abs(g3.mean()) < 1e-13 * np.abs(g3).max()
