@@ -97,7 +97,8 @@ def time_form(cc, torch, prob, fv, steps, warmup):
     dt, res, _ = run_solves(cc, torch, plan, f, phi, steps)
     assert all(r.status == cc.OK and r.rel_resid <= prob.rtol for r in res)
     _, _, stats = run_solves(cc, torch, plan, f, phi, max(2, steps // 2), profile=True)
-    out = dict(ms=1e3 * dt / steps, cycles=res[-1].cycles, rel_resid=res[-1].rel_resid,
+    out = dict(ms=1e3 * dt / steps, cycles=res[-1].cycles, inner_cycles=res[-1].inner_cycles,
+               rel_resid=res[-1].rel_resid,
                kernels=[dict(name=k["name"], avg_ms=round(k["ms"] / k["launches"], 5),
                              gbs=round(k["bytes"] / k["launches"] / (k["ms"] / k["launches"] * 1e-3) / 1e9, 1))
                         for k in stats if k["launches"] > 0])

@@ -53,8 +53,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const MarchArgs<T> a) {
     T fsub = T(0);
     if (a.fmean_part) {
         const int cnt = a.fmean_count_ptr ? *a.fmean_count_ptr : a.fmean_count;
+        // every 64th partial per lane in turn, loaded eight at a time
         double s = 0.0;
-        for (int i = tid & 63; i < cnt; i += 64) s += a.fmean_part[i];
+        int i = tid & 63;
+        for (; i + 7 * 64 < cnt; i += 8 * 64) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = a.fmean_part[i + 64 * k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
+        for (; i < cnt; i += 64) s += a.fmean_part[i];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
         fsub = T(s / ((double)n * (double)n));

@@ -67,7 +67,18 @@ __global__ __launch_bounds__(kRed) void k_cycle_end(const double *p, int count, 
     __shared__ double red[4];
     if (done && *done) return;  // uniform
     double s0 = 0.0, s1 = 0.0;
-    for (int i = threadIdx.x; i < count; i += kRed) {
+    int i = threadIdx.x;
+    for (; i + 3 * kRed < count; i += 4 * kRed) {  // four pairs in flight, added in order
+        double2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const double2 *>(p + 2 * (i + k * kRed));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s0 += v[k].x;
+            s1 += v[k].y;
+        }
+    }
+    for (; i < count; i += kRed) {
         s0 += p[2 * i];
         s1 += p[2 * i + 1];
     }
