@@ -67,20 +67,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Total of `count` partial sums, formed in a fixed order (deterministic):
 // each lane adds every 64th value in turn, then the lanes are combined.  The
-// values are loaded eight at a time before they are added (the same order),
-// so a few thousand partials cost a few memory round trips, not one per 64.
+// values are loaded 16 at a time (predicated) before they are added in that
+// order, so a few thousand partials cost a few memory round trips, not one
+// per 64.
 __device__ __forceinline__ double sum_partials(const double *p, int count) {
     const int lane = threadIdx.x & 63;
+    constexpr int B = 16;
     double s = 0.0;
-    int i = lane;
-    for (; i + 7 * 64 < count; i += 8 * 64) {
-        double v[8];
+    for (int i = lane; i < count; i += B * 64) {
+        double v[B];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = p[i + 64 * k];
+        for (int k = 0; k < B; ++k) v[k] = i + 64 * k < count ? p[i + 64 * k] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += v[k];
+        for (int k = 0; k < B; ++k)
+            if (i + 64 * k < count) s += v[k];
     }
-    for (; i < count; i += 64) s += p[i];
     return wave_sum(s);
 }
 

@@ -50,24 +50,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const MarchArgs<T> a) {
     const T sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T syh = a.bc[CCMG_YHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
-    T fsub = T(0);
-    if (a.fmean_part) {
-        const int cnt = a.fmean_count_ptr ? *a.fmean_count_ptr : a.fmean_count;
-        // every 64th partial per lane in turn, loaded eight at a time
-        double s = 0.0;
-        int i = tid & 63;
-        for (; i + 7 * 64 < cnt; i += 8 * 64) {
-            double v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = a.fmean_part[i + 64 * k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s += v[k];
-        }
-        for (; i < cnt; i += 64) s += a.fmean_part[i];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        fsub = T(s / ((double)n * (double)n));
-    }
     // global coordinate of local index l (axis origin o); -1 when outside a
     // non-periodic domain
     auto gco = [&](int o, int l, bool per) -> int {
@@ -76,31 +58,78 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const MarchArgs<T> a) {
         return (g < 0 || g > nm) ? -1 : g;
     };
 
-    // 1. load f (minus the mean shift) and phi (or zero) with the halo
-    for (int k = tid; k < R * R; k += kTileThreads) {
-        const int lj = k / R, li = k - lj * R;
-        const int gx = gco(X0, li, px), gy = gco(Y0, lj, py);
-        T fval = T(0), pval = T(0);
-        if (gx >= 0 && gy >= 0) {
-            fval = a.f[(long)(gy + 1) * a.pf + 1 + gx];
-            if (a.fmean_part) fval -= fsub;
-            if constexpr (LOADPHI) pval = a.phi_in[(long)(gy + 1) * a.pin + 1 + gx];
+    // 1. every global load of the block is issued before the first is used
+    // (one memory round trip): f and phi (or zero) with the halo, the coarse
+    // correction, then the partial sums of f's mean
+    constexpr int NL = (R * R + kTileThreads - 1) / kTileThreads;
+    constexpr int NC = PROLONG ? (RC * RC + kTileThreads - 1) / kTileThreads : 1;
+    T fr[NL], pr[NL], cr[NC];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int k = tid + q * kTileThreads;
+        fr[q] = pr[q] = T(0);
+        if (k < R * R) {
+            const int lj = k / R, li = k - lj * R;
+            const int gx = gco(X0, li, px), gy = gco(Y0, lj, py);
+            if (gx >= 0 && gy >= 0) {
+                fr[q] = a.f[(long)(gy + 1) * a.pf + 1 + gx];
+                if constexpr (LOADPHI) pr[q] = a.phi_in[(long)(gy + 1) * a.pin + 1 + gx];
+            }
         }
-        fv[lj][li] = fval;
-        u[lj][li] = pval;
+    }
+    // coarse cells covering the block and its halo, one more for the slopes
+    const int CX0 = ((X0 - H) >> 1) - 1, CY0 = ((Y0 - H) >> 1) - 1;
+    if constexpr (PROLONG) {
+        const int ncm = (n >> 1) - 1;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int k = tid + q * kTileThreads;
+            cr[q] = T(0);
+            if (k < RC * RC) {
+                const int cj = k / RC, ci = k - cj * RC;
+                int I = CX0 + ci, J = CY0 + cj;
+                if (px) I &= ncm;
+                if (py) J &= ncm;
+                if (I >= 0 && I <= ncm && J >= 0 && J <= ncm) cr[q] = a.ec[(long)(J + 1) * a.pc + 1 + I];
+            }
+        }
+    }
+    T fsub = T(0);
+    if (a.fmean_part) {
+        const int cnt = a.fmean_count_ptr ? *a.fmean_count_ptr : a.fmean_count;
+        // every 64th partial per lane in turn, loaded 16 at a time (predicated)
+        double s = 0.0;
+        for (int i = tid & 63; i < cnt; i += 16 * 64) {
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = i + 64 * k < cnt ? a.fmean_part[i + 64 * k] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (i + 64 * k < cnt) s += v[k];
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+        fsub = T(s / ((double)n * (double)n));
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int k = tid + q * kTileThreads;
+        if (k < R * R) {
+            const int lj = k / R, li = k - lj * R;
+            T fval = fr[q];
+            if (a.fmean_part && gco(X0, li, px) >= 0 && gco(Y0, lj, py) >= 0) fval -= fsub;
+            fv[lj][li] = fval;
+            u[lj][li] = pr[q];
+        }
     }
     if constexpr (PROLONG) {
-        // coarse cells covering the block and its halo, one more for the slopes
-        const int nc = n >> 1, ncm = nc - 1;
-        const int CX0 = ((X0 - H) >> 1) - 1, CY0 = ((Y0 - H) >> 1) - 1;
-        for (int k = tid; k < RC * RC; k += kTileThreads) {
-            const int cj = k / RC, ci = k - cj * RC;
-            int I = CX0 + ci, J = CY0 + cj;
-            T v = T(0);
-            if (px) I &= ncm;
-            if (py) J &= ncm;
-            if (I >= 0 && I <= ncm && J >= 0 && J <= ncm) v = a.ec[(long)(J + 1) * a.pc + 1 + I];
-            ec[cj][ci] = v;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int k = tid + q * kTileThreads;
+            if (k < RC * RC) {
+                const int cj = k / RC, ci = k - cj * RC;
+                ec[cj][ci] = cr[q];
+            }
         }
         __syncthreads();
         for (int k = tid; k < R * R; k += kTileThreads) {
