@@ -44,11 +44,13 @@ enum { CCMG_XLO = 0, CCMG_XHI = 1, CCMG_YLO = 2, CCMG_YHI = 3 };
  *               is rounded to FP32, FP32 V-cycles solve for the correction
  *               (2x2 bottom solve in FP64), the correction is added in FP64,
  *               and the stop test always uses the FP64 residual.  With
- *               nu1 = nu2 = 2 a refinement step runs up to 3 FP32 V-cycles
- *               from a zero correction (environment CCMG_MIXED_INNER, 1..8),
- *               as many as the measured contraction says the tolerance
- *               needs; the finest level's post-smoothing of one inner cycle
- *               and pre-smoothing of the next share one launch. */
+ *               nu1 = nu2 = 2 a refinement step runs several FP32 V-cycles
+ *               from a zero correction: the first step 2, later steps as
+ *               many as the contraction measured so far says the tolerance
+ *               needs, at most 3 (environment CCMG_MIXED_INNER, 1..8; one
+ *               more when that is expected to end the solve); the finest
+ *               level's post-smoothing of one inner cycle and pre-smoothing
+ *               of the next share one launch. */
 enum { CCMG_FP64 = 0, CCMG_MIXED = 1 };
 
 /* Status codes */

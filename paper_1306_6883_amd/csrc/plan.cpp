@@ -230,7 +230,11 @@ bool fused_eligible(const ccmg_plan *P) {
 }
 // Mixed-precision steps with several FP32 V-cycles per FP64 refinement: the
 // most inner cycles per step (CCMG_MIXED_INNER, default 3; 1 = one cycle per
-// step).  Needs the same cycle shape as the fused FP64 launch.
+// step; one more is allowed when it is expected to end the solve).  More
+// cycles per step do not pay on ill-conditioned problems: the FP32 residual
+// of a smooth correction loses about log10(kappa) of its 7 digits, so a step
+// cannot reduce the FP64 residual by much more than about 1e-4 there (seen on
+// 4096^2 Poisson).  Needs the same cycle shape as the fused FP64 launch.
 int mixed_inner_max(const ccmg_plan *P) {
     if (P->p.prec != CCMG_MIXED || P->lay.lt < 1 || P->p.nu1 != 2 || P->p.nu2 != 2) return 1;
     const char *e = std::getenv("CCMG_MIXED_INNER");
@@ -1365,9 +1369,12 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             return rhos[m] * std::pow(rhos[m] / rhos[m - 1], (double)(j - m));
         };
         // MIXED with several FP32 cycles per step: the per-cycle contraction of
-        // the last step read (0.1 before one is known), the residual it
-        // predicts at the start of step j, and the inner cycles that step j
-        // needs to reach the tolerance (at most inner_max)
+        // the last step read, the residual it predicts at the start of step j,
+        // and the inner cycles that step j needs to reach the tolerance (at
+        // most inner_max).  The first step runs 2 cycles and step 2 is queued
+        // only once its residual is known: contraction rates range from about
+        // 0.1 (Poisson) to below 1e-6 (strongly diagonal Helmholtz), and a
+        // blind guess either way costs whole cycles.
         auto mixed_rate = [&]() -> double {
             const int m = checked;
             if (m < 1 || !(rhos[m - 1] > 0.0) || !(rhos[m] > 0.0)) return 0.1;
@@ -1382,10 +1389,12 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         };
         auto inner_for = [&](int j) -> int {
             if (inner_max <= 1) return 1;
+            if (j == 1 || checked == 0) return std::min(2, inner_max);
             const double r = mixed_pred(j);
             if (!(r > P->p.rtol)) return 1;
-            const double need = std::log(P->p.rtol / r) / std::log(mixed_rate());
-            return std::max(1, std::min(inner_max, (int)std::ceil(need)));
+            const int need = (int)std::ceil(std::log(P->p.rtol / r) / std::log(mixed_rate()));
+            if (need == inner_max + 1) return need;  // one more cycle than the cap ends the solve
+            return std::max(1, std::min(inner_max, need));
         };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
             hipError_t x;
@@ -1417,11 +1426,11 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         int queued = 1;
         for (int k = 1; e == hipSuccess; ++k) {
             if (queued == k && k < P->p.max_cycles) {
-                const bool likely_last =
+                const bool check_first =  // queue k+1 only after reading k
                     (mixed && inner_max > 1)
-                        ? (k >= 2 && mixed_pred(k + 1) <= 0.5 * P->p.rtol)
+                        ? (k == 1 || mixed_pred(k + 1) <= 0.5 * P->p.rtol)
                         : (k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol);
-                if (!likely_last) {
+                if (!check_first) {
                     e = enqueue(k + 1);
                     queued = k + 1;
                 }
