@@ -67,6 +67,7 @@ def measure(cc, torch, n, bc, fv, steps, warmup):
     phi = cc.field(n)
     cc.ccmg_plan_autotune(plan, f, phi)  # launch shapes per level, before any timing
     shapes = cc.ccmg_plan_shapes(plan)
+    fused_shape = cc.ccmg_plan_fused_shape(plan, 2)
     for _ in range(warmup):
         r = cc.ccmg_solve(plan, f, phi)
         assert r.status == cc.OK, r
@@ -79,7 +80,7 @@ def measure(cc, torch, n, bc, fv, steps, warmup):
     out = dict(n=n, bc=bc, seconds=dt, solves=steps, cycles=cycles,
                cycles_per_solve=cycles / steps, ms_per_solve=1e3 * dt / steps,
                pts_cycles_per_s=n * n * cycles / dt, rel_resid=res[-1].rel_resid,
-               history=res[-1].history, kernels=stats, shapes=shapes)
+               history=res[-1].history, kernels=stats, shapes=shapes, fused_shape=fused_shape)
     del plan, f, phi
     torch.cuda.empty_cache()
     return out
@@ -249,10 +250,12 @@ PMC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles
                            "march_finest_fused_poisson4096_pmc.md")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, shape=None):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
-    None when there is none or the kernel's sources changed since."""
+    None when there is none, the kernel's sources changed since, or the
+    autotuner chose another launch shape (rows per band, waves per workgroup)
+    than the one the counters were taken with."""
     import hashlib
     try:
         text = open(PMC_SUMMARY).read()
@@ -268,6 +271,8 @@ def measured_traffic(kernel: str):
             h.update(fh.read())
     if h.hexdigest() != fields.get("source_sha256"):
         return None
+    if shape is not None and fields.get("launch_shape", "").split() != [str(shape[0]), str(shape[1])]:
+        return None
     return float(fields["traffic_bytes_per_launch"])
 
 
@@ -277,7 +282,7 @@ def roofline_of(meas, n_expected=None):
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom["name"]) if n_expected == 4096 else None
+    traffic = measured_traffic(dom["name"], meas.get("fused_shape")) if n_expected == 4096 else None
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["name"],
                 avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_per_launch,
@@ -403,7 +408,7 @@ def main():
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "all_kernels")},
         "launch_shapes": {"levels": "finest first; (rows per band, waves per workgroup) of the nu1 and nu2 launches",
-                          "value": m["shapes"]},
+                          "value": m["shapes"], "fused": m["fused_shape"]},
         "cpu_baseline": cpu,
         "also": also,
     }

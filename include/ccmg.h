@@ -255,10 +255,14 @@ int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdif
  * `level`, 1 = the nu2 (prolongating) launch; ty even, >= 8 unless it covers
  * the level; 1 <= wpb <= 4.  ty = 0 selects the 2-D LDS tile kernel instead
  * of the row march (levels below the finest with at least 64 cells per side
- * that are not in the one-workgroup tail).  Results do not depend on the
- * shape. */
+ * that are not in the one-workgroup tail).  kind 2 = the fused finest launch
+ * of FP64 solves, 3 = its FP32 form in mixed-precision steps (level 0 only,
+ * ty even and >= 8, no tile kernel).  Results do not depend on the shape. */
 int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
 /* The plan's launch shapes per level (arrays of max_levels entries). */
+/* The fused finest launch's shape: kind 2 (FP64) or 3 (FP32), as for
+ * ccmg_plan_set_shape. */
+int ccmg_plan_fused_shape(ccmg_plan *plan, int kind, int *ty, int *wpb);
 int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, int *wpb_post,
                      int max_levels);
 

@@ -101,6 +101,7 @@ def lib():
         L.ccmg_plan_autotune.argtypes = [vp, dp, dp, pd]
         ip = ctypes.POINTER(ctypes.c_int)
         L.ccmg_plan_shapes.argtypes = [vp, ip, ip, ip, ip, i]
+        L.ccmg_plan_fused_shape.argtypes = [vp, i, ip, ip]
         L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
         L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
         fp = ctypes.POINTER(ctypes.c_float)
@@ -313,6 +314,14 @@ def ccmg_plan_autotune(plan: Plan, f: torch.Tensor, phi: torch.Tensor) -> None:
 
 def ccmg_plan_set_shape(plan: Plan, level: int, kind: int, ty: int, wpb: int) -> None:
     _check(lib().ccmg_plan_set_shape(plan.handle, level, kind, ty, wpb), "ccmg_plan_set_shape")
+
+
+def ccmg_plan_fused_shape(plan: Plan, kind: int = 2) -> tuple:
+    """(ty, wpb) of the fused finest launch: kind 2 FP64, 3 FP32."""
+    ty, wpb = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ccmg_plan_fused_shape(plan.handle, kind, ctypes.byref(ty), ctypes.byref(wpb)),
+           "ccmg_plan_fused_shape")
+    return ty.value, wpb.value
 
 
 def ccmg_plan_shapes(plan: Plan) -> list:

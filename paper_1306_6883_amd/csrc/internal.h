@@ -74,6 +74,15 @@ struct WorkItem {
     int tile;
 };
 
+// Columns of a row-march tile: a wavefront loads 128 (two per lane) and
+// outputs the middle ones; each side gives up one column per stage (2 nu
+// relaxations, the residual when there is a post stage) and one lane for the
+// prolongation's slope, rounded up to whole lanes.
+constexpr int march_halo_x(int nu, bool prolong, bool post) {
+    return (2 * nu + (post ? 1 : 0) + (prolong ? 2 : 0) + 1) & ~1;
+}
+constexpr int march_outw(int nu, bool prolong, bool post) { return 128 - 2 * march_halo_x(nu, prolong, post); }
+
 // Launch description chosen by the host for one level.
 struct MarchShape {
     int ty;       // rows per tile (even); 0: the 2-D LDS tile kernel (tile.hip)

@@ -100,14 +100,13 @@ struct Cfg {
     static constexpr int LAGR = POST ? 2 * NU + 1 : 0;  // residual stage
     static constexpr int LAST = POST ? LAGR : 2 * NU;   // last stage
     // halo columns: one per stage, two (one lane) for the prolongation slope
-    static constexpr int HXC = 2 * NU + (POST ? 1 : 0) + (PROLONG ? 2 : 0);
-    static constexpr int HX = (HXC + 1) & ~1;
+    static constexpr int HX = march_halo_x(NU, PROLONG, POST != 0);
     static constexpr int HY = (LAST + 1) & ~1;  // halo rows (even: rows start on red parity)
     static constexpr int W = LAST >= 7 ? 14 : 10;  // register window (rows), even
     static constexpr int D = W - LAST - 2;      // prefetch distance (rows)
     static constexpr int WC = W / 2;            // coarse-row window
     static constexpr int DC = WC - 3;           // coarse prefetch distance
-    static constexpr int OUTW = 128 - 2 * HX;   // output columns per tile
+    static constexpr int OUTW = march_outw(NU, PROLONG, POST != 0);  // output columns per tile
     static_assert(D >= 1 && DC >= 0, "window too small");
 };
 

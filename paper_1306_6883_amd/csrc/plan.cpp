@@ -15,6 +15,7 @@
 // into no-ops once the tolerance is met, so the GPU never waits on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -177,6 +178,7 @@ struct ccmg_plan {
     Layout lay;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
+    int simds = 1024;         // SIMDs of the device (compute units x 4)
     bool singular = false;
     double *hpin = nullptr;  // pinned host: relative residual per cycle
     hipEvent_t ev_sync[2] = {nullptr, nullptr};
@@ -834,6 +836,12 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     P->singular = p->alpha == 0.0 && p->bc[0] != CCMG_BC_DIRICHLET && p->bc[1] != CCMG_BC_DIRICHLET &&
                   p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
     for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            P->simds = 4 * ncu;
+    }
     P->shp_fused = shape_for(P->lay.lev[0].n);
     P->shp_fused32 = shape_for(P->lay.lev[0].n);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
@@ -857,6 +865,26 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
 }  // extern "C"
 
 namespace {
+// Rows per band that make a launch's wave count just fit k waves per SIMD
+// (k = 1 .. kmax), one wave per workgroup.  The dispatcher spreads such
+// workgroups evenly, so a wave count slightly above a multiple of the SIMD
+// count leaves some SIMDs a whole band more to march than the rest (at
+// 4096^2 the fused launch takes 136 us with 1280 waves on 1024 SIMDs and
+// 116 us with 1000).
+std::vector<int> balanced_tys(int n, int outw, int simds, int kmax) {
+    std::vector<int> out;
+    const int strips = (n + outw - 1) / outw;
+    for (int k = 1; k <= kmax; ++k) {
+        const int chunks = k * simds / strips;
+        if (chunks < 1) continue;
+        int ty = (n + chunks - 1) / chunks;
+        ty += ty & 1;
+        if (ty < kMinTy || ty >= n) continue;
+        if (std::find(out.begin(), out.end(), ty) == out.end()) out.push_back(ty);
+    }
+    return out;
+}
+
 // Time every candidate launch shape of each row-march level (the nu1 half and
 // the nu2 half of the cycle separately) and keep the fastest.  T is the
 // precision of the relaxed levels (double for FP64 plans, float for MIXED).
@@ -933,15 +961,23 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             }
             float best = 1e30f;
             MarchShape bs = kind == 0 ? P->shp_pre[l] : P->shp_post[l];
-            // candidates: row-march shapes, and (levels below the finest) the
-            // 2-D LDS tile kernel, written as ty = 0
+            // candidates: row-march shapes (powers of two, and bands that
+            // balance the waves over the SIMDs), and (levels below the finest)
+            // the 2-D LDS tile kernel, written as ty = 0
             const bool tile_ok = l > 0 && n >= kTileMinN;
+            std::vector<MarchShape> cands;
             for (int ty : tys) {
-                if (ty > n && ty != tys[0] && !(ty == tys[0] && tile_ok)) continue;
-                for (int wpb : wpbs) {
-                    if (ty == 0 && wpb != wpbs[0]) continue;
-                    MarchShape sh{ty == 0 ? 0 : (ty < n ? ty : n), wpb};
-                    if (ty == 0 && !tile_ok) continue;
+                if (ty == 0) {
+                    if (tile_ok) cands.push_back(MarchShape{0, 1});
+                    continue;
+                }
+                if (ty > n) continue;
+                for (int wpb : wpbs) cands.push_back(MarchShape{ty < n ? ty : n, wpb});
+            }
+            for (int ty : balanced_tys(n, march_outw(nu, prolong, post != POST_NONE), P->simds, 4))
+                cands.push_back(MarchShape{ty, 1});
+            for (const MarchShape &sh : cands) {
+                {
                     int nt;
                     err = launch_march<T>(a, nu, load_phi, prolong, post, sh, s, &nt);  // warm-up
                     if (err == hipSuccess) err = hipEventRecord(e0, s);
@@ -993,10 +1029,14 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
         const int n = lay.lev[0].n;
         float best = 1e30f;
         MarchShape bs = f64 ? P->shp_fused : P->shp_fused32;
+        std::vector<MarchShape> cands;
         for (int ty : {16, 32, 64, 128, 256}) {
             if (ty > n && ty != 16) continue;
-            for (int wpb : {1, 2}) {
-                const MarchShape sh{ty < n ? ty : n, wpb};
+            for (int wpb : {1, 2}) cands.push_back(MarchShape{ty < n ? ty : n, wpb});
+        }
+        for (int ty : balanced_tys(n, march_outw(4, true, true), P->simds, 4)) cands.push_back(MarchShape{ty, 1});
+        for (const MarchShape &sh : cands) {
+            {
                 int nt;
                 err = launch_march<T>(a, 4, true, true, POST_FUSED, sh, s, &nt);  // warm-up
                 if (err == hipSuccess) err = hipEventRecord(e0, s);
@@ -1035,7 +1075,15 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
 }
 
 int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
-    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || (kind != 0 && kind != 1)) return CCMG_EINVAL;
+    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 3) return CCMG_EINVAL;
+    if (kind >= 2) {  // the fused finest launch (FP64 / FP32)
+        const int n = P->lay.lev[0].n;
+        if (level != 0 || ty < 2 || (ty & 1) || (ty < kMinTy && ty < n) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
+        const MarchShape sh{ty < n ? ty : n, wpb};
+        if (kind == 2) P->shp_fused = sh;
+        else P->shp_fused32 = sh;
+        return CCMG_OK;
+    }
     if (ty == 0) {  // the 2-D LDS tile kernel: levels below the finest that are not in the tail
         if (level == 0 || level >= P->lay.lt || P->lay.lev[level].n < kTileMinN) return CCMG_EINVAL;
         if (kind == 0) P->shp_pre[level] = MarchShape{0, 1};
@@ -1049,6 +1097,14 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     MarchShape sh{ty < n ? ty : n, wpb};
     if (kind == 0) P->shp_pre[level] = sh;
     else P->shp_post[level] = sh;
+    return CCMG_OK;
+}
+
+int ccmg_plan_fused_shape(ccmg_plan *P, int kind, int *ty, int *wpb) {
+    if (!P || !ty || !wpb || (kind != 2 && kind != 3)) return CCMG_EINVAL;
+    const MarchShape &sh = kind == 2 ? P->shp_fused : P->shp_fused32;
+    *ty = sh.ty;
+    *wpb = sh.wpb;
     return CCMG_OK;
 }
 
