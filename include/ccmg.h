@@ -14,8 +14,9 @@
  *
  * Conventions for every entry point:
  *   - Device arrays hold one grid level *with* one ghost layer: (n+2) rows of
- *     `pitch` elements (pitch >= n+2), row-major, x contiguous; valid cell
- *     (i, j) is element (j+1)*pitch + (i+1).  Pitches are in elements.
+ *     `pitch` elements (pitch >= n+2, and (n+2) * pitch < 2^31), row-major,
+ *     x contiguous; valid cell (i, j) is element (j+1)*pitch + (i+1).
+ *     Pitches are in elements; a pitch outside these bounds is CCMG_EINVAL.
  *   - Arrays are owned by the caller; the library never allocates device
  *     memory.  Plans work inside a caller-provided workspace.
  *   - All GPU work is enqueued on the plan's stream (a hipStream_t passed as

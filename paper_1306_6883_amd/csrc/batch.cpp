@@ -659,11 +659,21 @@ int ccmg_batch_destroy(ccmg_batch *B) {
     return CCMG_OK;
 }
 
+// Every problem's arrays: present, pitch >= n + 2, fewer than 2^31 elements
+// (the kernels form row offsets in 32 bits).
+static bool arrays_ok(const ccmg_batch *B, const double *const *d_f, double *const *d_phi, const ptrdiff_t *pitch) {
+    if (!d_f || !d_phi || !pitch) return false;
+    for (int i = 0; i < B->m; ++i) {
+        const long rows = B->prob[i].n + 2;
+        if (!d_f[i] || !d_phi[i] || pitch[i] < rows || (double)pitch[i] * (double)rows >= 2147483648.0)
+            return false;
+    }
+    return true;
+}
+
 int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_phi, const ptrdiff_t *pitch,
                      int use_guess, ccmg_result *out, ccmg_batch_info *info) {
-    if (!B || !d_f || !d_phi || !pitch) return CCMG_EINVAL;
-    for (int i = 0; i < B->m; ++i)
-        if (!d_f[i] || !d_phi[i] || pitch[i] < B->prob[i].n + 2) return CCMG_EINVAL;
+    if (!B || !arrays_ok(B, d_f, d_phi, pitch)) return CCMG_EINVAL;
     const int m = B->m;
     hipError_t e = hipEventRecord(B->ev_in, B->user);  // order after the caller's prior work
     if (e == hipSuccess) e = hipStreamWaitEvent(B->stream, B->ev_in, 0);
@@ -777,7 +787,7 @@ int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_p
 // Time the candidate rows-per-band of every level size class on the given
 // arrays (whole steps replayed) and keep the fastest; recaptures the graphs.
 int ccmg_batch_autotune(ccmg_batch *B, const double *const *d_f, double *const *d_phi, const ptrdiff_t *pitch) {
-    if (!B || !d_f || !d_phi || !pitch) return CCMG_EINVAL;
+    if (!B || !arrays_ok(B, d_f, d_phi, pitch)) return CCMG_EINVAL;
     hipError_t e = prepare(B, d_f, d_phi, pitch, false, true);
     if (e != hipSuccess) return CCMG_EHIP;
     // reset the flags so that every launch does its work while being timed

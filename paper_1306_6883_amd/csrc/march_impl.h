@@ -65,6 +65,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Element offset of row r (>= 0) of an array with pitch p.  The host admits
+// only arrays of fewer than 2^31 elements ((n + 2) * pitch), so the product
+// fits 32 bits: one scalar multiply per row address instead of a 64-bit one.
+__device__ __forceinline__ unsigned row_off(int r, long p) { return (unsigned)r * (unsigned)p; }
+
 // Total of `count` partial sums, formed in a fixed order (deterministic):
 // each lane adds every 64th value in turn, then the lanes are combined.  The
 // values are loaded 16 at a time (predicated) before they are added in that
@@ -170,11 +175,11 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     auto load_row = [&](int y, T &p0, T &p1, T &f0, T &f1) {
         y = min(y, ye - 1);
         const int yy = py ? (y & nm) : y;
-        const T *fr = a.f + (long)(yy + 1) * a.pf;
+        const T *fr = a.f + row_off(yy + 1, a.pf);
         f0 = fr[lo];
         f1 = fr[lo + 1];
         if (LOADPHI) {
-            const T *pr = a.phi_in + (long)(yy + 1) * a.pin;
+            const T *pr = a.phi_in + row_off(yy + 1, a.pin);
             p0 = pr[lo];
             p1 = pr[lo + 1];
         }
@@ -182,8 +187,8 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     auto load_row64 = [&](int y, double &q0, double &q1, double &g0, double &g1) {
         y = min(y, ye - 1);
         const int yy = py ? (y & nm) : y;
-        const double *qr = a.q_in + (long)(yy + 1) * a.pq_in;
-        const double *gr = a.g + (long)(yy + 1) * a.pg;
+        const double *qr = a.q_in + row_off(yy + 1, a.pq_in);
+        const double *gr = a.g + row_off(yy + 1, a.pg);
         q0 = qr[lo];
         q1 = qr[lo + 1];
         g0 = gr[lo];
@@ -191,7 +196,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     };
     auto load_coarse = [&](int J, T &c) {
         const int Jl = py ? (J & (nc - 1)) : (J < 0 ? 0 : (J >= nc ? nc - 1 : J));
-        c = (a.ec + (long)(Jl + 1) * a.pc)[co];
+        c = (a.ec + row_off(Jl + 1, a.pc))[co];
     };
 
     double acc0 = 0.0, acc1 = 0.0;
@@ -231,10 +236,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             }
             // 2. finish the load of row t: mean shifts, prolongation (done for
             // every step: past the band it only touches halo slots)
-            if (subf) {
-                F0[k] -= fsub;
-                F1[k] -= fsub;
-            }
+            // (fsub and psub are 0 when there is no shift: x - 0 is x, bit for
+            // bit, and costs less than selecting between the two)
+            F0[k] -= fsub;
+            F1[k] -= fsub;
             if constexpr (IR) {
                 if (a.q_zero) {
                     Q0[k] = 0.0;
@@ -245,7 +250,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 }
             }
             if (LOADPHI) {
-                if (subp && !IR) {
+                if constexpr (!IR) {
                     P0[k] -= psub;
                     P1[k] -= psub;
                 }
@@ -351,7 +356,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         accN0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
                         accN1 += (double)p0 + (double)p1;
                         if (a.phi_mid) {
-                            T *o = a.phi_mid + (long)(y + 1) * a.pmid;
+                            T *o = a.phi_mid + row_off(y + 1, a.pmid);
                             o[1 + tl.x0] = p0;
                             o[2 + tl.x0] = p1;
                         }
@@ -371,12 +376,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     Q0[kk] += (double)P0[kk];
                     Q1[kk] += (double)P1[kk];
                     if (y >= y0 && y < y1 && tl.outl) {
-                        double *o = a.q_out + (long)(y + 1) * a.pq_out;
+                        double *o = a.q_out + row_off(y + 1, a.pq_out);
                         o[1 + tl.x0] = Q0[kk];
                         o[2 + tl.x0] = Q1[kk];
                     }
                 } else if (a.phi_out && y >= y0 && y < y1 && tl.outl) {
-                    T *o = a.phi_out + (long)(y + 1) * a.pout;
+                    T *o = a.phi_out + row_off(y + 1, a.pout);
                     o[1 + tl.x0] = P0[kk];
                     o[2 + tl.x0] = P1[kk];
                 }
@@ -413,7 +418,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const double r1 = G1[kk] - (a.alpha64 * p1 - a.beta64 * lap1);
                     if (tl.outl) {
                         const float q0 = (float)r0, q1 = (float)r1;
-                        float *o = a.r_out + (long)(y + 1) * a.pr;
+                        float *o = a.r_out + row_off(y + 1, a.pr);
                         o[1 + tl.x0] = q0;
                         o[2 + tl.x0] = q1;
                         acc0 += r0 * r0 + r1 * r1;
@@ -454,7 +459,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
                             const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
                             if (tl.outl) {
-                                (a.aux + (long)((y >> 1) + 1) * a.paux)[1 + (tl.x0 >> 1)] = v;
+                                (a.aux + row_off((y >> 1) + 1, a.paux))[1 + (tl.x0 >> 1)] = v;
                                 acc0 += (double)v;
                             }
                         } else {
@@ -469,7 +474,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     } else if constexpr (POST == POST_R32) {
                         if (tl.outl) {
                             const float q0 = (float)r0, q1 = (float)r1;
-                            float *o = a.r_out + (long)(y + 1) * a.pr;
+                            float *o = a.r_out + row_off(y + 1, a.pr);
                             o[1 + tl.x0] = q0;
                             o[2 + tl.x0] = q1;
                             acc0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
@@ -478,7 +483,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         }
                     } else {  // POST_RESID
                         if (tl.outl) {
-                            T *o = a.aux + (long)(y + 1) * a.paux;
+                            T *o = a.aux + row_off(y + 1, a.paux);
                             o[1 + tl.x0] = r0;
                             o[2 + tl.x0] = r1;
                         }

@@ -737,9 +737,12 @@ hipError_t enqueue_mixed_step_inner(ccmg_plan *P, const double *d_f, long pf, Mi
                             skip ? P->drho + slot : nullptr, s);
 }
 
+// pitch >= n + 2, and the array holds fewer than 2^31 elements (the kernels
+// form row offsets in 32 bits)
 int check_pitch(const ccmg_plan *P, int level, ptrdiff_t pitch) {
     if (level < 0 || level >= P->lay.L) return CCMG_EINVAL;
-    if (pitch < (ptrdiff_t)(P->lay.lev[level].n + 2)) return CCMG_EINVAL;
+    const ptrdiff_t rows = P->lay.lev[level].n + 2;
+    if (pitch < rows || (double)pitch * (double)rows >= 2147483648.0) return CCMG_EINVAL;
     return CCMG_OK;
 }
 

@@ -57,10 +57,12 @@ def test_batch_mixed_sizes_and_sides():
         assert np.array_equal(h[1:-1, :], filled[1:-1, :]) and np.array_equal(h[:, 1:-1], filled[:, 1:-1])
 
 
-def test_batch_matches_single_mixed_solves():
+def test_batch_matches_single_mixed_solves(monkeypatch):
     """Each problem of a batch takes the same steps as solving it alone with a
-    MIXED plan (the same arithmetic; tile shapes may differ, so compare to
+    MIXED plan that runs one FP32 V-cycle per refinement step, as the batch
+    does (the same arithmetic; tile shapes may differ, so compare to
     rounding)."""
+    monkeypatch.setenv("CCMG_MIXED_INNER", "1")
     items, probs = make_batch(seed=4, count=8, sizes=(64, 128, 256))
     batch = cc.Batch(probs)
     fs = [dev_field(oracle.embed(it.f)) for it in items]

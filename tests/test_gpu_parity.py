@@ -300,3 +300,20 @@ def test_tile_shape_invariance(bc):
         else:
             assert np.array_equal(o, outs[0])
     assert len(cc.ccmg_plan_shapes(plan)) == 10
+
+
+def test_pitch_bounds_rejected_before_any_launch():
+    """A pitch below n + 2, or one that makes an array of 2^31 elements or
+    more, is refused by the host checks (the kernels form 32-bit row
+    offsets); nothing is launched, so small real buffers are safe here."""
+    n = 64
+    plan = plan_for(n, "DDDD")
+    f = dev_field(oracle.embed(rand(n, 1)))
+    phi = dev_field(oracle.field_zeros(n))
+    phi2 = dev_field(oracle.field_zeros(n))
+    L = cc.lib()
+    big = (2 ** 31) // (n + 2) + 1
+    for pitch in (n + 1, big):
+        assert L.ccmg_solve(plan.handle, f.data_ptr(), phi.data_ptr(), pitch, 0, None) == cc.EINVAL
+        assert L.ccmg_smooth(plan.handle, 0, 1, f.data_ptr(), phi.data_ptr(), phi2.data_ptr(), pitch) == cc.EINVAL
+    torch.cuda.synchronize()
