@@ -60,12 +60,14 @@ def run_solves(cc, torch, plan, f, phi, steps, profile=False):
     return dt, res, stats
 
 
-def measure(cc, torch, n, bc, fv, steps, warmup):
+def measure(cc, torch, n, bc, fv, steps, warmup, fused_shape=None):
     prob = cc.Problem(n=n, bc=bc, rtol=1e-10)
     plan = cc.Plan(prob)
     f = upload(cc, torch, fv)
     phi = cc.field(n)
     cc.ccmg_plan_autotune(plan, f, phi)  # launch shapes per level, before any timing
+    if fused_shape:  # a fixed shape for the fused launch (reproducible counter runs)
+        cc.ccmg_plan_set_shape(plan, 0, 2, fused_shape[0], fused_shape[1])
     shapes = cc.ccmg_plan_shapes(plan)
     fused_shape = cc.ccmg_plan_fused_shape(plan, 2)
     for _ in range(warmup):
@@ -271,9 +273,11 @@ def measured_traffic(kernel: str, shape=None):
             h.update(fh.read())
     if h.hexdigest() != fields.get("source_sha256"):
         return None
-    if shape is not None and fields.get("launch_shape", "").split() != [str(shape[0]), str(shape[1])]:
+    # one counter pair per launch shape the autotuner picks at this size
+    key = f"traffic_bytes_per_launch_{shape[0]}_{shape[1]}" if shape is not None else None
+    if key not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[key])
 
 
 def roofline_of(meas, n_expected=None):
@@ -326,6 +330,9 @@ def main():
                     help="run only the learned-guess leg and print its result (profiling aid)")
     ap.add_argument("--learned-solves", type=int, default=20000, help="training solves of the learned leg")
     ap.add_argument("--learned-steps", type=int, default=30000, help="training steps of the learned leg")
+    ap.add_argument("--fused-shape", type=str, default=None,
+                    help="TY,WPB: rows per band and waves per workgroup of the 4096^2 fused launch, "
+                         "instead of the autotuner's choice (for counter runs)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -357,7 +364,8 @@ def main():
         del a, b
 
     log(f"{n}^2 periodic: {args.warmup} warmup + {args.steps} timed solves")
-    m = measure(cc, torch, n, "P", f4096, args.steps, args.warmup)
+    fshape = tuple(int(x) for x in args.fused_shape.split(",")) if args.fused_shape else None
+    m = measure(cc, torch, n, "P", f4096, args.steps, args.warmup, fused_shape=fshape)
     log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
         f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
     rl = roofline_of(m, n_expected=n)
