@@ -89,6 +89,8 @@ def _load(path: str):
                              ctypes.POINTER(_Result)]
     lib.og_smooth_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
                                     ctypes.POINTER(_Result)]
+    lib.og_cn_rhs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, dp, dp]
+    lib.og_cn_step.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.POINTER(_Result)]
     return lib
 
 
@@ -235,4 +237,24 @@ def smooth_solve(p: Problem, f: np.ndarray, max_iters: int, phi: np.ndarray | No
     phi = field_zeros(p.n) if phi is None else phi
     res = _Result()
     _lib().og_smooth_solve(ctypes.byref(p._c()), _ptr(phi), _ptr(f), max_iters, ctypes.byref(res))
+    return phi, _result(res)
+
+
+def cn_rhs(n: int, h: float, beta: float, bc, phi: np.ndarray) -> np.ndarray:
+    """Right-hand side of a Crank-Nicolson diffusion step (Sec. 3.4):
+    f = phi + beta Lap phi with beta = k dt / 2 (phi's ghosts are filled)."""
+    f = field_zeros(n)
+    _lib().og_cn_rhs(n, h, beta, _bcp(bc), _ptr(phi), _ptr(f))
+    return f
+
+
+def cn_step(p: Problem, phi: np.ndarray):
+    """One Crank-Nicolson step of phi_t = k Lap phi in place: p.alpha = 1 and
+    p.beta = k dt / 2; the old phi is the solve's initial guess.  Returns
+    (phi, Result)."""
+    work = field_zeros(p.n)
+    res = _Result()
+    st = _lib().og_cn_step(ctypes.byref(p._c()), _ptr(phi), _ptr(work), ctypes.byref(res))
+    if st == EINVAL:
+        raise ValueError("oracle cn_step: bad problem (alpha must be 1)")
     return phi, _result(res)

@@ -309,3 +309,33 @@ int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_it
     free(r);
     return status;
 }
+
+/* Crank-Nicolson step of the diffusion equation phi_t = k Lap phi (pyro
+ * paper, Sec. 3.4 "Implicit diffusion"): the step averages k Lap phi over
+ * the old and the new time level, so with beta = k dt / 2 the new phi solves
+ * (1 - beta Lap) phi' = phi + beta Lap phi -- the Helmholtz problem of
+ * Sec. 3.3 with alpha = 1 and that right-hand side.
+ * og_cn_rhs: f = phi + beta Lap phi on valid cells (phi's ghosts filled
+ * first; Lap written as differences from the centre, as in og_residual). */
+void og_cn_rhs(int n, double h, double beta, const int bc[4], double *phi, double *f) {
+    og_fill(n, bc, phi);
+    const double ih2 = 1.0 / (h * h);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            double p = phi[IDX(n, i, j)];
+            double lap = ((phi[IDX(n, i + 1, j)] - p) + (phi[IDX(n, i - 1, j)] - p) +
+                          (phi[IDX(n, i, j + 1)] - p) + (phi[IDX(n, i, j - 1)] - p)) * ih2;
+            f[IDX(n, i, j)] = p + beta * lap;
+        }
+    }
+}
+
+/* One step in place: work <- the right-hand side, then V-cycles from phi
+ * (the old level as the initial guess) to the tolerance.  p->alpha must be
+ * 1 and p->beta = k dt / 2. */
+int og_cn_step(const og_params *p, double *phi, double *work, og_result *out) {
+    if (!valid_n(p->n) || p->alpha != 1.0) return OG_EINVAL;
+    og_cn_rhs(p->n, p->h, p->beta, p->bc, phi, work);
+    return og_solve(p, phi, work, 1, out);
+}

@@ -51,6 +51,8 @@ int og_vcycle(const og_params *p, double *phi, const double *f);
 int og_solve(const og_params *p, double *phi, const double *f, int use_guess, og_result *out);
 int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_iters,
                     og_result *out);
+void og_cn_rhs(int n, double h, double beta, const int bc[4], double *phi, double *f);
+int og_cn_step(const og_params *p, double *phi, double *work, og_result *out);
 
 #ifdef __cplusplus
 }

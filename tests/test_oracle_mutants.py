@@ -25,13 +25,24 @@ def _pins():
 
 P = _pins()
 
+
+def _cn_pins():
+    spec = importlib.util.spec_from_file_location("oracle_cn_pins", os.path.join(HERE, "test_oracle_cn.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+C = _cn_pins()
+
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
 MUTANTS = {
     "relaxation_sign": ("(f[IDX(n, i, j)] + c * nb) / diag", "(f[IDX(n, i, j)] - c * nb) / diag"),
     "dirichlet_ghost_sign": ("(bc[OG_XLO] == OG_DIRICHLET ? -lo : lo)", "(bc[OG_XLO] == OG_DIRICHLET ? lo : lo)"),
     "neumann_ghost_sign": ("(bc[OG_YHI] == OG_DIRICHLET ? -hi : hi)", "(bc[OG_YHI] == OG_DIRICHLET ? -hi : -hi)"),
     "periodic_wrap_side": ("bc[OG_YHI] == OG_PERIODIC ? lo :", "bc[OG_YHI] == OG_PERIODIC ? hi :"),
-    "residual_dropped_term": (" + (phi[IDX(n, i, j - 1)] - p)) * ih2;", ") * ih2;"),
+    "residual_dropped_term": (" + (phi[IDX(n, i, j - 1)] - p)) * ih2;\n            r[IDX(n, i, j)]",
+                              ") * ih2;\n            r[IDX(n, i, j)]"),
     "residual_sign": ("f[IDX(n, i, j)] - (alpha * p - beta * lap)", "f[IDX(n, i, j)] - (alpha * p + beta * lap)"),
     "restriction_weight": ("0.25 * (fine[IDX(n, 2 * I, 2 * J)]", "0.5 * (fine[IDX(n, 2 * I, 2 * J)]"),
     "restriction_index": ("fine[IDX(n, 2 * I + 1, 2 * J + 1)]", "fine[IDX(n, 2 * I + 1, 2 * J)]"),
@@ -41,6 +52,8 @@ MUTANTS = {
     "coarse_spacing": ("double h = p->h * (double)(1 << lev);", "double h = p->h;"),
     "colour_order": ("relax_colour(n, h, alpha, beta, bc, phi, f, 0); /* red   */",
                      "relax_colour(n, h, alpha, beta, bc, phi, f, 1); /* red   */"),
+    "cn_rhs_sign": ("f[IDX(n, i, j)] = p + beta * lap;", "f[IDX(n, i, j)] = p - beta * lap;"),
+    "cn_rhs_half_step": ("f[IDX(n, i, j)] = p + beta * lap;", "f[IDX(n, i, j)] = p + 2.0 * beta * lap;"),
 }
 # Not a mutant: dropping the removal of each restricted right-hand side's mean
 # (singular problems) changes the iterates only by rounding -- the residual of
@@ -61,6 +74,7 @@ BATTERY = [
     (P.test_vcycle_convergence_factor_h_independent, ("PPPP",)),
     (P.test_vcycle_convergence_factor_h_independent, ("DDDD",)),
     (P.test_mg_matches_transform_solution_n128, ("PPPP",)),
+    (C.test_cn_step_multiplies_an_eigenmode_by_the_closed_form_factor, ("NNNN", 2.0)),
 ]
 
 
