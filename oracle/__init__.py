@@ -91,6 +91,10 @@ def _load(path: str):
                                     ctypes.POINTER(_Result)]
     lib.og_cn_rhs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, dp, dp]
     lib.og_cn_step.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.POINTER(_Result)]
+    bp = ctypes.POINTER(dp)
+    lib.og_fill_bc.argtypes = [ctypes.c_int, ctypes.c_double, ip, bp, dp]
+    lib.og_bc_rhs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, bp, dp, dp]
+    lib.og_solve_bc.argtypes = [ctypes.POINTER(_Params), dp, dp, bp, ctypes.c_int, ctypes.POINTER(_Result)]
     return lib
 
 
@@ -257,4 +261,46 @@ def cn_step(p: Problem, phi: np.ndarray):
     st = _lib().og_cn_step(ctypes.byref(p._c()), _ptr(phi), _ptr(work), ctypes.byref(res))
     if st == EINVAL:
         raise ValueError("oracle cn_step: bad problem (alpha must be 1)")
+    return phi, _result(res)
+
+
+def _sides(b):
+    """Four side-data arrays (or None) -> a C array of four pointers; the
+    arrays are kept alive by the returned tuple."""
+    keep = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (b or [None] * 4)]
+    if len(keep) != 4:
+        raise ValueError("side data needs four entries")
+    dp = ctypes.POINTER(ctypes.c_double)
+    arr = (dp * 4)(*[ctypes.cast(None, dp) if v is None else v.ctypes.data_as(dp) for v in keep])
+    return arr, keep
+
+
+def fill_bc(a: np.ndarray, h: float, bc, b) -> np.ndarray:
+    """Ghost cells with side data b (four arrays of n values or None): a
+    Dirichlet value v gives ghost 2v - phi, a Neumann derivative d gives
+    phi - h d (lo sides) or phi + h d (hi sides)."""
+    n = a.shape[0] - 2
+    arr, _keep = _sides(b)
+    _lib().og_fill_bc(n, h, _bcp(bc), arr, _ptr(a))
+    return a
+
+
+def bc_rhs(n: int, h: float, beta: float, bc, b, f: np.ndarray) -> np.ndarray:
+    """The right-hand side of the equivalent homogeneous problem."""
+    arr, _keep = _sides(b)
+    out = field_zeros(n)
+    _lib().og_bc_rhs(n, h, beta, _bcp(bc), arr, _ptr(f), _ptr(out))
+    return out
+
+
+def solve_bc(p: Problem, f: np.ndarray, b, phi: np.ndarray | None = None):
+    """V-cycles with side data b until ||r||/||f'|| <= rtol (f' the shifted
+    right-hand side); the returned field's ghosts carry the data."""
+    use_guess = phi is not None
+    phi = field_zeros(p.n) if phi is None else phi
+    arr, _keep = _sides(b)
+    res = _Result()
+    st = _lib().og_solve_bc(ctypes.byref(p._c()), _ptr(phi), _ptr(f), arr, int(use_guess), ctypes.byref(res))
+    if st == EINVAL:
+        raise ValueError("oracle solve_bc: bad problem")
     return phi, _result(res)

@@ -339,3 +339,67 @@ int og_cn_step(const og_params *p, double *phi, double *work, og_result *out) {
     og_cn_rhs(p->n, p->h, p->beta, p->bc, phi, work);
     return og_solve(p, phi, work, 1, out);
 }
+
+/* Inhomogeneous side data (Sec. 3.3: the boundary value itself then enters
+ * the ghost cell's expression).  b[s] holds n values along side s (index j
+ * for the x sides, i for the y sides; NULL = homogeneous on that side; a
+ * periodic side takes none).  Second-order ghosts:
+ *   Dirichlet, value v at the face:  ghost = 2 v - phi_adjacent;
+ *   Neumann, derivative d = dphi/dx (x sides) or dphi/dy (y sides) at the
+ *   face:  lo ghost = phi_adjacent - h d,  hi ghost = phi_adjacent + h d. */
+static double side_value(const double *const b[4], int s, int k) { return b && b[s] ? b[s][k] : 0.0; }
+
+void og_fill_bc(int n, double h, const int bc[4], const double *const b[4], double *a) {
+    og_fill(n, bc, a);
+    for (int j = 0; j < n; ++j) {
+        double vl = side_value(b, OG_XLO, j), vh = side_value(b, OG_XHI, j);
+        if (bc[OG_XLO] == OG_DIRICHLET) a[IDX(n, -1, j)] += 2.0 * vl;
+        if (bc[OG_XLO] == OG_NEUMANN) a[IDX(n, -1, j)] -= h * vl;
+        if (bc[OG_XHI] == OG_DIRICHLET) a[IDX(n, n, j)] += 2.0 * vh;
+        if (bc[OG_XHI] == OG_NEUMANN) a[IDX(n, n, j)] += h * vh;
+    }
+    for (int i = 0; i < n; ++i) {
+        double vl = side_value(b, OG_YLO, i), vh = side_value(b, OG_YHI, i);
+        if (bc[OG_YLO] == OG_DIRICHLET) a[IDX(n, i, -1)] += 2.0 * vl;
+        if (bc[OG_YLO] == OG_NEUMANN) a[IDX(n, i, -1)] -= h * vl;
+        if (bc[OG_YHI] == OG_DIRICHLET) a[IDX(n, i, n)] += 2.0 * vh;
+        if (bc[OG_YHI] == OG_NEUMANN) a[IDX(n, i, n)] += h * vh;
+    }
+}
+
+/* The problem with side data as a homogeneous one: the data's part of each
+ * ghost (ghost with data minus ghost without) multiplies beta / h^2 in the
+ * operator, so it moves to the right-hand side:
+ *   f_out = f + (beta / h^2) * sum over the cell's out-of-domain neighbours of
+ *           (data part of that ghost).
+ * The coarse levels then solve the homogeneous correction problem, as the
+ * paper's V-cycle does. */
+void og_bc_rhs(int n, double h, double beta, const int bc[4], const double *const b[4], const double *f,
+               double *f_out) {
+    double *g0 = (double *)calloc(og_field_len(n), sizeof(double));
+    og_fill_bc(n, h, bc, b, g0); /* the data part of every ghost (phi = 0) */
+    const double c = beta / (h * h);
+    memcpy(f_out, f, sizeof(double) * og_field_len(n));
+    for (int j = 0; j < n; ++j) {
+        f_out[IDX(n, 0, j)] += c * (bc[OG_XLO] == OG_PERIODIC ? 0.0 : g0[IDX(n, -1, j)]);
+        f_out[IDX(n, n - 1, j)] += c * (bc[OG_XHI] == OG_PERIODIC ? 0.0 : g0[IDX(n, n, j)]);
+    }
+    for (int i = 0; i < n; ++i) {
+        f_out[IDX(n, i, 0)] += c * (bc[OG_YLO] == OG_PERIODIC ? 0.0 : g0[IDX(n, i, -1)]);
+        f_out[IDX(n, i, n - 1)] += c * (bc[OG_YHI] == OG_PERIODIC ? 0.0 : g0[IDX(n, i, n)]);
+    }
+    free(g0);
+}
+
+/* Solve with side data: V-cycles on the shifted right-hand side, then the
+ * returned field's ghosts filled with the data. */
+int og_solve_bc(const og_params *p, double *phi, const double *f, const double *const b[4], int use_guess,
+                og_result *out) {
+    if (!valid_n(p->n)) return OG_EINVAL;
+    double *f2 = (double *)calloc(og_field_len(p->n), sizeof(double));
+    og_bc_rhs(p->n, p->h, p->beta, p->bc, b, f, f2);
+    int st = og_solve(p, phi, f2, use_guess, out);
+    og_fill_bc(p->n, p->h, p->bc, b, phi);
+    free(f2);
+    return st;
+}

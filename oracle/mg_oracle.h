@@ -53,6 +53,11 @@ int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_it
                     og_result *out);
 void og_cn_rhs(int n, double h, double beta, const int bc[4], double *phi, double *f);
 int og_cn_step(const og_params *p, double *phi, double *work, og_result *out);
+void og_fill_bc(int n, double h, const int bc[4], const double *const b[4], double *a);
+void og_bc_rhs(int n, double h, double beta, const int bc[4], const double *const b[4], const double *f,
+               double *f_out);
+int og_solve_bc(const og_params *p, double *phi, const double *f, const double *const b[4], int use_guess,
+                og_result *out);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,16 @@ def _cn_pins():
 
 C = _cn_pins()
 
+
+def _bc_pins():
+    spec = importlib.util.spec_from_file_location("oracle_bc_pins", os.path.join(HERE, "test_oracle_bc.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+B = _bc_pins()
+
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
 MUTANTS = {
     "relaxation_sign": ("(f[IDX(n, i, j)] + c * nb) / diag", "(f[IDX(n, i, j)] - c * nb) / diag"),
@@ -54,6 +64,10 @@ MUTANTS = {
                      "relax_colour(n, h, alpha, beta, bc, phi, f, 1); /* red   */"),
     "cn_rhs_sign": ("f[IDX(n, i, j)] = p + beta * lap;", "f[IDX(n, i, j)] = p - beta * lap;"),
     "cn_rhs_half_step": ("f[IDX(n, i, j)] = p + beta * lap;", "f[IDX(n, i, j)] = p + 2.0 * beta * lap;"),
+    "dirichlet_data_factor": ("if (bc[OG_XLO] == OG_DIRICHLET) a[IDX(n, -1, j)] += 2.0 * vl;",
+                              "if (bc[OG_XLO] == OG_DIRICHLET) a[IDX(n, -1, j)] += vl;"),
+    "neumann_data_sign": ("if (bc[OG_XLO] == OG_NEUMANN) a[IDX(n, -1, j)] -= h * vl;",
+                          "if (bc[OG_XLO] == OG_NEUMANN) a[IDX(n, -1, j)] += h * vl;"),
 }
 # Not a mutant: dropping the removal of each restricted right-hand side's mean
 # (singular problems) changes the iterates only by rounding -- the residual of
@@ -75,6 +89,8 @@ BATTERY = [
     (P.test_vcycle_convergence_factor_h_independent, ("DDDD",)),
     (P.test_mg_matches_transform_solution_n128, ("PPPP",)),
     (C.test_cn_step_multiplies_an_eigenmode_by_the_closed_form_factor, ("NNNN", 2.0)),
+    (B.test_side_data_solve_matches_the_extended_dense_system, ("DNND", (0.0, -1.0))),
+    (B.test_side_data_solve_matches_the_extended_dense_system, ("NDDN", (1.0, 0.02))),
 ]
 
 
