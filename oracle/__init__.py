@@ -95,6 +95,9 @@ def _load(path: str):
     lib.og_fill_bc.argtypes = [ctypes.c_int, ctypes.c_double, ip, bp, dp]
     lib.og_bc_rhs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ip, bp, dp, dp]
     lib.og_solve_bc.argtypes = [ctypes.POINTER(_Params), dp, dp, bp, ctypes.c_int, ctypes.POINTER(_Result)]
+    lib.og_divergence.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
+    lib.og_subtract_gradient.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
+    lib.og_project.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.POINTER(_Result)]
     return lib
 
 
@@ -304,3 +307,22 @@ def solve_bc(p: Problem, f: np.ndarray, b, phi: np.ndarray | None = None):
     if st == EINVAL:
         raise ValueError("oracle solve_bc: bad problem")
     return phi, _result(res)
+
+
+def divergence(n: int, h: float, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Centred-difference divergence of a cell-centred periodic field (Sec. 3.5)."""
+    f = field_zeros(n)
+    _lib().og_divergence(n, h, _ptr(u), _ptr(v), _ptr(f))
+    return f
+
+
+def project(n: int, u: np.ndarray, v: np.ndarray, rtol: float = 1e-10):
+    """Approximate cell-centred projection of (u, v) on the periodic unit
+    square, in place: Lap phi = D U, U -= G phi.  Returns (u, v, phi, Result)."""
+    p = Problem(n=n, h=1.0 / n, alpha=0.0, beta=-1.0, bc="PPPP", rtol=rtol)
+    phi = field_zeros(n)
+    res = _Result()
+    st = _lib().og_project(ctypes.byref(p._c()), _ptr(u), _ptr(v), _ptr(phi), ctypes.byref(res))
+    if st == EINVAL:
+        raise ValueError("oracle project: bad problem")
+    return u, v, phi, _result(res)

@@ -403,3 +403,53 @@ int og_solve_bc(const og_params *p, double *phi, const double *f, const double *
     free(f2);
     return st;
 }
+
+/* Cell-centred approximate projection (pyro paper, Sec. 3.5, incompressible
+ * flow): a velocity field U* = (u, v) at cell centres is split as U^d + grad
+ * phi by solving Lap phi = D U* and setting U = U* - G phi, where D and G are
+ * centred differences across two cells and Lap the 5-point operator (so
+ * D G != Lap: the projection is approximate).  Doubly periodic domain (the
+ * paper's convergence test); the Poisson problem is then singular and its
+ * zero-mean solution is taken. */
+void og_divergence(int n, double h, const double *u, const double *v, double *f) {
+    const int bc[4] = {OG_PERIODIC, OG_PERIODIC, OG_PERIODIC, OG_PERIODIC};
+    double *uu = (double *)malloc(sizeof(double) * og_field_len(n));
+    double *vv = (double *)malloc(sizeof(double) * og_field_len(n));
+    memcpy(uu, u, sizeof(double) * og_field_len(n));
+    memcpy(vv, v, sizeof(double) * og_field_len(n));
+    og_fill(n, bc, uu);
+    og_fill(n, bc, vv);
+    const double i2h = 1.0 / (2.0 * h);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
+            f[IDX(n, i, j)] = (uu[IDX(n, i + 1, j)] - uu[IDX(n, i - 1, j)]) * i2h +
+                              (vv[IDX(n, i, j + 1)] - vv[IDX(n, i, j - 1)]) * i2h;
+    free(uu);
+    free(vv);
+}
+
+/* u -= (phi[i+1] - phi[i-1]) / 2h, v -= (phi[j+1] - phi[j-1]) / 2h */
+void og_subtract_gradient(int n, double h, double *phi, double *u, double *v) {
+    const int bc[4] = {OG_PERIODIC, OG_PERIODIC, OG_PERIODIC, OG_PERIODIC};
+    og_fill(n, bc, phi);
+    const double i2h = 1.0 / (2.0 * h);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            u[IDX(n, i, j)] -= (phi[IDX(n, i + 1, j)] - phi[IDX(n, i - 1, j)]) * i2h;
+            v[IDX(n, i, j)] -= (phi[IDX(n, i, j + 1)] - phi[IDX(n, i, j - 1)]) * i2h;
+        }
+}
+
+/* In place on u, v; phi receives the zero-mean potential.  p must describe
+ * the periodic Poisson problem (alpha 0, beta -1, all sides periodic). */
+int og_project(const og_params *p, double *u, double *v, double *phi, og_result *out) {
+    if (!valid_n(p->n) || p->alpha != 0.0 || p->beta != -1.0) return OG_EINVAL;
+    for (int s = 0; s < 4; ++s)
+        if (p->bc[s] != OG_PERIODIC) return OG_EINVAL;
+    double *f = (double *)calloc(og_field_len(p->n), sizeof(double));
+    og_divergence(p->n, p->h, u, v, f);
+    int st = og_solve(p, phi, f, 0, out);
+    og_subtract_gradient(p->n, p->h, phi, u, v);
+    free(f);
+    return st;
+}

@@ -58,6 +58,9 @@ void og_bc_rhs(int n, double h, double beta, const int bc[4], const double *cons
                double *f_out);
 int og_solve_bc(const og_params *p, double *phi, const double *f, const double *const b[4], int use_guess,
                 og_result *out);
+void og_divergence(int n, double h, const double *u, const double *v, double *f);
+void og_subtract_gradient(int n, double h, double *phi, double *u, double *v);
+int og_project(const og_params *p, double *u, double *v, double *phi, og_result *out);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,17 @@ def _bc_pins():
 
 B = _bc_pins()
 
+
+def _projection_pins():
+    spec = importlib.util.spec_from_file_location("oracle_projection_pins",
+                                                  os.path.join(HERE, "test_oracle_projection.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+J = _projection_pins()
+
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
 MUTANTS = {
     "relaxation_sign": ("(f[IDX(n, i, j)] + c * nb) / diag", "(f[IDX(n, i, j)] - c * nb) / diag"),
@@ -68,6 +79,10 @@ MUTANTS = {
                               "if (bc[OG_XLO] == OG_DIRICHLET) a[IDX(n, -1, j)] += vl;"),
     "neumann_data_sign": ("if (bc[OG_XLO] == OG_NEUMANN) a[IDX(n, -1, j)] -= h * vl;",
                           "if (bc[OG_XLO] == OG_NEUMANN) a[IDX(n, -1, j)] += h * vl;"),
+    "divergence_axis": ("(vv[IDX(n, i, j + 1)] - vv[IDX(n, i, j - 1)]) * i2h;",
+                        "(vv[IDX(n, i + 1, j)] - vv[IDX(n, i - 1, j)]) * i2h;"),
+    "projection_gradient_sign": ("u[IDX(n, i, j)] -= (phi[IDX(n, i + 1, j)] - phi[IDX(n, i - 1, j)]) * i2h;",
+                                 "u[IDX(n, i, j)] += (phi[IDX(n, i + 1, j)] - phi[IDX(n, i - 1, j)]) * i2h;"),
 }
 # Not a mutant: dropping the removal of each restricted right-hand side's mean
 # (singular problems) changes the iterates only by rounding -- the residual of
@@ -91,6 +106,8 @@ BATTERY = [
     (C.test_cn_step_multiplies_an_eigenmode_by_the_closed_form_factor, ("NNNN", 2.0)),
     (B.test_side_data_solve_matches_the_extended_dense_system, ("DNND", (0.0, -1.0))),
     (B.test_side_data_solve_matches_the_extended_dense_system, ("NDDN", (1.0, 0.02))),
+    (J.test_discrete_curl_is_left_unchanged, ()),
+    (J.test_gradient_of_a_mode_in_closed_form, ()),
 ]
 
 
