@@ -140,6 +140,135 @@ def mixed_vs_plain(cc, torch, W, steps):
     return out
 
 
+def cn_diffusion(cc, torch, steps):
+    """Crank-Nicolson diffusion steps (the paper's Gaussian test problem,
+    t0 = 1e-4, phi1 = 1, phi2 = 2, k = 1, C = dt k / dx^2 = 2) on 8192^2 with
+    Neumann sides: per step the right-hand side kernel and a solve from the
+    old level to 1e-10, plain FP64 and mixed precision."""
+    n = 8192
+    h = 1.0 / n
+    dt = 2.0 * h * h
+    x = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) * h
+    r2 = (x[None, :] - 0.5) ** 2 + (x[:, None] - 0.5) ** 2
+    g0 = (1e-4 / (0.0 + 1e-4)) * torch.exp(-0.25 * r2 / 1e-4) + 1.0
+    out = {}
+    for name, prec in (("plain_fp64", cc.FP64), ("mixed", cc.MIXED)):
+        plan = cc.Plan(cc.Problem(n=n, bc=("N",) * 4, alpha=1.0, beta=dt / 2, rtol=1e-10, prec=prec))
+        phi, work = cc.field(n), cc.field(n)
+        phi[1:n + 1, 1:n + 1] = g0
+        cc.ccmg_plan_autotune(plan, phi, work)
+        for _ in range(2):
+            r = cc.ccmg_cn_step(plan, phi, work)
+            assert r.status == cc.OK, r
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc = 0
+        for _ in range(steps):
+            r = cc.ccmg_cn_step(plan, phi, work)
+            assert r.status == cc.OK, r
+            cyc += r.cycles
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        cc.ccmg_plan_profile(plan, True)
+        for _ in range(3):
+            cc.ccmg_cn_step(plan, phi, work)
+        st = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+        cc.ccmg_plan_profile(plan, False)
+        k = st["cn_rhs"]
+        avg = k["ms"] / k["launches"]
+        out[name] = dict(ms_per_step=round(1e3 * dt_s / steps, 3), cycles_per_step=cyc / steps,
+                         cell_steps_per_s=n * n * steps / dt_s,
+                         cn_rhs=dict(avg_ms=round(avg, 5), gbs=round(k["bytes"] / k["launches"] / (avg * 1e-3) / 1e9, 1)))
+        del plan, phi, work
+        torch.cuda.empty_cache()
+    out["speedup_mixed"] = round(out["plain_fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"], 3)
+    log(f"CN diffusion 8192^2: plain {out['plain_fp64']['ms_per_step']} ms/step "
+        f"({out['plain_fp64']['cycles_per_step']:.1f} cyc), mixed {out['mixed']['ms_per_step']} ms/step, "
+        f"rhs kernel {out['plain_fp64']['cn_rhs']['gbs']} GB/s")
+    return out
+
+
+def side_data_solves(cc, torch, W, reps):
+    """Inhomogeneous side data on the 4096^2 Fourier-mode right-hand side:
+    Dirichlet values on x-lo / y-hi and Neumann derivatives on x-hi / y-lo
+    (smooth periodic profiles along each side), time to 1e-10 against the same
+    solve with homogeneous sides."""
+    n = 4096
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    t = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n
+    b = [torch.sin(2 * torch.pi * t) + 0.5, torch.cos(4 * torch.pi * t), 0.3 * torch.sin(6 * torch.pi * t),
+         1.0 - t * 0.0]
+    plan = cc.Plan(cc.Problem(n=n, bc=("D", "N", "N", "D"), rtol=1e-10))
+    f = upload(cc, torch, fv)
+    phi, work = cc.field(n), cc.field(n)
+    cc.ccmg_plan_autotune(plan, f, phi)
+    out = {}
+    for name, data in (("homogeneous", None), ("with_data", b)):
+        best, cyc = float("inf"), 0
+        for _ in range(reps + 1):
+            phi.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = cc.ccmg_solve_bc(plan, f, phi, data, work)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            assert r.status == cc.OK, r
+            cyc = r.cycles
+        out[name] = dict(ms=round(1e3 * best, 3), cycles=cyc)
+    log(f"side data 4096^2: homogeneous {out['homogeneous']['ms']} ms, with data {out['with_data']['ms']} ms "
+        f"({out['with_data']['cycles']} cycles)")
+    del plan, f, phi, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def projection(cc, torch, reps):
+    """Cell-centred approximate projection on 4096^2 (doubly periodic): the
+    paper's convergence field (Minion's divergence-free u, v) plus the
+    gradient of 0.1 sin(2 pi x) cos(4 pi y); time per projection (divergence,
+    Poisson solve to 1e-10, gradient correction) and the error against the
+    divergence-free part."""
+    n = 4096
+    t = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n
+    X, Y = t[None, :], t[:, None]
+    ud = 1 - 2 * torch.cos(2 * np.pi * X) * torch.sin(2 * np.pi * Y)
+    vd = 1 + 2 * torch.sin(2 * np.pi * X) * torch.cos(2 * np.pi * Y)
+    gx = 0.2 * np.pi * torch.cos(2 * np.pi * X) * torch.cos(4 * np.pi * Y)
+    gy = -0.4 * np.pi * torch.sin(2 * np.pi * X) * torch.sin(4 * np.pi * Y)
+    plan = cc.Plan(cc.Problem(n=n, bc=("P",) * 4, rtol=1e-10))
+    u, v, phi, work = (cc.field(n) for _ in range(4))
+    u[1:n + 1, 1:n + 1] = ud + gx
+    cc.ccmg_plan_autotune(plan, u, work)
+    best, cyc = float("inf"), 0
+    for rep in range(reps + 1):
+        u[1:n + 1, 1:n + 1] = ud + gx
+        v[1:n + 1, 1:n + 1] = vd + gy
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cc.ccmg_project(plan, u, v, phi, work)
+        torch.cuda.synchronize()
+        if rep > 0:
+            best = min(best, time.perf_counter() - t0)
+        assert r.status == cc.OK, r
+        cyc = r.cycles
+    err = max((u[1:n + 1, 1:n + 1] - ud).abs().max().item(), (v[1:n + 1, 1:n + 1] - vd).abs().max().item())
+    cc.ccmg_plan_profile(plan, True)
+    u[1:n + 1, 1:n + 1] = ud + gx
+    v[1:n + 1, 1:n + 1] = vd + gy
+    cc.ccmg_project(plan, u, v, phi, work)
+    st = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+    cc.ccmg_plan_profile(plan, False)
+    kern = {name: dict(avg_ms=round(st[name]["ms"] / st[name]["launches"], 5),
+                       gbs=round(st[name]["bytes"] / st[name]["ms"] * 1e-6, 1))
+            for name in ("divergence", "subtract_gradient")}
+    out = dict(ms=round(1e3 * best, 3), cycles=cyc, max_error_vs_divergence_free=err, kernels=kern)
+    log(f"projection 4096^2: {out['ms']} ms ({cyc} cycles), error {err:.2e}, "
+        f"divergence {kern['divergence']['gbs']} GB/s, gradient {kern['subtract_gradient']['gbs']} GB/s")
+    del plan, u, v, phi, work
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_vs_sequential(cc, torch, W, reps):
     """The batched workload: 512 independent Poisson problems, sizes uniform in
     {32, ..., 1024}^2, per-axis periodic / Dirichlet sides, 16 seeded Fourier
@@ -387,6 +516,9 @@ def main():
         del f8
         also["mixed_precision"] = mixed_vs_plain(cc, torch, W, max(args.steps // 4, 3))
         also["batched"] = batched_vs_sequential(cc, torch, W, 3)
+        also["cn_diffusion"] = cn_diffusion(cc, torch, 10)
+        also["side_data"] = side_data_solves(cc, torch, W, 5)
+        also["projection"] = projection(cc, torch, 5)
         if not args.no_learned:
             also["learned"] = learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)
 

@@ -131,6 +131,61 @@ int ccmg_plan_destroy(ccmg_plan *plan);
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 
+/* ---- Inhomogeneous side data (Sec. 3.3: the V-cycle's levels use the
+ * homogeneous rules; with data the boundary value enters the ghost cell's
+ * expression).  d_b is a host array of four device arrays, one per side in
+ * the order CCMG_XLO, CCMG_XHI, CCMG_YLO, CCMG_YHI, each of n values along the
+ * side (index j on the x sides, i on the y sides), or NULL for a homogeneous
+ * side (d_b itself may be NULL: all homogeneous).  A periodic side takes
+ * NULL (else CCMG_EINVAL).  Dirichlet: the value v at the face, ghost =
+ * 2 v - phi.  Neumann: the derivative d along +x (x sides) or +y (y sides) at
+ * the face, ghost = phi - h d on a lo side and phi + h d on a hi side.  The
+ * arrays are only read. */
+/* d_f_out = d_f plus (beta / h^2) times the data part of each ghost next to
+ * a cell: the right-hand side of the equivalent homogeneous problem.  Out of
+ * place, same pitch, asynchronous. */
+int ccmg_bc_rhs(ccmg_plan *plan, const double *d_f, double *d_f_out, ptrdiff_t pitch, const double *const d_b[4]);
+/* Ghost cells of d_phi (finest level) from its valid cells with the data. */
+int ccmg_fill_ghosts_bc(ccmg_plan *plan, double *d_phi, ptrdiff_t pitch, const double *const d_b[4]);
+/* ccmg_solve of the problem with side data: d_work <- ccmg_bc_rhs(d_f), the
+ * solve on d_work (its stop test uses ||r|| / ||d_work||, which stays
+ * meaningful when f = 0 and only the data drive the solution), then the
+ * returned field's ghosts filled with the data.  d_work: caller-owned
+ * scratch of the same layout, distinct from d_f and d_phi.  Singular
+ * problems need compatible data (the shifted right-hand side sums to 0). */
+int ccmg_solve_bc(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+                  const double *const d_b[4], double *d_work, ccmg_result *out);
+
+/* ---- Cell-centred approximate projection (Sec. 3.5, incompressible flow).
+ * In place on a cell-centred velocity (d_u, d_v) of the doubly periodic
+ * square: d_work <- D U (centred differences across two cells), then
+ * ccmg_solve(plan, d_work, d_phi) for Lap phi = D U (zero-mean phi, ghosts
+ * filled), then U -= G phi (the same centred differences).  D G differs from
+ * the 5-point Lap, so D U is small afterwards, not zero.  The plan must be the
+ * periodic Poisson problem (alpha 0, beta -1, all sides periodic), else
+ * CCMG_EINVAL, as are NULL or coinciding arrays.  Ghost cells of d_u, d_v are
+ * not read or written; all four arrays share one pitch.  Blocks like
+ * ccmg_solve. */
+int ccmg_project(ccmg_plan *plan, double *d_u, double *d_v, ptrdiff_t pitch, double *d_phi, double *d_work,
+                 ccmg_result *out);
+
+/* ---- Crank-Nicolson implicit diffusion (Sec. 3.4).
+ * A step of phi_t = k Lap phi averages k Lap phi over the old and new time
+ * levels; with beta = k dt / 2 the new level solves the Helmholtz problem
+ * (1 - beta Lap) phi' = phi + beta Lap phi.  Both calls use a plan made for
+ * alpha = 1, beta = k dt / 2 (the plan's sides, spacing and precision). */
+/* d_f = d_phi + beta Lap d_phi on the finest level's valid cells, with the
+ * plan's side rules applied where a neighbour is read (d_phi's ghost cells
+ * are not read; d_f's are not written).  Out of place, same pitch.
+ * Asynchronous on the plan's stream.  CCMG_EINVAL for NULL or equal pointers
+ * or a bad pitch. */
+int ccmg_cn_rhs(ccmg_plan *plan, const double *d_phi, double *d_f, ptrdiff_t pitch);
+/* One step in place: d_work <- the right-hand side of d_phi, then
+ * ccmg_solve(plan, d_work, d_phi, pitch, use_guess = 1, out) -- the old level
+ * is the initial guess.  d_work: caller-owned scratch of the same layout.
+ * CCMG_EINVAL also when the plan's alpha is not 1.  Blocks like ccmg_solve. */
+int ccmg_cn_step(ccmg_plan *plan, double *d_phi, double *d_work, ptrdiff_t pitch, ccmg_result *out);
+
 /* Exactly one V-cycle (FP64 plans) or one refinement step (MIXED plans) on
  * the finest level, in place on d_phi, without a stop test.  Asynchronous. */
 int ccmg_vcycle(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
@@ -278,7 +333,9 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  * fused launches: "finest_fused" (prolongation + 2 relaxations + residual
  * norm [+ that iterate kept], then 2 relaxations + residual + restriction);
  * MIXED steps with several inner cycles: "mixed_finest_fused" (the same in
- * FP32 between two inner cycles, without norm or kept iterate).
+ * FP32 between two inner cycles, without norm or kept iterate); the
+ * Crank-Nicolson right-hand side "cn_rhs"; the projection's "divergence" and
+ * "subtract_gradient" passes.
  * `bytes` is the algorithmic traffic of one launch: each valid cell of each
  * array the launch reads or writes, counted once (ghost cells and halo
  * re-reads excluded). */

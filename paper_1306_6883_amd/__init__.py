@@ -101,6 +101,13 @@ def lib():
         L.ccmg_plan_autotune.argtypes = [vp, dp, dp, pd]
         ip = ctypes.POINTER(ctypes.c_int)
         L.ccmg_plan_shapes.argtypes = [vp, ip, ip, ip, ip, i]
+        b4 = ctypes.c_void_p * 4
+        L.ccmg_bc_rhs.argtypes = [vp, dp, dp, pd, b4]
+        L.ccmg_fill_ghosts_bc.argtypes = [vp, dp, pd, b4]
+        L.ccmg_solve_bc.argtypes = [vp, dp, dp, pd, i, b4, dp, ctypes.POINTER(ccmg_result)]
+        L.ccmg_project.argtypes = [vp, dp, dp, pd, dp, dp, ctypes.POINTER(ccmg_result)]
+        L.ccmg_cn_rhs.argtypes = [vp, dp, dp, pd]
+        L.ccmg_cn_step.argtypes = [vp, dp, dp, pd, ctypes.POINTER(ccmg_result)]
         L.ccmg_plan_fused_shape.argtypes = [vp, i, ip, ip]
         L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
         L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
@@ -247,6 +254,87 @@ def ccmg_solve(plan: Plan, f: torch.Tensor, phi: torch.Tensor, use_guess: bool =
     r = ccmg_result()
     st = lib().ccmg_solve(plan.handle, fp, pp, pitch, int(use_guess), ctypes.byref(r))
     _check(st, "ccmg_solve", allow=(OK, NOT_CONVERGED))
+    hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
+
+
+def _side_data(plan: Plan, b) -> "ctypes.Array":
+    """Four 1-d FP64 device tensors of n values (or None) -> the host array
+    of device pointers the library takes."""
+    arr = (ctypes.c_void_p * 4)()
+    for s_, v in enumerate(b or [None] * 4):
+        if v is None:
+            arr[s_] = None
+            continue
+        if v.dtype != torch.float64 or not v.is_cuda or v.numel() != plan.n or not v.is_contiguous():
+            raise ValueError("side data: contiguous float64 device tensors of n values")
+        arr[s_] = v.data_ptr()
+    return arr
+
+
+def ccmg_bc_rhs(plan: Plan, f: torch.Tensor, f_out: torch.Tensor, b) -> None:
+    fp, pitch = _field_args(f, plan.n)
+    op, pitch2 = _field_args(f_out, plan.n)
+    if pitch != pitch2:
+        raise ValueError("f and f_out must share one pitch")
+    _check(lib().ccmg_bc_rhs(plan.handle, fp, op, pitch, _side_data(plan, b)), "ccmg_bc_rhs")
+
+
+def ccmg_fill_ghosts_bc(plan: Plan, phi: torch.Tensor, b) -> None:
+    pp, pitch = _field_args(phi, plan.n)
+    _check(lib().ccmg_fill_ghosts_bc(plan.handle, pp, pitch, _side_data(plan, b)), "ccmg_fill_ghosts_bc")
+
+
+def ccmg_solve_bc(plan: Plan, f: torch.Tensor, phi: torch.Tensor, b, work: torch.Tensor,
+                  use_guess: bool = False) -> Result:
+    """Solve with side data b: four 1-d device tensors of n values (Dirichlet
+    face values / Neumann derivatives) or None per side (x-lo, x-hi, y-lo,
+    y-hi); `work` is scratch of f's layout."""
+    fp, pitch = _field_args(f, plan.n)
+    pp, pitch2 = _field_args(phi, plan.n)
+    wp, pitch3 = _field_args(work, plan.n)
+    if not (pitch == pitch2 == pitch3):
+        raise ValueError("f, phi and work must share one pitch")
+    r = ccmg_result()
+    st = lib().ccmg_solve_bc(plan.handle, fp, pp, pitch, int(use_guess), _side_data(plan, b), wp, ctypes.byref(r))
+    _check(st, "ccmg_solve_bc", allow=(OK, NOT_CONVERGED))
+    hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
+
+
+def ccmg_project(plan: Plan, u: torch.Tensor, v: torch.Tensor, phi: torch.Tensor, work: torch.Tensor) -> Result:
+    """Approximate cell-centred projection of (u, v) in place (periodic
+    Poisson plan); phi receives the potential, work is scratch."""
+    ptrs = [_field_args(t, plan.n) for t in (u, v, phi, work)]
+    if len({p_[1] for p_ in ptrs}) != 1:
+        raise ValueError("u, v, phi and work must share one pitch")
+    r = ccmg_result()
+    st = lib().ccmg_project(plan.handle, ptrs[0][0], ptrs[1][0], ptrs[0][1], ptrs[2][0], ptrs[3][0], ctypes.byref(r))
+    _check(st, "ccmg_project", allow=(OK, NOT_CONVERGED))
+    hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
+    return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
+
+
+def ccmg_cn_rhs(plan: Plan, phi: torch.Tensor, f: torch.Tensor) -> None:
+    """f = phi + beta Lap phi (the Crank-Nicolson right-hand side) with the
+    plan's beta = k dt / 2 and side rules; asynchronous."""
+    pp, pitch = _field_args(phi, plan.n)
+    fp, pitch2 = _field_args(f, plan.n)
+    if pitch != pitch2:
+        raise ValueError("phi and f must share one pitch")
+    _check(lib().ccmg_cn_rhs(plan.handle, pp, fp, pitch), "ccmg_cn_rhs")
+
+
+def ccmg_cn_step(plan: Plan, phi: torch.Tensor, work: torch.Tensor) -> Result:
+    """One Crank-Nicolson step of phi_t = k Lap phi in place (plan made with
+    alpha = 1, beta = k dt / 2); `work` is scratch of phi's layout."""
+    pp, pitch = _field_args(phi, plan.n)
+    wp, pitch2 = _field_args(work, plan.n)
+    if pitch != pitch2:
+        raise ValueError("phi and work must share one pitch")
+    r = ccmg_result()
+    st = lib().ccmg_cn_step(plan.handle, pp, wp, pitch, ctypes.byref(r))
+    _check(st, "ccmg_cn_step", allow=(OK, NOT_CONVERGED))
     hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
     return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
 

@@ -151,6 +151,25 @@ hipError_t launch_fill_ghosts_f64(double *a, long pitch, int n, const int bc[4],
 //   *done = 1 if rho <= rtol or rho is not finite.
 // Does nothing if *done is already set.  One workgroup.
 // host_rho (optional): host-mapped address that also receives rho.
+// Side data (bcdata.hip): per side its type and a device array of n values
+// (nullptr: homogeneous).
+struct BcData {
+    const double *b[4];
+    int type[4];
+};
+hipError_t launch_bc_rhs(const double *f, double *f_out, long pitch, int n, const BcData &d, double beta, double h,
+                         hipStream_t s);
+hipError_t launch_add_ghost_data(double *a, long pitch, int n, const BcData &d, double h, hipStream_t s);
+
+// Approximate projection (proj.hip), doubly periodic: f = D U; U -= G phi.
+hipError_t launch_divergence(const double *u, const double *v, double *f, long pitch, int n, double h,
+                             hipStream_t s);
+hipError_t launch_subtract_gradient(const double *phi, double *u, double *v, long pitch, int n, double h,
+                                    hipStream_t s);
+
+// Crank-Nicolson right-hand side f = phi + beta Lap phi on valid cells (cn.hip).
+hipError_t launch_cn_rhs(const double *phi, long pp, double *f, long pf, int n, const int bc[4], double beta,
+                         double h, hipStream_t s);
 hipError_t launch_cycle_end(const double *partial, int count, int n, int singular, const double *f2,
                             double rtol, double *rho_out, double *phi_mean, int *done, double *host_rho,
                             hipStream_t s);

@@ -154,15 +154,15 @@ MarchShape shape_for(int n) {
 
 // Events bracketing finest-level launches while profiling is on.
 struct KernelTimer {
-    static constexpr int kKinds = 6;
+    static constexpr int kKinds = 9;
     static constexpr int kPairs = 1024;
     bool on = false;
     std::vector<hipEvent_t> ev;          // 2 * kPairs
     int used = 0;
     int kind[kPairs];
     double bytes[kPairs];
-    int launches[kKinds] = {0, 0, 0, 0, 0, 0};
-    double ms[kKinds] = {0, 0, 0, 0, 0, 0}, tbytes[kKinds] = {0, 0, 0, 0, 0, 0};
+    int launches[kKinds] = {};
+    double ms[kKinds] = {}, tbytes[kKinds] = {};
 };
 
 constexpr int kMaxLevels = 16;
@@ -1103,6 +1103,103 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     return CCMG_OK;
 }
 
+// side data of a plan: NULL for a homogeneous side; a periodic side takes none
+static int bc_data(const ccmg_plan *P, const double *const d_b[4], BcData &d) {
+    for (int s = 0; s < 4; ++s) {
+        d.type[s] = P->p.bc[s];
+        d.b[s] = d_b ? d_b[s] : nullptr;
+        if (d.b[s] && P->p.bc[s] == CCMG_BC_PERIODIC) return CCMG_EINVAL;
+    }
+    return CCMG_OK;
+}
+
+int ccmg_bc_rhs(ccmg_plan *P, const double *d_f, double *d_f_out, ptrdiff_t pitch, const double *const d_b[4]) {
+    if (!P || !d_f || !d_f_out || d_f == d_f_out) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    BcData d;
+    if (bc_data(P, d_b, d) != CCMG_OK) return CCMG_EINVAL;
+    return hip_status(launch_bc_rhs(d_f, d_f_out, pitch, P->lay.lev[0].n, d, P->p.beta, P->lay.lev[0].h, P->stream));
+}
+
+int ccmg_fill_ghosts_bc(ccmg_plan *P, double *d_phi, ptrdiff_t pitch, const double *const d_b[4]) {
+    if (!P || !d_phi) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    BcData d;
+    if (bc_data(P, d_b, d) != CCMG_OK) return CCMG_EINVAL;
+    const int n = P->lay.lev[0].n;
+    hipError_t e = launch_fill_ghosts_f64(d_phi, pitch, n, P->p.bc, nullptr, P->stream);
+    if (e == hipSuccess) e = launch_add_ghost_data(d_phi, pitch, n, d, P->lay.lev[0].h, P->stream);
+    return hip_status(e);
+}
+
+int ccmg_solve_bc(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
+                  const double *const d_b[4], double *d_work, ccmg_result *out) {
+    ccmg_result local;
+    ccmg_result *R = out ? out : &local;
+    std::memset(R, 0, sizeof(*R));
+    if (!P || !d_f || !d_phi || !d_work || d_work == d_f || d_work == d_phi) return R->status = CCMG_EINVAL;
+    int st = ccmg_bc_rhs(P, d_f, d_work, pitch, d_b);
+    if (st != CCMG_OK) return R->status = st;
+    st = ccmg_solve(P, d_work, d_phi, pitch, use_guess, R);
+    if (st != CCMG_OK && st != CCMG_NOT_CONVERGED) return st;
+    const int g = ccmg_fill_ghosts_bc(P, d_phi, pitch, d_b);
+    if (g != CCMG_OK) return R->status = g;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return R->status = CCMG_EHIP;
+    return st;
+}
+
+int ccmg_project(ccmg_plan *P, double *d_u, double *d_v, ptrdiff_t pitch, double *d_phi, double *d_work,
+                 ccmg_result *out) {
+    ccmg_result local;
+    ccmg_result *R = out ? out : &local;
+    std::memset(R, 0, sizeof(*R));
+    if (!P || !d_u || !d_v || !d_phi || !d_work) return R->status = CCMG_EINVAL;
+    const double *arrs[4] = {d_u, d_v, d_phi, d_work};
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b)
+            if (arrs[a] == arrs[b]) return R->status = CCMG_EINVAL;
+    if (P->p.alpha != 0.0 || P->p.beta != -1.0) return R->status = CCMG_EINVAL;
+    for (int s = 0; s < 4; ++s)
+        if (P->p.bc[s] != CCMG_BC_PERIODIC) return R->status = CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return R->status = CCMG_EINVAL;
+    const int n = P->lay.lev[0].n;
+    const double h = P->lay.lev[0].h;
+    const double nn = (double)n * n;
+    int ti = P->tstart(7, 3.0 * sizeof(double) * nn);
+    hipError_t e = launch_divergence(d_u, d_v, d_work, pitch, n, h, P->stream);
+    P->tstop(ti);
+    if (e != hipSuccess) return R->status = CCMG_EHIP;
+    const int st = ccmg_solve(P, d_work, d_phi, pitch, 0, R);
+    if (st != CCMG_OK && st != CCMG_NOT_CONVERGED) return st;
+    ti = P->tstart(8, 5.0 * sizeof(double) * nn);
+    e = launch_subtract_gradient(d_phi, d_u, d_v, pitch, n, h, P->stream);
+    P->tstop(ti);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return R->status = CCMG_EHIP;
+    return st;
+}
+
+int ccmg_cn_rhs(ccmg_plan *P, const double *d_phi, double *d_f, ptrdiff_t pitch) {
+    if (!P || !d_phi || !d_f || d_phi == d_f) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    const int n = P->lay.lev[0].n;
+    const int ti = P->tstart(6, 2.0 * sizeof(double) * (double)n * n);
+    hipError_t e = launch_cn_rhs(d_phi, pitch, d_f, pitch, n, P->p.bc, P->p.beta, P->lay.lev[0].h, P->stream);
+    P->tstop(ti);
+    return hip_status(e);
+}
+
+int ccmg_cn_step(ccmg_plan *P, double *d_phi, double *d_work, ptrdiff_t pitch, ccmg_result *out) {
+    ccmg_result local;
+    ccmg_result *R = out ? out : &local;
+    std::memset(R, 0, sizeof(*R));
+    if (!P || !d_phi || !d_work || d_phi == d_work || P->p.alpha != 1.0) return R->status = CCMG_EINVAL;
+    const int st = ccmg_cn_rhs(P, d_phi, d_work, pitch);
+    if (st != CCMG_OK) return R->status = st;
+    return ccmg_solve(P, d_work, d_phi, pitch, 1, R);
+}
+
 int ccmg_plan_fused_shape(ccmg_plan *P, int kind, int *ty, int *wpb) {
     if (!P || !ty || !wpb || (kind != 2 && kind != 3)) return CCMG_EINVAL;
     const MarchShape &sh = kind == 2 ? P->shp_fused : P->shp_fused32;
@@ -1145,7 +1242,8 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     P->tcollect();
     static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post", "mixed_finest_pre",
                                                       "mixed_finest_post_ir", "finest_fused",
-                                                      "mixed_finest_fused"};
+                                                      "mixed_finest_fused", "cn_rhs", "divergence",
+                                                      "subtract_gradient"};
     *count = KernelTimer::kKinds;
     for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
         std::memset(&out[k], 0, sizeof(out[k]));
