@@ -153,6 +153,72 @@ __device__ void prolong_add(const T *E, T *P, int lg, const Sides &sd) {
 
 }  // namespace
 
+// Levels with at most 2^kWaveLg cells per side run on one wave (see coarse_body).
+constexpr int kWaveLg = 3;
+
+// One level on the way down: nu1 relaxations, residual restricted to the
+// next level (its mean removed for singular problems), next level's
+// correction zeroed.  NTW threads (the workgroup, or the first wave) take part.
+template <int NTW, typename T>
+__device__ void down_level(const CoarseArgs<T> &a, const Sides &sd, T *sP, T *sF, const int *off, int lg0, int l,
+                           double *red) {
+    const int lg = lg0 - l;
+    relax<NTW>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu1);
+    restrict_residual<NTW>(sP + off[l], sF + off[l], sF + off[l + 1], lg, sd, T(a.alpha), T(a.beta),
+                           T(a.ih2[l]));
+    if (a.singular) remove_mean<NTW>(sF + off[l + 1], lg - 1, red);
+    for (int i = threadIdx.x; i < (1 << (2 * (lg - 1))); i += NTW) sP[off[l + 1] + i] = T(0);
+    sync<NTW>();
+}
+
+// One level on the way up: prolongation of the next level's correction, nu2
+// relaxations.
+template <int NTW, typename T>
+__device__ void up_level(const CoarseArgs<T> &a, const Sides &sd, T *sP, const T *sF, const int *off, int lg0,
+                         int l) {
+    const int lg = lg0 - l;
+    prolong_add<NTW>(sP + off[l + 1], sP + off[l], lg, sd);
+    relax<NTW>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu2);
+}
+
+// Bottom: 2 x 2 grid, relaxation only, in FP64 registers of thread 0.
+// Cell q = 2y + x; its x-neighbour is q^1 and its y-neighbour q^2.  On a
+// 2 x 2 grid the periodic image of that neighbour is the same cell, and a
+// Dirichlet / Neumann ghost is -/+ the cell itself.
+template <typename T>
+__device__ void bottom(const CoarseArgs<T> &a, const Sides &sd, T *sP, const T *sF, const int *off, int L) {
+    if (threadIdx.x != 0) return;
+    const int l = L - 1;
+    const double c = a.cc[l], invd = a.invd[l];
+    double p0 = sP[off[l] + 0], p1 = sP[off[l] + 1], p2 = sP[off[l] + 2], p3 = sP[off[l] + 3];
+    const double f0 = sF[off[l] + 0], f1 = sF[off[l] + 1], f2 = sF[off[l] + 2], f3 = sF[off[l] + 3];
+    const double xl = sd.px ? 1.0 : (double)sd.sxl, xh = sd.px ? 1.0 : (double)sd.sxh;
+    const double yl = sd.py ? 1.0 : (double)sd.syl, yh = sd.py ? 1.0 : (double)sd.syh;
+    // x-ghost of a cell at x = 0 is its west side (x-lo), at x = 1 its east side (x-hi)
+    auto upd = [&](double self, double ex, double ey, double f, bool x0, bool y0) {
+        const double e = x0 ? ex : (sd.px ? ex : xh * self);
+        const double w = x0 ? (sd.px ? ex : xl * self) : ex;
+        const double nn = y0 ? ey : (sd.py ? ey : yh * self);
+        const double s = y0 ? (sd.py ? ey : yl * self) : ey;
+        return (f + c * (((e + w) + nn) + s)) * invd;
+    };
+    for (int it = 0; it < a.nu_bottom; ++it) {
+        const double q0 = upd(p0, p1, p2, f0, true, true);    // red (0,0)
+        const double q3 = upd(p3, p2, p1, f3, false, false);  // red (1,1)
+        const double q1 = upd(p1, q0, q3, f1, false, true);   // black (1,0)
+        const double q2 = upd(p2, q3, q0, f2, true, false);   // black (0,1)
+        // an iteration that changes nothing is a fixed point: the remaining
+        // iterations would return exactly these values
+        const bool same = q0 == p0 && q1 == p1 && q2 == p2 && q3 == p3;
+        p0 = q0, p1 = q1, p2 = q2, p3 = q3;
+        if (same) break;
+    }
+    sP[off[l] + 0] = T(p0);
+    sP[off[l] + 1] = T(p1);
+    sP[off[l] + 2] = T(p2);
+    sP[off[l] + 3] = T(p3);
+}
+
 template <int NT, typename T>
 __device__ void coarse_body(const CoarseArgs<T> &a) {
     __shared__ T sP[kCoarseMax * kCoarseMax * 4 / 3 + 8];
@@ -185,58 +251,22 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
     sync<NT>();
     if (a.sub_top_mean) remove_mean<NT>(sF, lg0, red);
 
-    // down
-    for (int l = 0; l + 1 < L; ++l) {
-        const int lg = lg0 - l;
-        relax<NT>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu1);
-        restrict_residual<NT>(sP + off[l], sF + off[l], sF + off[l + 1], lg, sd, T(a.alpha), T(a.beta),
-                          T(a.ih2[l]));
-        if (a.singular) remove_mean<NT>(sF + off[l + 1], lg - 1, red);
-        for (int i = threadIdx.x; i < (1 << (2 * (lg - 1))); i += NT) sP[off[l + 1] + i] = T(0);
-        sync<NT>();
-    }
-    // bottom: 2 x 2 grid, relaxation only, in FP64 registers of one thread.
-    // Cell q = 2y + x; its x-neighbour is q^1 and its y-neighbour q^2.  On a
-    // 2 x 2 grid the periodic image of that neighbour is the same cell, and a
-    // Dirichlet / Neumann ghost is -/+ the cell itself.
-    if (threadIdx.x == 0) {
-        const int l = L - 1;
-        const double c = a.cc[l], invd = a.invd[l];
-        double p0 = sP[off[l] + 0], p1 = sP[off[l] + 1], p2 = sP[off[l] + 2], p3 = sP[off[l] + 3];
-        const double f0 = sF[off[l] + 0], f1 = sF[off[l] + 1], f2 = sF[off[l] + 2], f3 = sF[off[l] + 3];
-        const double xl = sd.px ? 1.0 : (double)sd.sxl, xh = sd.px ? 1.0 : (double)sd.sxh;
-        const double yl = sd.py ? 1.0 : (double)sd.syl, yh = sd.py ? 1.0 : (double)sd.syh;
-        // x-ghost of a cell at x = 0 is its west side (x-lo), at x = 1 its east side (x-hi)
-        auto upd = [&](double self, double ex, double ey, double f, bool x0, bool y0) {
-            const double e = x0 ? ex : (sd.px ? ex : xh * self);
-            const double w = x0 ? (sd.px ? ex : xl * self) : ex;
-            const double nn = y0 ? ey : (sd.py ? ey : yh * self);
-            const double s = y0 ? (sd.py ? ey : yl * self) : ey;
-            return (f + c * (((e + w) + nn) + s)) * invd;
-        };
-        for (int it = 0; it < a.nu_bottom; ++it) {
-            const double q0 = upd(p0, p1, p2, f0, true, true);    // red (0,0)
-            const double q3 = upd(p3, p2, p1, f3, false, false);  // red (1,1)
-            const double q1 = upd(p1, q0, q3, f1, false, true);   // black (1,0)
-            const double q2 = upd(p2, q3, q0, f2, true, false);   // black (0,1)
-            // an iteration that changes nothing is a fixed point: the remaining
-            // iterations would return exactly these values
-            const bool same = q0 == p0 && q1 == p1 && q2 == p2 && q3 == p3;
-            p0 = q0, p1 = q1, p2 = q2, p3 = q3;
-            if (same) break;
-        }
-        sP[off[l] + 0] = T(p0);
-        sP[off[l] + 1] = T(p1);
-        sP[off[l] + 2] = T(p2);
-        sP[off[l] + 3] = T(p3);
+    // Levels of at most 8 x 8 cells (and the bottom) run on the first wave
+    // alone: 64 lanes cover such a level's colour in one pass, and a wave
+    // needs no workgroup barrier between phases.  lw = first such level.
+    int lw = 0;
+    while (lw < L && lg0 - lw > kWaveLg) ++lw;
+    // down, whole workgroup
+    for (int l = 0; l < lw && l + 1 < L; ++l) down_level<NT>(a, sd, sP, sF, off, lg0, l, red);
+    if (NT == 64 || threadIdx.x < 64) {
+        for (int l = lw; l + 1 < L; ++l) down_level<64>(a, sd, sP, sF, off, lg0, l, red);
+        bottom(a, sd, sP, sF, off, L);
+        sync<64>();
+        for (int l = L - 2; l >= lw; --l) up_level<64>(a, sd, sP, sF, off, lg0, l);
     }
     sync<NT>();
-    // up
-    for (int l = L - 2; l >= 0; --l) {
-        const int lg = lg0 - l;
-        prolong_add<NT>(sP + off[l + 1], sP + off[l], lg, sd);
-        relax<NT>(sP + off[l], sF + off[l], lg, sd, T(a.cc[l]), T(a.invd[l]), a.nu2);
-    }
+    // up, whole workgroup
+    for (int l = (lw < L - 1 ? lw : L - 1) - 1; l >= 0; --l) up_level<NT>(a, sd, sP, sF, off, lg0, l);
     // top level out
     for (int i = threadIdx.x; i < n0 * n0; i += NT) {
         const int y = i >> lg0, x = i - (y << lg0);
