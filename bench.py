@@ -215,8 +215,10 @@ def side_data_solves(cc, torch, W, reps):
             assert r.status == cc.OK, r
             cyc = r.cycles
         out[name] = dict(ms=round(1e3 * best, 3), cycles=cyc)
-    log(f"side data 4096^2: homogeneous {out['homogeneous']['ms']} ms, with data {out['with_data']['ms']} ms "
-        f"({out['with_data']['cycles']} cycles)")
+    # (the tolerance is relative to the shifted right-hand side, which the data
+    # enlarge: the two solves are different problems, not a speed comparison)
+    log(f"side data 4096^2: homogeneous {out['homogeneous']['ms']} ms ({out['homogeneous']['cycles']} cycles), "
+        f"with data {out['with_data']['ms']} ms ({out['with_data']['cycles']} cycles)")
     del plan, f, phi, work
     torch.cuda.empty_cache()
     return out

@@ -427,11 +427,12 @@ def ccmg_plan_profile(plan: Plan, enable: bool) -> None:
 
 def ccmg_plan_kernel_stats(plan: Plan) -> list:
     """[{name, launches, ms, bytes}] summed since profiling was enabled."""
-    arr = (ccmg_kernel_stat * 8)()
     cnt = ctypes.c_int()
-    _check(lib().ccmg_plan_kernel_stats(plan.handle, arr, 8, ctypes.byref(cnt)), "ccmg_plan_kernel_stats")
+    _check(lib().ccmg_plan_kernel_stats(plan.handle, None, 0, ctypes.byref(cnt)), "ccmg_plan_kernel_stats")
+    arr = (ccmg_kernel_stat * max(1, cnt.value))()
+    _check(lib().ccmg_plan_kernel_stats(plan.handle, arr, cnt.value, ctypes.byref(cnt)), "ccmg_plan_kernel_stats")
     return [dict(name=arr[k].name.decode(), launches=arr[k].launches, ms=arr[k].ms, bytes=arr[k].bytes)
-            for k in range(min(cnt.value, 8))]
+            for k in range(cnt.value)]
 
 
 class Batch:
