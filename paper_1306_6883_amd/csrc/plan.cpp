@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kMinTy = 8;       // smallest rows-per-tile the shape picker uses
 constexpr int kMinOutw = 104;   // narrowest output width of any march variant (the fused one)
-constexpr int kStatBlocks = 512;
+constexpr int kStatBlocks = 2048;  // f statistics: workgroups (8 waves per SIMD)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 long pitch_for(int n) { return (long)((n + 2 + 31) & ~31); }

@@ -106,18 +106,26 @@ hipError_t launch_cycle_end(const double *partial, int count, int n, int singula
 __global__ __launch_bounds__(kRed) void k_fstats(const double *f, long pitch, int n, double *out) {
     __shared__ double red[4];
     double s = 0.0, sa = 0.0, s2 = 0.0, bad = 0.0;
+    auto add = [&](double v) {
+        if (!isfinite(v)) {
+            bad += 1.0;
+            return;
+        }
+        s += v;
+        sa += fabs(v);
+        s2 += v * v;
+    };
     for (int y = blockIdx.x; y < n; y += gridDim.x) {
         const double *row = f + (long)(y + 1) * pitch + 1;
-        for (int x = threadIdx.x; x < n; x += kRed) {
-            const double v = row[x];
-            if (!isfinite(v)) {
-                bad += 1.0;
-                continue;
-            }
-            s += v;
-            sa += fabs(v);
-            s2 += v * v;
+        int x = threadIdx.x;
+        for (; x + 3 * kRed < n; x += 4 * kRed) {  // four loads in flight, added in column order
+            const double v0 = row[x], v1 = row[x + kRed], v2 = row[x + 2 * kRed], v3 = row[x + 3 * kRed];
+            add(v0);
+            add(v1);
+            add(v2);
+            add(v3);
         }
+        for (; x < n; x += kRed) add(row[x]);
     }
     s = block_sum256(s, red);
     sa = block_sum256(sa, red);
@@ -134,7 +142,20 @@ __global__ __launch_bounds__(kRed) void k_fstats(const double *f, long pitch, in
 __global__ __launch_bounds__(kRed) void k_reduce4(const double *p, int count, double *out4) {
     __shared__ double red[4];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < count; i += kRed)
+    int i = threadIdx.x;
+    for (; i + 3 * kRed < count; i += 4 * kRed) {  // four quadruples in flight, added in order
+        double4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = *reinterpret_cast<const double4 *>(p + 4 * (i + k * kRed));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s[0] += v[k].x;
+            s[1] += v[k].y;
+            s[2] += v[k].z;
+            s[3] += v[k].w;
+        }
+    }
+    for (; i < count; i += kRed)
         for (int q = 0; q < 4; ++q) s[q] += p[4 * i + q];
     for (int q = 0; q < 4; ++q) {
         const double t = block_sum256(s[q], red);
