@@ -461,6 +461,8 @@ def main():
                     help="run only the learned-guess leg and print its result (profiling aid)")
     ap.add_argument("--learned-solves", type=int, default=20000, help="training solves of the learned leg")
     ap.add_argument("--learned-steps", type=int, default=30000, help="training steps of the learned leg")
+    ap.add_argument("--next-rows-only", action="store_true",
+                    help="only the Crank-Nicolson, side-data and projection legs (one JSON line of their own)")
     ap.add_argument("--fused-shape", type=str, default=None,
                     help="TY,WPB: rows per band and waves per workgroup of the 4096^2 fused launch, "
                          "instead of the autotuner's choice (for counter runs)")
@@ -479,6 +481,10 @@ def main():
     if args.learned_only:
         print(json.dumps({"learned": learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)}),
               flush=True)
+        return
+    if args.next_rows_only:
+        print(json.dumps({"cn_diffusion": cn_diffusion(cc, torch, 10), "side_data": side_data_solves(cc, torch, W, 5),
+                          "projection": projection(cc, torch, 5)}), flush=True)
         return
     n = 4096
     log("generating inputs")
