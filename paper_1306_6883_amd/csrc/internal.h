@@ -29,15 +29,15 @@ enum Post {
 template <typename T>
 struct MarchArgs {
     const T *f;          // right-hand side, ghosted, pitch pf
-    long pf;
+    int pf;
     const T *phi_in;     // starting iterate (ignored when the launch assumes zero)
-    long pin;
+    int pin;
     T *phi_out;          // relaxed iterate (valid cells only)
-    long pout;
+    int pout;
     const T *ec;         // coarse correction e (level l+1) for the prolongation
-    long pc;
+    int pc;
     T *aux;              // POST_RESTRICT: coarse rhs (level l+1); POST_RESID: r
-    long paux;
+    int paux;
     double *partial;     // per-tile sums: RESTRICT -> sum of coarse rhs; NORM -> sum r^2, sum phi
     const double *fmean_part;  // partial sums whose total / (n*n) is subtracted from f (or null)
     int fmean_count;
@@ -51,20 +51,20 @@ struct MarchArgs {
     int strips, chunks, ty, outw, ntiles, groups_per_xcd;
     // mixed precision (POST_IR / POST_R32)
     const double *q_in;  // FP64 iterate, read (POST_IR)
-    long pq_in;
+    int pq_in;
     double *q_out;       // FP64 iterate + e, written (POST_IR)
-    long pq_out;
+    int pq_out;
     const double *g;     // FP64 right-hand side (POST_IR)
-    long pg;
+    int pg;
     float *r_out;        // FP32 copy of the FP64 residual
-    long pr;
+    int pr;
     double *partial3;    // per tile: sum of the FP32 residual (mean removal of singular problems)
     double alpha64, beta64, ih2_64;
     int q_zero;          // POST_IR: the FP64 iterate is zero (q_in is not used)
     int *count_out;      // if set, receives ntiles (producers of per-tile sums)
     // POST_FUSED: the iterate after the post-smoothing and its per-tile norm sums
     T *phi_mid;
-    long pmid;
+    int pmid;
     double *partial_norm;
 };
 
