@@ -134,6 +134,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     const int nm = tl.nm, nc = tl.nc;
     const bool py = tl.py;
     const int ys = tl.ys, ye = tl.ye, y0 = tl.y0, y1 = tl.y1;
+    // row y is one of the tile's output rows: one unsigned compare of
+    // wave-uniform values
+    const unsigned nrows = (unsigned)(y1 - y0);
+    auto inrow = [&](int y) { return (unsigned)(y - y0) < nrows; };
     const T sxl = a.bc[CCMG_XLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
@@ -347,7 +351,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             s1 = syl * p1;
                         }
                     }
-                    if (y >= y0 && y < y1 && tl.outl) {
+                    if (inrow(y) && tl.outl) {
                         const T ih2 = a.ih2;
                         const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
                         const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
@@ -375,12 +379,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 if constexpr (IR) {
                     Q0[kk] += (double)P0[kk];
                     Q1[kk] += (double)P1[kk];
-                    if (y >= y0 && y < y1 && tl.outl) {
+                    if (inrow(y) && tl.outl) {
                         double *o = a.q_out + row_off(y + 1, a.pq_out);
                         o[1 + tl.x0] = Q0[kk];
                         o[2 + tl.x0] = Q1[kk];
                     }
-                } else if (a.phi_out && y >= y0 && y < y1 && tl.outl) {
+                } else if ((FUSED || a.phi_out) && inrow(y) && tl.outl) {  // the fused launch always stores
                     T *o = a.phi_out + row_off(y + 1, a.pout);
                     o[1 + tl.x0] = P0[kk];
                     o[2 + tl.x0] = P1[kk];
@@ -389,7 +393,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             // 5. residual of the finished rows and what is made from it
             if constexpr (IR) {
                 const int y = t - C::LAGR;
-                if (y >= y0 && y < y1) {
+                if (inrow(y)) {
                     constexpr int kk = (k - C::LAGR + 2 * W) % W;
                     constexpr int km = (k - C::LAGR - 1 + 2 * W) % W;
                     constexpr int kp = (k - C::LAGR + 1 + 2 * W) % W;
@@ -428,7 +432,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 }
             } else if constexpr (POST != POST_NONE) {
                 const int y = t - C::LAGR;
-                if (y >= y0 && y < y1) {
+                if (inrow(y)) {
                     constexpr int kk = (k - C::LAGR + 2 * W) % W;
                     constexpr int km = (k - C::LAGR - 1 + 2 * W) % W;
                     constexpr int kp = (k - C::LAGR + 1 + 2 * W) % W;
