@@ -110,7 +110,9 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
             v.a = take(bytes);
             v.b = take(bytes);
             v.f = take(bytes);
-            v.fpart_cap = max_tiles(v.n * 2);
+            // partial sums from the launch on the level above, or from a
+            // two-level launch two levels above ((4n / 32)^2 blocks)
+            v.fpart_cap = std::max(max_tiles(v.n * 2), (v.n / 8) * (v.n / 8));
             v.fpart = take(sizeof(double) * v.fpart_cap);
         }
     }
@@ -173,6 +175,7 @@ struct ccmg_plan {
     MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
+    bool pair_down[kMaxLevels] = {};  // levels l, l+1 pre-smoothed in one launch (2-D tiles)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
     double *drho = nullptr;   // ... its device address
     Layout lay;
@@ -242,6 +245,24 @@ int mixed_inner_max(const ccmg_plan *P) {
     const char *e = std::getenv("CCMG_MIXED_INNER");
     const int v = e ? std::atoi(e) : 3;
     return v < 1 ? 1 : (v > 8 ? 8 : v);
+}
+// Pairs of levels whose pre-smoothing runs in one launch: from the first level
+// below the finest with at most kPairMaxN cells per side, (l, l+1), (l+2, l+3),
+// ... while level l has at least 128 cells per side and l+1 is not in the
+// one-workgroup tail.  Off unless the environment sets CCMG_PAIR=1 (read per
+// plan): on the MI355X the pair launch (17-19 us) takes as long as the two
+// launches it replaces, its longer chain of LDS sweeps and barriers eating
+// the saved launch.
+constexpr int kPairMaxN = 512;
+void choose_pairs(ccmg_plan *P) {
+    for (int l = 0; l < kMaxLevels; ++l) P->pair_down[l] = false;
+    const char *e = std::getenv("CCMG_PAIR");
+    if (!e || e[0] != '1') return;
+    const Layout &lay = P->lay;
+    int l = 1;
+    while (l < lay.lt && lay.lev[l].n > kPairMaxN) ++l;
+    for (; l + 1 < lay.lt && l + 1 < kMaxLevels; l += 2)
+        if (lay.lev[l].n >= 128) P->pair_down[l] = true;
 }
 double fused_keep_factor() {
     const char *e = std::getenv("CCMG_FUSED_KEEP");
@@ -394,6 +415,37 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     if (io.coarse_only) fpart_count[1] = io.f1_count;
     for (int l = io.coarse_only ? 1 : 0; l < lay.lt; ++l) {
         setup_bufs(l);
+        if (l >= 1 && l + 1 < lay.lt && P->pair_down[l] && (P->p.nu1 == 1 || P->p.nu1 == 2)) {
+            // levels l and l+1 pre-smoothed (from zero) in one launch
+            setup_bufs(l + 1);
+            MarchArgs<T> a{}, b{};
+            level_consts(P, l, a);
+            level_consts(P, l + 1, b);
+            const Buf<T> fb = fptr(l);
+            a.f = fb.p;
+            a.pf = fb.pitch;
+            fmean(l, a);
+            a.phi_out = other[l].p;
+            a.pout = other[l].pitch;
+            a.aux = P->at<T>(lay.lev[l + 1].f);
+            a.paux = lay.lev[l + 1].pitch;
+            a.partial = P->at<double>(lay.lev[l + 1].fpart);
+            a.skip = io.skip;
+            b.phi_out = other[l + 1].p;
+            b.pout = other[l + 1].pitch;
+            b.aux = P->at<T>(lay.lev[l + 2].f);
+            b.paux = lay.lev[l + 2].pitch;
+            b.partial = P->at<double>(lay.lev[l + 2].fpart);
+            int nb = 0;
+            e = launch_pair_down<T>(a, b, P->p.nu1, s, &nb);
+            if (e != hipSuccess) return e;
+            fpart_count[l + 1] = nb;
+            fpart_count[l + 2] = nb;
+            std::swap(cur[l], other[l]);
+            std::swap(cur[l + 1], other[l + 1]);
+            ++l;
+            continue;
+        }
         const MarchShape sh = P->shp_pre[l];
         const std::vector<int> chain = split_nu(P->p.nu1);
         bool zero = (l > 0) || io.zero;
@@ -847,6 +899,7 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     }
     P->shp_fused = shape_for(P->lay.lev[0].n);
     P->shp_fused32 = shape_for(P->lay.lev[0].n);
+    choose_pairs(P);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
     if (e == hipSuccess)

@@ -122,10 +122,11 @@ def test_mixed_guess_and_history():
 
 
 @pytest.mark.parametrize("bc", ["DDDD", "PPPP", "DNPP"])
-def test_mixed_tile_kernel_matches_row_march(bc):
+def test_mixed_tile_kernel_matches_row_march(bc, monkeypatch):
     """The FP32 inner cycles give the same iterate whether the levels below the
     finest run as row-march bands or as 2-D LDS tiles (bitwise; singular
     problems to rounding, their coarse means being sums grouped by tile)."""
+    monkeypatch.setenv("CCMG_PAIR", "0")  # every level's own launches
     n = 512
     fv = np.random.default_rng(33).standard_normal((n, n))
     if exact.is_singular(0.0, bc):
