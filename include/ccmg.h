@@ -127,7 +127,9 @@ int ccmg_plan_destroy(ccmg_plan *plan);
  * pre-smoothing of the next in one launch (the same iterates; environment
  * CCMG_FUSED=0 turns this off, CCMG_FUSED_KEEP sets how far above the
  * tolerance the extrapolated residual may be for a cycle's own iterate to be
- * kept, default 100). */
+ * kept, default 100).  CCMG_PAIR=1 (read when a plan is created) makes the
+ * pre-smoothing of pairs of levels with 128..512 cells per side one launch
+ * of 2-D tiles (same iterates; off by default: not faster on the MI355X). */
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 
