@@ -251,8 +251,9 @@ int ccmg_batch_shapes(ccmg_batch *batch, int *sizes, int *ty, int max, int *coun
 /* ---- learned initial guess.
  * A linear network of six 3x3 convolutions with circular padding and
  * dilations 1, 2, 4, 8, 16, 32 on a 128 x 128 grid (channels 1 -> 32 -> ... ->
- * 32 -> 1, no biases; BF16 weights and operands, FP32 accumulation on the
- * matrix cores, activations carried as BF16 hi + lo pairs)
+ * 32 -> 1, no biases; the 32 -> 32 layers on the matrix cores with weights
+ * and activations as BF16 hi + lo pairs and FP32 accumulation, the first and
+ * last layers with FP32 weights)
  * maps a right-hand side, averaged onto that grid and divided by its RMS, to
  * the solution averaged the same way.  The guess for an n x n problem
  * (n >= 256, power of two) is that output times the RMS, prolonged back to

@@ -10,9 +10,12 @@ A convolution here is the cross-correlation
 
 with tap = 3 (dy + 1) + (dx + 1), indices taken modulo G.  Loss: mean squared
 error.  `bf=True` applies the roundings of the GPU path (bfloat16, round to
-nearest even), with sums kept in FP64: weights rounded to bfloat16; the
-activations between layers carried as a pair of bfloat16 values
-(hi = bf16(v), lo = bf16(v - hi)); the network input unrounded; the output
+nearest even), with sums kept in FP64.  Forward: the first and last layers'
+weights unrounded; those of the 32 -> 32 layers carried as a bfloat16 pair
+(hi = bf16(w), lo = bf16(w - hi)) whose lo part multiplies only the
+activations' hi part; the activations between layers carried as a pair of
+bfloat16 values (hi = bf16(v), lo = bf16(v - hi)); the network input
+unrounded.  Backward: weights rounded to bfloat16 (hi only); the output
 gradient and the back-propagated activation gradients rounded to bfloat16;
 the weight gradients of the 32 -> 32 layers formed from the activations'
 hi parts, those of the first and last layer from the full input / pair.
@@ -104,12 +107,15 @@ def conv_w(g: np.ndarray, a: np.ndarray, d: int) -> np.ndarray:
 def forward(params: np.ndarray, x: np.ndarray, bf: bool = False):
     """x: [B, G, G] -> (y [B, G, G], layer inputs a0 .. a5, their hi parts).
     Without `bf` the hi parts are the inputs themselves."""
-    rw = bf16 if bf else (lambda v: v)
-    ws = [rw(w) for w in split(params)]
+    ws = split(params)
     a = [x[..., None]]
     hi = [x[..., None]]
     for l in range(5):
-        v = conv(a[-1], ws[l], DIL[l])
+        if bf and l > 0:
+            wh = bf16(ws[l])
+            v = conv(a[-1], wh, DIL[l]) + conv(hi[-1], bf16(ws[l] - wh), DIL[l])
+        else:
+            v = conv(a[-1], ws[l], DIL[l])
         if bf:
             h = bf16(v)
             a.append(h + bf16(v - h))

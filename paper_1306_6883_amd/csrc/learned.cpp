@@ -28,7 +28,7 @@ constexpr double kGuessReject = 1e6;
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct NetLayout {
-    size_t w, m, v, grad, w16, wt16, act, g0, g1, y, dy, part, part2, lpart, loss, x1, y1, dec0, dec1, stats, fpart;
+    size_t w, m, v, grad, w16, w16lo, wt16, act, g0, g1, y, dy, part, part2, lpart, loss, x1, y1, dec0, dec1, stats, fpart;
     size_t total;
 };
 
@@ -46,6 +46,7 @@ NetLayout net_layout(int batch, int nmax) {
     L.v = take(sizeof(float) * kNetParams);
     L.grad = take(sizeof(float) * kNetParams);
     L.w16 = take(2 * (size_t)kNetParams);
+    L.w16lo = take(2 * (size_t)kNetParams);
     L.wt16 = take(2 * (size_t)4 * kWmid);
     L.act = take(2 * npix * kNetC * 10);  // a1 .. a5 (hi), then a1 .. a5 (lo)
     L.g0 = take(2 * npix * kNetC);
@@ -93,7 +94,7 @@ int hs(hipError_t e) { return e == hipSuccess ? CCMG_OK : CCMG_EHIP; }
 
 hipError_t refresh_bf16(ccmg_net *N) {
     hipLaunchKernelGGL(k_to_bf16, dim3((kNetParams + 255) / 256), dim3(256), 0, N->stream, N->w(), N->w16(),
-                       kNetParams);
+                       N->at<__bf16>(N->L.w16lo), kNetParams);
     for (int l = 1; l <= 4; ++l)
         hipLaunchKernelGGL(k_transpose_flip, dim3((kWmid + 255) / 256), dim3(256), 0, N->stream,
                            N->w16() + net_param_offset(l), N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid);
@@ -110,7 +111,8 @@ hipError_t forward(ccmg_net *N, const float *x, float *y, int nb) {
     const int waves = nb * kNetG * (kNetG / 32);
     for (int l = 1; l <= 4; ++l)
         hipLaunchKernelGGL(k_conv32, dim3((waves + 3) / 4), dim3(256), 0, s, N->act(l - 1), N->act_lo(l - 1),
-                           N->w16() + net_param_offset(l), N->act(l), N->act_lo(l), nb, net_dilation(l));
+                           N->w16() + net_param_offset(l), N->at<__bf16>(N->L.w16lo) + net_param_offset(l),
+                           N->act(l), N->act_lo(l), nb, net_dilation(l));
     hipLaunchKernelGGL(k_conv_out, dim3((npix + 255) / 256), dim3(256), 0, s, N->act(4), N->act_lo(4),
                        N->w() + net_param_offset(5), y, nb, net_dilation(5));
     return hipGetLastError();
@@ -151,7 +153,7 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
                            kWgChunk, net_dilation(l));
         sum_partials(N, part, wg_waves, kWmid, grad + net_param_offset(l));
         hipLaunchKernelGGL(k_conv32, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur, (const __bf16 *)nullptr,
-                           N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, gnext, (__bf16 *)nullptr, nb,
+                           N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, (const __bf16 *)nullptr, gnext, (__bf16 *)nullptr, nb,
                            net_dilation(l));
         std::swap(gcur, gnext);
     }

@@ -19,8 +19,8 @@ constexpr int kNetParams = kW0 + 4 * kWmid + kW5;  // 37440
 inline int net_param_offset(int layer) { return layer == 0 ? 0 : kW0 + (layer - 1) * kWmid; }
 inline int net_dilation(int layer) { return 1 << layer; }
 
-__global__ void k_conv32(const __bf16 *in, const __bf16 *in_lo, const __bf16 *w, __bf16 *out, __bf16 *out_lo, int nb,
-                         int dil);
+__global__ void k_conv32(const __bf16 *in, const __bf16 *in_lo, const __bf16 *w, const __bf16 *w_lo, __bf16 *out,
+                         __bf16 *out_lo, int nb, int dil);
 __global__ void k_conv32_wgrad(const __bf16 *g, const __bf16 *in, float *part, int npix, int chunk, int dil);
 __global__ void k_sum_partials(const float *part, int count, int len, float *out);
 __global__ void k_sum_partials_grouped(const float *part, int count, int len, int groups, float *out);
@@ -34,7 +34,7 @@ __global__ void k_mse(const float *y, const float *t, float *dy, double *part, i
 __global__ void k_loss_finish(const double *part, int blocks, int count, float *loss);
 __global__ void k_adam(float *w, const float *g, float *m, float *v, __bf16 *w16, int count, float lr, float b1,
                        float b2, float eps, float c1, float c2);
-__global__ void k_to_bf16(const float *a, __bf16 *b, int count);
+__global__ void k_to_bf16(const float *a, __bf16 *b, __bf16 *lo, int count);
 __global__ void k_encode(const double *f, long pitch, int n, const double *sumsq, float *out);
 constexpr int kRelaxThreads = 512;
 __global__ void k_coarse_relax(const float *y, const float *x, const double *sumsq, int nfine, double length,

@@ -47,8 +47,9 @@ __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_c
 // `out_lo` the FP32 sum is written as such a pair.  Without them (gradients)
 // one BF16 value.
 __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, const __bf16 *__restrict__ in_lo,
-                                                const __bf16 *__restrict__ w, __bf16 *__restrict__ out,
-                                                __bf16 *__restrict__ out_lo, int nb, int dil) {
+                                                const __bf16 *__restrict__ w, const __bf16 *__restrict__ w_lo,
+                                                __bf16 *__restrict__ out, __bf16 *__restrict__ out_lo, int nb,
+                                                int dil) {
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tiles_per_row = kNetG / 32;
@@ -67,10 +68,14 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
         const size_t px = img + ((size_t)ys * kNetG + xs) * kNetC;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const bf16x8 bv = load8(w + ((size_t)r * 9 + t) * kNetC + 16 * h + 8 * hk);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(in + px + 16 * h + 8 * hk), bv, acc, 0, 0, 0);
+            const size_t wo = ((size_t)r * 9 + t) * kNetC + 16 * h + 8 * hk;
+            const bf16x8 bv = load8(w + wo);
+            const bf16x8 av = load8(in + px + 16 * h + 8 * hk);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
             if (in_lo)
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(in_lo + px + 16 * h + 8 * hk), bv, acc, 0, 0, 0);
+            if (w_lo)  // the weights' low parts (hi activations; lo x lo is below the FP32 sums' rounding)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, load8(w_lo + wo), acc, 0, 0, 0);
         }
     }
     const size_t o = (((size_t)b * kNetG + y) * kNetG + x0) * kNetC;
@@ -196,7 +201,7 @@ __global__ void k_transpose_flip(const __bf16 *__restrict__ w, __bf16 *__restric
     wt[i] = w[((size_t)co * 9 + (8 - t)) * kNetC + ci];
 }
 
-// First layer (1 -> 32): one thread per pixel; FP32 input, BF16 weights, the
+// First layer (1 -> 32): one thread per pixel; FP32 input and weights, the
 // output as a BF16 (hi, lo) pair.
 __global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__ w1, __bf16 *__restrict__ out,
                           __bf16 *__restrict__ out_lo, int nb, int dil) {
@@ -210,14 +215,15 @@ __global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__
     for (int co = 0; co < kNetC; ++co) {
         float s = 0.f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w1[co * 9 + t] * v[t];
+        for (int t = 0; t < 9; ++t) s += w1[co * 9 + t] * v[t];
         const __bf16 hi = (__bf16)s;
         out[(size_t)q * kNetC + co] = hi;
         out_lo[(size_t)q * kNetC + co] = (__bf16)(s - (float)hi);
     }
 }
 
-// Last layer (32 -> 1): one thread per pixel, (hi + lo) activations, FP32 output.
+// Last layer (32 -> 1): one thread per pixel, (hi + lo) activations, FP32
+// weights and output.
 __global__ void k_conv_out(const __bf16 *__restrict__ in, const __bf16 *__restrict__ in_lo,
                            const float *__restrict__ w6, float *__restrict__ y, int nb, int dil) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -228,7 +234,7 @@ __global__ void k_conv_out(const __bf16 *__restrict__ in, const __bf16 *__restri
         const size_t px =
             (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))) * kNetC;
         for (int ci = 0; ci < kNetC; ++ci)
-            s += (float)(__bf16)w6[t * kNetC + ci] * ((float)in[px + ci] + (float)in_lo[px + ci]);
+            s += w6[t * kNetC + ci] * ((float)in[px + ci] + (float)in_lo[px + ci]);
     }
     y[q] = s;
 }
@@ -339,9 +345,14 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
     w16[i] = (__bf16)wi;
 }
 
-__global__ void k_to_bf16(const float *__restrict__ a, __bf16 *__restrict__ b, int count) {
+// BF16 copy of the weights as a (hi, lo) pair: hi = bf16(a), lo = bf16(a - hi).
+__global__ void k_to_bf16(const float *__restrict__ a, __bf16 *__restrict__ b, __bf16 *__restrict__ lo, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) b[i] = (__bf16)a[i];
+    if (i < count) {
+        const __bf16 h = (__bf16)a[i];
+        b[i] = h;
+        if (lo) lo[i] = (__bf16)(a[i] - (float)h);
+    }
 }
 
 // Scale of a right-hand side: its RMS over the valid cells, sqrt(sum f^2 / n^2);

@@ -76,3 +76,19 @@ def test_bf16_pair_keeps_about_16_bits():
     v = np.random.default_rng(4).standard_normal(10000) * 10.0 ** np.random.default_rng(5).uniform(-5, 5, 10000)
     p = N.bf16_pair(v)
     assert np.all(np.abs(p - v) <= 2.0 ** -16 * np.abs(v))
+
+
+def test_rounded_forward_stays_within_the_pairs_precision():
+    """Each layer's weights and activations keep about 16 bits (hi + lo
+    pairs), so six layers of the rounded forward stay within a few 2^-16 of
+    the unrounded one; rounding the weights to one bfloat16 (2^-9) would not."""
+    g = np.random.default_rng(6)
+    p = np.concatenate([g.normal(0, 1 / np.sqrt(k * ci), co * k * ci)
+                        for co, k, ci in [(32, 9, 1)] + [(32, 9, 32)] * 4 + [(1, 9, 32)]])
+    p = p.astype(np.float32).astype(np.float64)
+    x = g.standard_normal((1, N.G, N.G)).astype(np.float32).astype(np.float64)
+    y = N.forward(p, x)[0]
+    e = np.linalg.norm(N.forward(p, x, bf=True)[0] - y) / np.linalg.norm(y)
+    assert e < 6 * 2.0 ** -16
+    e1 = np.linalg.norm(N.forward(N.bf16(p), x)[0] - y) / np.linalg.norm(y)
+    assert e1 > 10 * e
