@@ -47,7 +47,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("h", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("bc", ctypes.c_int * 4), ("nu1", ctypes.c_int),
                 ("nu2", ctypes.c_int), ("nu_bottom", ctypes.c_int),
-                ("max_cycles", ctypes.c_int), ("rtol", ctypes.c_double)]
+                ("max_cycles", ctypes.c_int), ("rtol", ctypes.c_double), ("n_bottom", ctypes.c_int)]
 
 
 class _Result(ctypes.Structure):
@@ -127,6 +127,7 @@ class Problem:
     nu_bottom: int = 50
     max_cycles: int = 100
     rtol: float = 1e-10
+    n_bottom: int = 2      # 4, 8, ...: exact solve on that level, nothing below
 
     def _c(self) -> _Params:
         p = _Params()
@@ -134,6 +135,7 @@ class Problem:
         p.bc[:] = list(bc_codes(self.bc))
         p.nu1, p.nu2, p.nu_bottom = self.nu1, self.nu2, self.nu_bottom
         p.max_cycles, p.rtol = self.max_cycles, self.rtol
+        p.n_bottom = self.n_bottom
         return p
 
     @property

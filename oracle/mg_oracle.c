@@ -177,11 +177,73 @@ static void add_const(int n, double *a, double c) {
 
 size_t og_field_len(int n) { return (size_t)(n + 2) * (size_t)(n + 2); }
 
+/* Exact solve of one level, an alternative bottom for the V-cycle (Sec. 3.3
+ * leaves the coarsest solve open): the level's operator alpha - beta Lap_h,
+ * side rules included, written out as a dense matrix over the n*n valid cells
+ * (unknown k = j n + i) and solved by Gaussian elimination with partial
+ * pivoting.  A singular operator (constants in its null space) gets c 1 1^T
+ * added, c = beta / h^2: for a right-hand side of zero sum, 1^T A = 0 makes
+ * the modified system's solution the zero-sum solution of the original. */
+static void direct_solve(int n, double h, double alpha, double beta, const int bc[4], int singular,
+                         double *phi, const double *f) {
+    int m = n * n, w = m + 1;
+    double c = beta / (h * h);
+    double *A = (double *)calloc((size_t)m * (size_t)w, sizeof(double)); /* rows [A | b] */
+    static const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1}; /* sides x-lo, x-hi, y-lo, y-hi */
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            int k = j * n + i;
+            double *row = A + (size_t)k * w;
+            row[k] += alpha + 4.0 * c;
+            for (int s = 0; s < 4; ++s) {
+                int ii = i + di[s], jj = j + dj[s];
+                if (ii >= 0 && ii < n && jj >= 0 && jj < n)
+                    row[jj * n + ii] -= c;
+                else if (bc[s] == OG_PERIODIC)
+                    row[((jj + n) % n) * n + (ii + n) % n] -= c;
+                else if (bc[s] == OG_DIRICHLET)
+                    row[k] += c; /* ghost = -cell */
+                else
+                    row[k] -= c; /* ghost = +cell */
+            }
+            if (singular)
+                for (int q = 0; q < m; ++q) row[q] += c;
+            row[m] = f[IDX(n, i, j)];
+        }
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (fabs(A[(size_t)r * w + col]) > fabs(A[(size_t)piv * w + col])) piv = r;
+        if (piv != col)
+            for (int q = 0; q < w; ++q) {
+                double t = A[(size_t)col * w + q];
+                A[(size_t)col * w + q] = A[(size_t)piv * w + q];
+                A[(size_t)piv * w + q] = t;
+            }
+        for (int r = col + 1; r < m; ++r) {
+            double g = A[(size_t)r * w + col] / A[(size_t)col * w + col];
+            for (int q = col; q < w; ++q) A[(size_t)r * w + q] -= g * A[(size_t)col * w + q];
+        }
+    }
+    for (int k = m - 1; k >= 0; --k) {
+        double s = A[(size_t)k * w + m];
+        for (int q = k + 1; q < m; ++q) s -= A[(size_t)k * w + q] * A[(size_t)q * w + m];
+        A[(size_t)k * w + m] = s / A[(size_t)k * w + k];
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) phi[IDX(n, i, j)] = A[(size_t)(j * n + i) * w + m];
+    free(A);
+}
+
 /* Recursive V(nu1, nu2) cycle on level `lev` of the hierarchy.  phi[l] and
  * f[l] hold the level-l fields; r is scratch of the finest size. */
 static void vcycle(const og_params *p, int lev, double **phi, double **f, double *r, int singular) {
     int n = p->n >> lev;
     double h = p->h * (double)(1 << lev);
+    if (n >= 4 && n == p->n_bottom) {
+        direct_solve(n, h, p->alpha, p->beta, p->bc, singular, phi[lev], f[lev]);
+        return;
+    }
     if (n == 2) {
         og_smooth(n, h, p->alpha, p->beta, p->bc, phi[lev], f[lev], p->nu_bottom);
         return;

@@ -27,6 +27,9 @@ typedef struct {
     int nu_bottom;  /* relaxations on the 2x2 grid                  */
     int max_cycles;
     double rtol;    /* stop when ||r|| / ||f|| <= rtol              */
+    int n_bottom;   /* 4, 8, ...: exact solve on the level of that  */
+                    /* size, nothing below it; else the 2x2 grid's  */
+                    /* nu_bottom relaxations                        */
 } og_params;
 
 typedef struct {

@@ -56,6 +56,16 @@ def _projection_pins():
 
 J = _projection_pins()
 
+
+def _bottom_pins():
+    spec = importlib.util.spec_from_file_location("oracle_bottom_pins", os.path.join(HERE, "test_oracle_bottom.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+Q = _bottom_pins()
+
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
 MUTANTS = {
     "relaxation_sign": ("(f[IDX(n, i, j)] + c * nb) / diag", "(f[IDX(n, i, j)] - c * nb) / diag"),
@@ -83,6 +93,12 @@ MUTANTS = {
                         "(vv[IDX(n, i + 1, j)] - vv[IDX(n, i - 1, j)]) * i2h;"),
     "projection_gradient_sign": ("u[IDX(n, i, j)] -= (phi[IDX(n, i + 1, j)] - phi[IDX(n, i - 1, j)]) * i2h;",
                                  "u[IDX(n, i, j)] += (phi[IDX(n, i + 1, j)] - phi[IDX(n, i - 1, j)]) * i2h;"),
+    "direct_dirichlet_side": ("row[k] += c; /* ghost = -cell */", "row[k] -= c; /* ghost = -cell */"),
+    "direct_periodic_as_neumann": ("row[((jj + n) % n) * n + (ii + n) % n] -= c;", "row[k] -= c;"),
+    "direct_singular_shift_sign": ("for (int q = 0; q < m; ++q) row[q] += c;",
+                                   "for (int q = 0; q < m; ++q) row[q] += (q == k ? c : 0.0);"),
+    "direct_back_substitution": ("s -= A[(size_t)k * w + q] * A[(size_t)q * w + m];",
+                                 "s -= A[(size_t)k * w + q] * A[(size_t)k * w + m];"),
 }
 # Not a mutant: dropping the removal of each restricted right-hand side's mean
 # (singular problems) changes the iterates only by rounding -- the residual of
@@ -108,6 +124,9 @@ BATTERY = [
     (B.test_side_data_solve_matches_the_extended_dense_system, ("NDDN", (1.0, 0.02))),
     (J.test_discrete_curl_is_left_unchanged, ()),
     (J.test_gradient_of_a_mode_in_closed_form, ()),
+    (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("DNPP", (1.0, 0.5 / 64), 8)),
+    (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("PPPP", (0.0, -1.0), 4)),
+    (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("NDDN", (0.0, -1.0), 8)),
 ]
 
 
