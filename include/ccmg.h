@@ -133,6 +133,22 @@ int ccmg_plan_destroy(ccmg_plan *plan);
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 
+/* Bottom of the V-cycle (Sec. 3.3 leaves the coarsest solve open).
+ * n_bottom = 2 (the default): nu_bottom red-black relaxations on the 2 x 2
+ * grid.  n_bottom = 4 or 8: the cycle ends on the level of n_bottom x
+ * n_bottom cells with an exact solve, phi = A^-1 f (A: the level's operator
+ * alpha - beta Lap_h with the plan's side rules; for a singular plan
+ * A + c 1 1^T, c = beta / h^2, whose solution of a zero-mean f is the
+ * zero-mean solution), and the levels below it are not visited; nu_bottom is
+ * then unused.  A^-1 is computed here on the device (Gauss-Jordan in FP64,
+ * n_bottom^4 doubles in the plan's workspace) and applied in FP64 from LDS by
+ * the one-workgroup tail, also in the FP32 cycles of mixed plans.  Applies to
+ * every later ccmg_solve, ccmg_vcycle, ccmg_solve_bc, ccmg_cn_step and
+ * ccmg_project of the plan.  Returns CCMG_EINVAL for another size, a size
+ * above min(n, 32), or an indefinite operator (alpha beta < 0 or beta == 0);
+ * blocks until the inverse is written. */
+int ccmg_plan_set_bottom(ccmg_plan *plan, int n_bottom);
+
 /* ---- Inhomogeneous side data (Sec. 3.3: the V-cycle's levels use the
  * homogeneous rules; with data the boundary value enters the ghost cell's
  * expression).  d_b is a host array of four device arrays, one per side in
@@ -318,10 +334,10 @@ int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdif
  * of FP64 solves, 3 = its FP32 form in mixed-precision steps (level 0 only,
  * ty even and >= 8, no tile kernel).  Results do not depend on the shape. */
 int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
-/* The plan's launch shapes per level (arrays of max_levels entries). */
 /* The fused finest launch's shape: kind 2 (FP64) or 3 (FP32), as for
  * ccmg_plan_set_shape. */
 int ccmg_plan_fused_shape(ccmg_plan *plan, int kind, int *ty, int *wpb);
+/* The plan's launch shapes per level (arrays of max_levels entries). */
 int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, int *wpb_post,
                      int max_levels);
 

@@ -110,6 +110,7 @@ def lib():
         L.ccmg_cn_step.argtypes = [vp, dp, dp, pd, ctypes.POINTER(ccmg_result)]
         L.ccmg_plan_fused_shape.argtypes = [vp, i, ip, ip]
         L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
+        L.ccmg_plan_set_bottom.argtypes = [vp, i]
         L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
         fp = ctypes.POINTER(ctypes.c_float)
         L.ccmg_net_param_count.argtypes = []
@@ -402,6 +403,12 @@ def ccmg_plan_autotune(plan: Plan, f: torch.Tensor, phi: torch.Tensor) -> None:
 
 def ccmg_plan_set_shape(plan: Plan, level: int, kind: int, ty: int, wpb: int) -> None:
     _check(lib().ccmg_plan_set_shape(plan.handle, level, kind, ty, wpb), "ccmg_plan_set_shape")
+
+
+def ccmg_plan_set_bottom(plan: Plan, n_bottom: int) -> None:
+    """Bottom of the V-cycle: 2 = relaxations on 2 x 2 (default), 4 or 8 =
+    exact solve on that level."""
+    _check(lib().ccmg_plan_set_bottom(plan.handle, n_bottom), "ccmg_plan_set_bottom")
 
 
 def ccmg_plan_fused_shape(plan: Plan, kind: int = 2) -> tuple:

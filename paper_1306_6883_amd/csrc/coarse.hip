@@ -7,7 +7,9 @@
 // neighbour is read).  The steps are those of the paper's V-cycle (Sec. 3.3):
 // nu1 red-black Gauss-Seidel iterations, residual and four-cell restriction,
 // recursion, centred-slope prolongation without the xy term, nu2 iterations;
-// on the 2 x 2 grid nu_bottom relaxations, done in FP64 whatever T is.
+// on the 2 x 2 grid nu_bottom relaxations, done in FP64 whatever T is.  Or an
+// exact bottom on a 4 x 4 or 8 x 8 level: its inverse operator (computed once
+// per plan by k_bottom_inverse) is held in LDS and applied in FP64.
 #include <cstdlib>
 
 #include "internal.h"
@@ -219,11 +221,27 @@ __device__ void bottom(const CoarseArgs<T> &a, const Sides &sd, T *sP, const T *
     sP[off[l] + 3] = T(p3);
 }
 
-template <int NT, typename T>
+// Exact bottom on level l (n = 1 << lg cells per side, m = n^2 unknowns), on
+// the first wave: lane i computes P[i] = sum_j ainv[i][j] F[j] in FP64 in
+// column order.  ainv is column-major in LDS, so a lane reads consecutive
+// doubles and F[j] is one broadcast.
+template <typename T>
+__device__ void direct_bottom(const double *sInv, T *P, const T *F, int lg) {
+    const int m = 1 << (2 * lg);
+    const int i = threadIdx.x;
+    if (i < m) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += sInv[j * m + i] * (double)F[j];
+        P[i] = T(s);
+    }
+}
+
+template <int NT, typename T, bool DIRECT>
 __device__ void coarse_body(const CoarseArgs<T> &a) {
     __shared__ T sP[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ T sF[kCoarseMax * kCoarseMax * 4 / 3 + 8];
     __shared__ double red[NT / 64];
+    __shared__ double sInv[DIRECT ? kDirectMax * kDirectMax * kDirectMax * kDirectMax : 1];
     if (a.skip && *a.skip) return;  // uniform over the workgroup
 
     Sides sd;
@@ -236,7 +254,13 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
 
     const int n0 = a.n_top;
     const int lg0 = 31 - __clz(n0);
-    const int L = lg0;  // levels n0, n0/2, ..., 2
+    // levels n0, n0/2, ..., n_bottom (2 unless the bottom is exact)
+    const int lgb = DIRECT ? 31 - __clz(a.n_bottom) : 1;
+    const int L = lg0 - lgb + 1;
+    if (DIRECT) {  // the inverse into LDS; its loads overlap the top level's
+        const int mm = 1 << (4 * lgb);
+        for (int i = threadIdx.x; i < mm; i += NT) sInv[i] = a.ainv[i];
+    }
     int off[8];
     off[0] = 0;
     for (int l = 1; l < L; ++l) off[l] = off[l - 1] + (1 << (2 * (lg0 - l + 1)));
@@ -260,7 +284,10 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
     for (int l = 0; l < lw && l + 1 < L; ++l) down_level<NT>(a, sd, sP, sF, off, lg0, l, red);
     if (NT == 64 || threadIdx.x < 64) {
         for (int l = lw; l + 1 < L; ++l) down_level<64>(a, sd, sP, sF, off, lg0, l, red);
-        bottom(a, sd, sP, sF, off, L);
+        if (DIRECT)
+            direct_bottom(sInv, sP + off[L - 1], sF + off[L - 1], lgb);
+        else
+            bottom(a, sd, sP, sF, off, L);
         sync<64>();
         for (int l = L - 2; l >= lw; --l) up_level<64>(a, sd, sP, sF, off, lg0, l);
     }
@@ -274,15 +301,71 @@ __device__ void coarse_body(const CoarseArgs<T> &a) {
     }
 }
 
-template <int NT, typename T>
+template <int NT, typename T, bool DIRECT>
 __global__ __launch_bounds__(NT) void k_coarse(const CoarseArgs<T> a) {
-    coarse_body<NT>(a);
+    coarse_body<NT, T, DIRECT>(a);
 }
 
-// Batches: one workgroup per problem.
+// Batches: one workgroup per problem (relaxation bottom).
 template <int NT, typename T>
 __global__ __launch_bounds__(NT) void k_coarse_list(const CoarseArgs<T> *__restrict__ list) {
-    coarse_body<NT>(list[blockIdx.x]);
+    coarse_body<NT, T, false>(list[blockIdx.x]);
+}
+
+// Inverse of a small level's operator by Gauss-Jordan elimination on [A | I]
+// in LDS, one workgroup.  No pivoting: the operator is definite (symmetric,
+// all eigenvalues of one sign; a singular one is made definite by c 1 1^T with
+// c of the operator's sign), so every pivot is a nonzero Schur complement
+// entry.  Four threads per row, each a quarter of the 2m columns.
+constexpr int kInvThreads = 256;
+__global__ __launch_bounds__(kInvThreads) void k_bottom_inverse(int lgb, int bc0, int bc1, int bc2, int bc3,
+                                                                double alpha, double beta, double h, int singular,
+                                                                double *__restrict__ out) {
+    constexpr int kM = kDirectMax * kDirectMax;
+    __shared__ double M[kM][2 * kM];
+    const int nb = 1 << lgb, m = nb * nb, w = 2 * m;
+    const int bc[4] = {bc0, bc1, bc2, bc3};
+    const double c = beta / (h * h);
+    for (int k = threadIdx.x; k < m; k += kInvThreads) {
+        for (int q = 0; q < m; ++q) M[k][q] = singular ? c : 0.0;  // A (+ c 1 1^T) ...
+        for (int q = m; q < w; ++q) M[k][q] = (q == k + m) ? 1.0 : 0.0;  // ... | I
+        const int i = k % nb, j = k / nb;
+        M[k][k] += alpha + 4.0 * c;
+        const int ni[4] = {i - 1, i + 1, i, i}, nj[4] = {j, j, j - 1, j + 1};
+        for (int s = 0; s < 4; ++s) {
+            const bool inside = ni[s] >= 0 && ni[s] < nb && nj[s] >= 0 && nj[s] < nb;
+            if (inside || bc[s] == CCMG_BC_PERIODIC)
+                M[k][((nj[s] + nb) % nb) * nb + (ni[s] + nb) % nb] -= c;
+            else  // ghost = -cell (Dirichlet) or +cell (Neumann)
+                M[k][k] -= (bc[s] == CCMG_BC_DIRICHLET ? -c : c);
+        }
+    }
+    const int r = threadIdx.x >> 2, part = threadIdx.x & 3;
+    const int q0 = part * (w / 4), q1 = q0 + w / 4;
+    for (int col = 0; col < m; ++col) {
+        __syncthreads();
+        const double piv = M[col][col];
+        const double g = (r < m && r != col) ? M[r][col] / piv : 0.0;
+        __syncthreads();
+        if (r < m && r != col)
+            for (int q = q0; q < q1; ++q) M[r][q] -= g * M[col][q];
+        __syncthreads();
+        if (r == col)
+            for (int q = q0; q < q1; ++q) M[col][q] /= piv;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += kInvThreads) {
+        const int k = t % m, q = t / m;  // out[q * m + k] = inverse[k][q]
+        out[t] = M[k][m + q];
+    }
+}
+
+hipError_t launch_bottom_inverse(int nb, const int bc[4], double alpha, double beta, double h, int singular,
+                                 double *out, hipStream_t s) {
+    if (nb < 4 || nb > kDirectMax || (nb & (nb - 1)) || !out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bottom_inverse, dim3(1), dim3(kInvThreads), 0, s, 31 - __builtin_clz(nb), bc[0], bc[1],
+                       bc[2], bc[3], alpha, beta, h, singular, out);
+    return hipGetLastError();
 }
 
 // Workgroup size of the tail: CCMG_COARSE_THREADS (64, 128, 256 or 512) if
@@ -312,11 +395,23 @@ hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
     if (a0.n_top < 2 || a0.n_top > kCoarseMax || (a0.n_top & (a0.n_top - 1))) return hipErrorInvalidValue;
     CoarseArgs<T> a = a0;
     coarse_fill_consts(a);
+    const bool direct = a.n_bottom >= 4;
+    if (direct && (a.n_bottom > kDirectMax || a.n_bottom > a.n_top || (a.n_bottom & (a.n_bottom - 1)) || !a.ainv))
+        return hipErrorInvalidValue;
+    if (direct) {
+        switch (coarse_threads()) {
+            case 64: hipLaunchKernelGGL((k_coarse<64, T, true>), dim3(1), dim3(64), 0, s, a); break;
+            case 128: hipLaunchKernelGGL((k_coarse<128, T, true>), dim3(1), dim3(128), 0, s, a); break;
+            case 256: hipLaunchKernelGGL((k_coarse<256, T, true>), dim3(1), dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_coarse<512, T, true>), dim3(1), dim3(512), 0, s, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (coarse_threads()) {
-        case 64: hipLaunchKernelGGL((k_coarse<64, T>), dim3(1), dim3(64), 0, s, a); break;
-        case 128: hipLaunchKernelGGL((k_coarse<128, T>), dim3(1), dim3(128), 0, s, a); break;
-        case 256: hipLaunchKernelGGL((k_coarse<256, T>), dim3(1), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_coarse<512, T>), dim3(1), dim3(512), 0, s, a); break;
+        case 64: hipLaunchKernelGGL((k_coarse<64, T, false>), dim3(1), dim3(64), 0, s, a); break;
+        case 128: hipLaunchKernelGGL((k_coarse<128, T, false>), dim3(1), dim3(128), 0, s, a); break;
+        case 256: hipLaunchKernelGGL((k_coarse<256, T, false>), dim3(1), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_coarse<512, T, false>), dim3(1), dim3(512), 0, s, a); break;
     }
     return hipGetLastError();
 }

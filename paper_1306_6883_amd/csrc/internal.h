@@ -141,7 +141,19 @@ struct CoarseArgs {
     int load_phi;        // 1: top level starts from phi_in; 0: from zero
     int sub_top_mean;    // 1: remove the mean of the top-level rhs (singular, not finest)
     int singular;        // remove the mean of every restricted rhs below the top
+    // exact bottom: n_bottom in {4, 8} (<= n_top) ends the cycle on that level
+    // with phi = ainv f (ainv: the level's inverse operator, FP64, column-major
+    // m x m, m = n_bottom^2); otherwise (0 or 2) the 2 x 2 relaxations.
+    int n_bottom;
+    const double *ainv;
 };
+// Largest exact-bottom level (cells per side): its inverse is held in LDS.
+constexpr int kDirectMax = 8;
+// Inverse of (alpha - beta Lap_h) on an nb x nb level with the side rules bc
+// (plus c 1 1^T, c = beta / h^2, when singular), column-major into out
+// (nb^4 doubles).  The operator must be definite (alpha beta >= 0, beta != 0).
+hipError_t launch_bottom_inverse(int nb, const int bc[4], double alpha, double beta, double h, int singular,
+                                 double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_coarse(const CoarseArgs<T> &a, hipStream_t s);
 // One workgroup per entry of a device array of tail descriptors (batches).

@@ -67,6 +67,7 @@ struct Layout {
     size_t part3b = 0;     // one written by the same launch)
     size_t fstats = 0;
     size_t scal = 0, hist = 0, flags = 0;
+    size_t ainv = 0;       // inverse operator of an exact-bottom level (FP64)
     size_t total = 0;
 };
 
@@ -124,6 +125,7 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     lay.scal = take(sizeof(double) * kScal);
     lay.hist = take(sizeof(double) * CCMG_HISTORY);
     lay.flags = take(sizeof(int) * 16);
+    lay.ainv = take(sizeof(double) * kDirectMax * kDirectMax * kDirectMax * kDirectMax);  // keep last
     lay.total = off;
     return true;
 }
@@ -176,6 +178,7 @@ struct ccmg_plan {
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     bool pair_down[kMaxLevels] = {};  // levels l, l+1 pre-smoothed in one launch (2-D tiles)
+    int n_bottom = 2;  // 4 or 8: exact solve on that level (ccmg_plan_set_bottom)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
     double *drho = nullptr;   // ... its device address
     Layout lay;
@@ -353,6 +356,8 @@ void coarse_consts(const ccmg_plan *P, int l, CoarseArgs<T> &c) {
     c.nu2 = P->p.nu2;
     c.nu_bottom = P->p.nu_bottom;
     c.n_top = P->lay.lev[l].n;
+    c.n_bottom = P->n_bottom >= 4 ? P->n_bottom : 0;
+    c.ainv = P->n_bottom >= 4 ? P->at<double>(P->lay.ainv) : nullptr;
 }
 
 // Enqueue one V-cycle in precision T.  Returns in *norm_tiles the tile count of
@@ -957,7 +962,8 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
     }
     // the workspace is scratch between calls: start from zeros (values do not
     // change the timing, but keep them finite)
-    hipError_t err = hipMemsetAsync(P->ws, 0, lay.total, s);
+    // (all but the exact bottom's inverse, the last region, which is kept)
+    hipError_t err = hipMemsetAsync(P->ws, 0, lay.ainv, s);
     const int tys[] = {0, 8, 16, 32, 64, 128, 256};
     const int wpbs[] = {1, 2, 4};
     const int reps = 4;
@@ -1153,6 +1159,26 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     MarchShape sh{ty < n ? ty : n, wpb};
     if (kind == 0) P->shp_pre[level] = sh;
     else P->shp_post[level] = sh;
+    return CCMG_OK;
+}
+
+int ccmg_plan_set_bottom(ccmg_plan *P, int n_bottom) {
+    if (!P) return CCMG_EINVAL;
+    if (n_bottom == 2) {
+        P->n_bottom = 2;
+        return CCMG_OK;
+    }
+    const ccmg_problem &p = P->p;
+    // a level the tail holds, and a definite operator (no pivoting in the inverse)
+    if ((n_bottom != 4 && n_bottom != kDirectMax) || n_bottom > P->lay.lev[P->lay.lt].n) return CCMG_EINVAL;
+    if (p.beta == 0.0 || p.alpha * p.beta < 0.0) return CCMG_EINVAL;
+    int lb = 0;
+    while (P->lay.lev[lb].n != n_bottom) ++lb;
+    hipError_t e = launch_bottom_inverse(n_bottom, p.bc, p.alpha, p.beta, P->lay.lev[lb].h, P->singular ? 1 : 0,
+                                         P->at<double>(P->lay.ainv), P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return CCMG_EHIP;
+    P->n_bottom = n_bottom;
     return CCMG_OK;
 }
 
