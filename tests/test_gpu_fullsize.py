@@ -96,3 +96,29 @@ def test_batched_512_against_oracle_solves():
             ref = ref - ref.mean()
         worst = max(worst, np.linalg.norm(got - ref) / np.linalg.norm(ref))
     assert worst <= 1e-9, worst
+
+
+@pytest.mark.parametrize("bc,prec", [("PPPP", "fp64"), ("DNDN", "mixed")])
+def test_maximum_size_16384(bc, prec):
+    """The largest grid a plan accepts (16384^2, 2 GiB per field), autotuned.
+    A white-noise right-hand side: smooth data would put the FP64 residual
+    floor of even the exact solution near 1e-10 at this size, rough data keep
+    it far below.  Checked by what holds at any size: the returned field's
+    residual recomputed in FP64 on the host, zero mean when singular."""
+    n = 16384
+    print(f"max size n={n} bc={bc} prec={prec}", flush=True)
+    fv = np.random.default_rng(5).standard_normal((n, n))
+    if exact.is_singular(0.0, bc):
+        fv -= fv.mean()
+    prob = cc.Problem(n=n, bc=tuple(bc), rtol=1e-10, prec=cc.FP64 if prec == "fp64" else cc.MIXED)
+    plan = cc.Plan(prob)
+    f, phi = to_dev(fv), to_dev(np.zeros((n, n)))
+    cc.ccmg_plan_autotune(plan, f, phi)
+    r = cc.ccmg_solve(plan, f, phi)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10, r
+    got = valid(phi)
+    del plan, f, phi
+    torch.cuda.empty_cache()
+    assert exact.relative_residual(got, fv, 1.0 / n, 0.0, -1.0, bc) <= 1.05e-10
+    if exact.is_singular(0.0, bc):
+        assert abs(got.mean()) <= 1e-13 * np.abs(got).max()
