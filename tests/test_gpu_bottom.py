@@ -41,16 +41,13 @@ def make(n, bc, ab, nb, prec=cc.FP64, **kw):
     return plan
 
 
-@pytest.mark.parametrize("nb", [4, 8])
 @pytest.mark.parametrize("ab", ABS)
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("n", [4, 8, 32, 64, 512])
-def test_vcycle_iterates_match_oracle(n, bc, ab, nb):
+@pytest.mark.parametrize("n,nb", [(4, 4), (8, 4), (8, 8), (32, 4), (32, 8), (64, 4), (64, 8), (512, 4), (512, 8)])
+def test_vcycle_iterates_match_oracle(n, nb, bc, ab):
     """Three cycles from a random start; the levels above the bottom are the
     ones the relaxation-bottom parity tests cover, so differences are the two
     inverses' rounding, carried up the hierarchy."""
-    if nb > n:
-        pytest.skip("bottom level above the finest")
     print(f"bottom vcycle n={n} bc={bc} ab={ab} nb={nb}", flush=True)
     plan = make(n, bc, ab, nb)
     p = oracle.Problem(n=n, h=1.0 / n, alpha=ab[0], beta=ab[1], bc=bc, n_bottom=nb)
