@@ -22,6 +22,8 @@ import argparse
 import json
 import os
 import re
+import subprocess
+import tempfile
 import sys
 import time
 
@@ -483,6 +485,34 @@ def cpu_baseline(fv, n, bc, budget_s=10.0):
                       f"plain C + OpenMP, {dt:.1f} s"}
 
 
+def cpu_single_thread(fv, n, bc):
+    """One whole oracle solve of the same problem on one thread (a child
+    process with OMP_NUM_THREADS=1: the thread count is fixed when the
+    OpenMP runtime starts), and the host's CPU model and thread count."""
+    fpath = os.path.join(tempfile.mkdtemp(), "f.npy")
+    np.save(fpath, fv)
+    code = ("import sys, time, json, numpy as np, oracle; f = oracle.embed(np.load(sys.argv[1])); "
+            "n = f.shape[0] - 2; p = oracle.Problem(n=n, h=1.0 / n, bc=sys.argv[2], rtol=1e-10); "
+            "t = time.perf_counter(); _, r = oracle.solve(p, f); dt = time.perf_counter() - t; "
+            "print(json.dumps([r.cycles, dt]))")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code, fpath, bc], env=env, capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.abspath(__file__)), timeout=300)
+    os.remove(fpath)
+    cycles, dt = json.loads(out.stdout.strip().splitlines()[-1])
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=n * n * cycles / dt, unit="grid-pts*V-cycles/s", threads=1,
+                sample=f"one {n}^2 periodic solve to 1e-10 ({cycles} cycles), {dt:.1f} s",
+                host_cpu=model, host_threads=os.cpu_count())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,6 +601,10 @@ def main():
         log("CPU oracle sample")
         cpu = cpu_baseline(f4096, n, "PPPP")
         log(f"oracle: {cpu['value'] / 1e9:.3f} G pts*cycles/s on {cpu['cores']} threads")
+        if not args.quick:
+            also["cpu_oracle_1_thread"] = cpu_single_thread(f4096, n, "PPPP")
+            log(f"oracle, 1 thread: {also['cpu_oracle_1_thread']['value'] / 1e9:.3f} G pts*cycles/s "
+                f"({also['cpu_oracle_1_thread']['host_cpu']})")
 
     line = {
         "metric": "time-to-1e-10 residual & grid-pts*V-cycles/s (HBM % peak), plain vs mixed/batched/learned",
