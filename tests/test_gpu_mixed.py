@@ -127,14 +127,14 @@ def test_mixed_tile_kernel_matches_row_march(bc, monkeypatch):
     finest run as row-march bands or as 2-D LDS tiles (bitwise; singular
     problems to rounding, their coarse means being sums grouped by tile)."""
     monkeypatch.setenv("CCMG_PAIR", "0")  # every level's own launches
-    n = 512
+    n = 1024
     fv = np.random.default_rng(33).standard_normal((n, n))
     if exact.is_singular(0.0, bc):
         fv -= fv.mean()
     outs = []
     for mode in ("march", "tile"):
         plan = mixed_plan(n, bc)
-        for level in range(1, 4):  # 256, 128, 64 (32 and below run in the tail)
+        for level in range(1, 4):  # 512, 256, 128 (the tail starts at 64 or 32)
             for kind in (0, 1):
                 if mode == "tile":
                     cc.ccmg_plan_set_shape(plan, level, kind, 0, 1)
