@@ -395,18 +395,25 @@ __global__ __launch_bounds__(256) void k_encode(const double *__restrict__ f, lo
 // the network output.  FP32 (it is only a guess).  One workgroup of 512
 // threads: the first 256 each keep an 8 x 8 block in registers and exchange
 // only block edges through LDS.  Output: G x G FP64 (no ghosts).
+// LDS layout of the G x G grid: one pad word after every 8 columns and rows of
+// kRelaxRow words, so that the 64 lanes of a wave (16 blocks across, 4 block
+// rows down) reading or writing one edge cell each hit 64 different banks
+// (a plain 128-word row put them on 8).
+constexpr int kRelaxRow = kNetG + kNetG / 8 + 2;  // 146
+__device__ __forceinline__ int relax_at(int r, int c) { return r * kRelaxRow + c + (c >> 3); }
+
 __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__restrict__ y,
                                                                 const float *__restrict__ x,
                                                                 const double *__restrict__ sumsq, int nfine,
                                                                 double length, int iters,
                                                                 double *__restrict__ out) {
     constexpr int B = 8, NB = kNetG / B, m = kNetG - 1;  // 16 x 16 blocks of 8 x 8 cells
-    __shared__ float u[kNetG][kNetG];
+    __shared__ float u[kNetG * kRelaxRow];
     const int t = threadIdx.x;
     const double rms = rms_scale(sumsq, nfine);
     const float su = (float)(rms * length * length);
     const float h2 = (float)(length * length / ((double)kNetG * kNetG));
-    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) u[q / kNetG][q % kNetG] = y[q] * su;
+    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) u[relax_at(q / kNetG, q % kNetG)] = y[q] * su;
     __syncthreads();
     if (t < NB * NB) {
         const int R0 = B * (t / NB), C0 = B * (t % NB);  // block origin (even: block parity = global parity)
@@ -415,7 +422,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__r
         for (int i = 0; i < B; ++i)
 #pragma unroll
             for (int j = 0; j < B; ++j) {
-                v[i][j] = u[R0 + i][C0 + j];
+                v[i][j] = u[relax_at(R0 + i, C0 + j)];
                 hf[i][j] = -h2 * (float)(x[(R0 + i) * kNetG + C0 + j] * rms);
             }
         const int up = (R0 - 1) & m, dn = (R0 + B) & m, lf = (C0 - 1) & m, rt = (C0 + B) & m;
@@ -429,10 +436,10 @@ __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__r
 #pragma unroll
                     for (int j = 0; j < B; ++j) {
                         if (((i + j) & 1) != c) continue;
-                        const float w = j > 0 ? v[i][j - 1] : u[R0 + i][lf];
-                        const float e = j < B - 1 ? v[i][j + 1] : u[R0 + i][rt];
-                        const float nn = i > 0 ? v[i - 1][j] : u[up][C0 + j];
-                        const float ss = i < B - 1 ? v[i + 1][j] : u[dn][C0 + j];
+                        const float w = j > 0 ? v[i][j - 1] : u[relax_at(R0 + i, lf)];
+                        const float e = j < B - 1 ? v[i][j + 1] : u[relax_at(R0 + i, rt)];
+                        const float nn = i > 0 ? v[i - 1][j] : u[relax_at(up, C0 + j)];
+                        const float ss = i < B - 1 ? v[i + 1][j] : u[relax_at(dn, C0 + j)];
                         v[i][j] = 0.25f * (hf[i][j] + ((e + w) + (ss + nn)));  // u = (sum - h^2 f) / 4
                     }
                 // publish the updated edge cells
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__r
 #pragma unroll
                     for (int j = 0; j < B; ++j) {
                         if (((i + j) & 1) != c) continue;
-                        if (i == 0 || i == B - 1 || j == 0 || j == B - 1) u[R0 + i][C0 + j] = v[i][j];
+                        if (i == 0 || i == B - 1 || j == 0 || j == B - 1) u[relax_at(R0 + i, C0 + j)] = v[i][j];
                     }
                 __syncthreads();
             }
@@ -449,12 +456,12 @@ __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__r
 #pragma unroll
         for (int i = 0; i < B; ++i)
 #pragma unroll
-            for (int j = 0; j < B; ++j) u[R0 + i][C0 + j] = v[i][j];
+            for (int j = 0; j < B; ++j) u[relax_at(R0 + i, C0 + j)] = v[i][j];
     } else {
         for (int it = 0; it < 2 * iters; ++it) __syncthreads();  // keep the barrier count of the relaxing threads
     }
     __syncthreads();
-    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) out[q] = (double)u[q / kNetG][q % kNetG];
+    for (int q = t; q < kNetG * kNetG; q += kRelaxThreads) out[q] = (double)u[relax_at(q / kNetG, q % kNetG)];
 }
 
 // Decoder step: one multigrid prolongation (centred slopes, no xy term,
