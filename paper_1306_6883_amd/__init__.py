@@ -622,7 +622,7 @@ def ccmg_net_encode(net: Net, a: torch.Tensor, scale_src: torch.Tensor, out: tor
     return out
 
 
-COARSE_ITERS = 16  # default relaxation iterations on the network's grid
+COARSE_ITERS = 32  # default relaxation iterations on the network's grid
 
 
 def ccmg_net_guess(net: Net, f: torch.Tensor, phi: torch.Tensor, length: float = 1.0,
