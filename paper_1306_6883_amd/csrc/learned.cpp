@@ -109,10 +109,15 @@ hipError_t forward(ccmg_net *N, const float *x, float *y, int nb) {
     hipLaunchKernelGGL(k_conv_in, dim3((npix + 255) / 256), dim3(256), 0, s, x, N->w() + net_param_offset(0),
                        N->act(0), N->act_lo(0), nb, net_dilation(0));
     const int waves = nb * kNetG * (kNetG / 32);
-    for (int l = 1; l <= 4; ++l)
-        hipLaunchKernelGGL(k_conv32, dim3((waves + 3) / 4), dim3(256), 0, s, N->act(l - 1), N->act_lo(l - 1),
-                           N->w16() + net_param_offset(l), N->at<__bf16>(N->L.w16lo) + net_param_offset(l),
-                           N->act(l), N->act_lo(l), nb, net_dilation(l));
+    for (int l = 1; l <= 4; ++l) {
+        const __bf16 *wl = N->w16() + net_param_offset(l), *wlo = N->at<__bf16>(N->L.w16lo) + net_param_offset(l);
+        if (nb <= kConvSplitMaxBatch)  // too few tiles for the GPU: three wavefronts per tile
+            hipLaunchKernelGGL(k_conv32<3>, dim3(waves), dim3(192), 0, s, N->act(l - 1), N->act_lo(l - 1), wl, wlo,
+                               N->act(l), N->act_lo(l), nb, net_dilation(l));
+        else
+            hipLaunchKernelGGL(k_conv32<1>, dim3((waves + 3) / 4), dim3(256), 0, s, N->act(l - 1),
+                               N->act_lo(l - 1), wl, wlo, N->act(l), N->act_lo(l), nb, net_dilation(l));
+    }
     hipLaunchKernelGGL(k_conv_out, dim3((npix + 255) / 256), dim3(256), 0, s, N->act(4), N->act_lo(4),
                        N->w() + net_param_offset(5), y, nb, net_dilation(5));
     return hipGetLastError();
@@ -152,7 +157,7 @@ hipError_t backward(ccmg_net *N, const float *x, const float *t, int nb) {
         hipLaunchKernelGGL(k_conv32_wgrad, dim3((3 * wg_waves + 3) / 4), dim3(256), 0, s, gcur, N->act(l - 1), part, npix,
                            kWgChunk, net_dilation(l));
         sum_partials(N, part, wg_waves, kWmid, grad + net_param_offset(l));
-        hipLaunchKernelGGL(k_conv32, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur, (const __bf16 *)nullptr,
+        hipLaunchKernelGGL(k_conv32<1>, dim3((cv_waves + 3) / 4), dim3(256), 0, s, gcur, (const __bf16 *)nullptr,
                            N->at<__bf16>(N->L.wt16) + (size_t)(l - 1) * kWmid, (const __bf16 *)nullptr, gnext, (__bf16 *)nullptr, nb,
                            net_dilation(l));
         std::swap(gcur, gnext);

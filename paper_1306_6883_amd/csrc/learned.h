@@ -19,8 +19,11 @@ constexpr int kNetParams = kW0 + 4 * kWmid + kW5;  // 37440
 inline int net_param_offset(int layer) { return layer == 0 ? 0 : kW0 + (layer - 1) * kWmid; }
 inline int net_dilation(int layer) { return 1 << layer; }
 
+template <int SPLIT>
 __global__ void k_conv32(const __bf16 *in, const __bf16 *in_lo, const __bf16 *w, const __bf16 *w_lo, __bf16 *out,
                          __bf16 *out_lo, int nb, int dil);
+// batches of at most this many images run k_conv32<3> in the forward pass
+constexpr int kConvSplitMaxBatch = 2;
 __global__ void k_conv32_wgrad(const __bf16 *g, const __bf16 *in, float *part, int npix, int chunk, int dil);
 __global__ void k_sum_partials(const float *part, int count, int len, float *out);
 __global__ void k_sum_partials_grouped(const float *part, int count, int len, int groups, float *out);

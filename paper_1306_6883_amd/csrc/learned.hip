@@ -46,14 +46,20 @@ __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_c
 // products take two MFMAs (hi and lo against the same BF16 weights), and with
 // `out_lo` the FP32 sum is written as such a pair.  Without them (gradients)
 // one BF16 value.
+// SPLIT = 1: four tiles per workgroup of 256, one per wavefront.  SPLIT = 3
+// (small batches, too few tiles to occupy the GPU): one tile per workgroup of
+// 192; wavefront s takes taps 3s .. 3s + 2 and the first adds the other two's
+// partial sums from LDS, (acc0 + acc1) + acc2.
+template <int SPLIT>
 __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, const __bf16 *__restrict__ in_lo,
                                                 const __bf16 *__restrict__ w, const __bf16 *__restrict__ w_lo,
                                                 __bf16 *__restrict__ out, __bf16 *__restrict__ out_lo, int nb,
                                                 int dil) {
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wave = SPLIT == 1 ? blockIdx.x * 4 + wib : blockIdx.x;
     const int tiles_per_row = kNetG / 32;
-    if (wave >= nb * kNetG * tiles_per_row) return;
+    if (wave >= nb * kNetG * tiles_per_row) return;  // uniform over the workgroup when SPLIT > 1
     const int b = wave / (kNetG * tiles_per_row);
     const int rem = wave - b * kNetG * tiles_per_row;
     const int y = rem / tiles_per_row;
@@ -61,8 +67,10 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
     const int r = lane & 31, hk = lane >> 5;
     const size_t img = (size_t)b * kNetG * kNetG * kNetC;
     f32x16 acc = {};
+    const int t0 = SPLIT == 1 ? 0 : 3 * wib;
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
+    for (int tt = 0; tt < 9 / SPLIT; ++tt) {
+        const int t = t0 + tt;
         const int ys = wrapg(y + tap_dy(t, dil));
         const int xs = wrapg(x0 + r + tap_dx(t, dil));
         const size_t px = img + ((size_t)ys * kNetG + xs) * kNetC;
@@ -78,6 +86,18 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, load8(w_lo + wo), acc, 0, 0, 0);
         }
     }
+    if constexpr (SPLIT > 1) {
+        __shared__ float part[SPLIT - 1][16][64];
+        if (wib > 0)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) part[wib - 1][j][lane] = acc[j];
+        __syncthreads();
+        if (wib > 0) return;
+#pragma unroll
+        for (int s = 0; s < SPLIT - 1; ++s)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] += part[s][j][lane];
+    }
     const size_t o = (((size_t)b * kNetG + y) * kNetG + x0) * kNetC;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -87,6 +107,11 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
         if (out_lo) out_lo[o + (size_t)row * kNetC + r] = (__bf16)(acc[j] - (float)hi);
     }
 }
+
+template __global__ void k_conv32<1>(const __bf16 *, const __bf16 *, const __bf16 *, const __bf16 *, __bf16 *,
+                                      __bf16 *, int, int);
+template __global__ void k_conv32<3>(const __bf16 *, const __bf16 *, const __bf16 *, const __bf16 *, __bf16 *,
+                                      __bf16 *, int, int);
 
 // Weight gradient of a 32 -> 32 layer:
 //   dw[co][tap][ci] = sum_{b, y, x} g[b][y][x][co] * in[b][y + dy][x + dx][ci]
