@@ -237,13 +237,22 @@ __global__ void k_conv_in(const float *__restrict__ x, const float *__restrict__
 #pragma unroll
     for (int t = 0; t < 9; ++t)
         v[t] = x[((size_t)b * kNetG + wrapg(y + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))];
-    for (int co = 0; co < kNetC; ++co) {
-        float s = 0.f;
+    // the pixel's 32 channels (64 B each for hi and lo) as 16-byte stores
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s += w1[co * 9 + t] * v[t];
-        const __bf16 hi = (__bf16)s;
-        out[(size_t)q * kNetC + co] = hi;
-        out_lo[(size_t)q * kNetC + co] = (__bf16)(s - (float)hi);
+    for (int c8 = 0; c8 < kNetC; c8 += 8) {
+        bf16x8 h8, l8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int co = c8 + k;
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s += w1[co * 9 + t] * v[t];
+            const __bf16 hi = (__bf16)s;
+            h8[k] = hi;
+            l8[k] = (__bf16)(s - (float)hi);
+        }
+        *reinterpret_cast<bf16x8 *>(out + (size_t)q * kNetC + c8) = h8;
+        *reinterpret_cast<bf16x8 *>(out_lo + (size_t)q * kNetC + c8) = l8;
     }
 }
 
@@ -255,11 +264,21 @@ __global__ void k_conv_out(const __bf16 *__restrict__ in, const __bf16 *__restri
     if (q >= nb * kNetG * kNetG) return;
     const int b = q / (kNetG * kNetG), rem = q - b * kNetG * kNetG, yy = rem / kNetG, xx = rem % kNetG;
     float s = 0.f;
+#pragma unroll 3
     for (int t = 0; t < 9; ++t) {
         const size_t px =
             (((size_t)b * kNetG + wrapg(yy + tap_dy(t, dil))) * kNetG + wrapg(xx + tap_dx(t, dil))) * kNetC;
+        // the neighbour's 32 channels as four 16-byte loads of hi and of lo;
+        // the sum runs over ci in order as before
+        bf16x8 h8[4], l8[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            h8[c] = load8(in + px + 8 * c);
+            l8[c] = load8(in_lo + px + 8 * c);
+        }
+#pragma unroll
         for (int ci = 0; ci < kNetC; ++ci)
-            s += w6[t * kNetC + ci] * ((float)in[px + ci] + (float)in_lo[px + ci]);
+            s += w6[t * kNetC + ci] * ((float)h8[ci >> 3][ci & 7] + (float)l8[ci >> 3][ci & 7]);
     }
     y[q] = s;
 }
@@ -274,11 +293,17 @@ __global__ void k_conv_out_bwd(const float *__restrict__ dy, const float *__rest
 #pragma unroll
     for (int t = 0; t < 9; ++t)
         d[t] = (float)(__bf16)dy[((size_t)b * kNetG + wrapg(yy - tap_dy(t, dil))) * kNetG + wrapg(xx - tap_dx(t, dil))];
-    for (int ci = 0; ci < kNetC; ++ci) {
-        float s = 0.f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s += (float)(__bf16)w6[t * kNetC + ci] * d[t];
-        g[(size_t)q * kNetC + ci] = (__bf16)s;
+    for (int c8 = 0; c8 < kNetC; c8 += 8) {  // 16-byte stores of 8 channels
+        bf16x8 g8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s += (float)(__bf16)w6[t * kNetC + c8 + k] * d[t];
+            g8[k] = (__bf16)s;
+        }
+        *reinterpret_cast<bf16x8 *>(g + (size_t)q * kNetC + c8) = g8;
     }
 }
 
