@@ -39,7 +39,7 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, __bf16 *w16
                        float b2, float eps, float c1, float c2);
 __global__ void k_to_bf16(const float *a, __bf16 *b, __bf16 *lo, int count);
 __global__ void k_encode(const double *f, long pitch, int n, const double *sumsq, float *out);
-constexpr int kRelaxThreads = 512;
+constexpr int kRelaxThreads = 1024;
 __global__ void k_coarse_relax(const float *y, const float *x, const double *sumsq, int nfine, double length,
                                int iters, double *out);
 __global__ void k_decode_step(const double *c, int nc, double *fine, long out_pitch, int ghosted);

@@ -442,22 +442,24 @@ __global__ __launch_bounds__(256) void k_encode(const double *__restrict__ f, lo
 // `iters` red-black Gauss-Seidel iterations of the periodic Poisson problem
 // Lap u = f on that grid against the encoded right-hand side (x times the
 // RMS), red ((row + column) even) first, which remove the grid-scale noise of
-// the network output.  FP32 (it is only a guess).  One workgroup of 512
-// threads: the first 256 each keep an 8 x 8 block in registers and exchange
-// only block edges through LDS.  Output: G x G FP64 (no ghosts).
-// LDS layout of the G x G grid: one pad word after every 8 columns and rows of
-// kRelaxRow words, so that the 64 lanes of a wave (16 blocks across, 4 block
+// the network output.  FP32 (it is only a guess).  One workgroup of 1024
+// threads, each keeping a 4 x 4 block in registers and exchanging only block
+// edges through LDS.  Output: G x G FP64 (no ghosts).
+// LDS layout of the G x G grid: one pad word after every 4 columns and rows of
+// kRelaxRow words, so that the 64 lanes of a wave (32 blocks across, 2 block
 // rows down) reading or writing one edge cell each hit 64 different banks
-// (a plain 128-word row put them on 8).
-constexpr int kRelaxRow = kNetG + kNetG / 8 + 2;  // 146
-__device__ __forceinline__ int relax_at(int r, int c) { return r * kRelaxRow + c + (c >> 3); }
+// (a plain 128-word row put them on far fewer).
+constexpr int kRelaxB = 4;
+constexpr int kRelaxRow = 168;
+__device__ __forceinline__ int relax_at(int r, int c) { return r * kRelaxRow + c + (c >> 2); }
 
 __global__ __launch_bounds__(kRelaxThreads) void k_coarse_relax(const float *__restrict__ y,
                                                                 const float *__restrict__ x,
                                                                 const double *__restrict__ sumsq, int nfine,
                                                                 double length, int iters,
                                                                 double *__restrict__ out) {
-    constexpr int B = 8, NB = kNetG / B, m = kNetG - 1;  // 16 x 16 blocks of 8 x 8 cells
+    constexpr int B = kRelaxB, NB = kNetG / B, m = kNetG - 1;  // 32 x 32 blocks of 4 x 4 cells
+    static_assert(NB * NB <= kRelaxThreads, "one block per thread");
     __shared__ float u[kNetG * kRelaxRow];
     const int t = threadIdx.x;
     const double rms = rms_scale(sumsq, nfine);
