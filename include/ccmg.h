@@ -357,7 +357,8 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  * "subtract_gradient" passes.
  * `bytes` is the algorithmic traffic of one launch: each valid cell of each
  * array the launch reads or writes, counted once (ghost cells and halo
- * re-reads excluded). */
+ * re-reads excluded).  Launches of a cycle queued after the one that met the
+ * tolerance (they exit as soon as they start) are not counted. */
 typedef struct {
     char name[32];
     int launches;          /* launches timed since profiling was (re)enabled */

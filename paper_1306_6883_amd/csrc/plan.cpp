@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -164,6 +165,7 @@ struct KernelTimer {
     std::vector<hipEvent_t> ev;          // 2 * kPairs
     int used = 0;
     int kind[kPairs];
+    int cyc[kPairs];  // cycle (refinement step) of a solve the launch belongs to, 0 outside solves
     double bytes[kPairs];
     int launches[kKinds] = {};
     double ms[kKinds] = {}, tbytes[kKinds] = {};
@@ -179,6 +181,7 @@ struct ccmg_plan {
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     bool pair_down[kMaxLevels] = {};  // levels l, l+1 pre-smoothed in one launch (2-D tiles)
     int n_bottom = 2;  // 4 or 8: exact solve on that level (ccmg_plan_set_bottom)
+    int tcycle = 0;    // cycle being enqueued by the solve loop (tags timed launches)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
     double *drho = nullptr;   // ... its device address
     Layout lay;
@@ -199,6 +202,7 @@ struct ccmg_plan {
         if (!timer.on || timer.used >= KernelTimer::kPairs) return -1;
         const int i = timer.used++;
         timer.kind[i] = kind;
+        timer.cyc[i] = tcycle;
         timer.bytes[i] = bytes;
         hipEventRecord(timer.ev[2 * i], stream);
         return i;
@@ -206,10 +210,13 @@ struct ccmg_plan {
     void tstop(int i) {
         if (i >= 0) hipEventRecord(timer.ev[2 * i + 1], stream);
     }
-    // Fold finished pairs into the per-kind totals.
-    void tcollect() {
+    // Fold finished pairs into the per-kind totals.  Launches of cycles after
+    // `last_cycle` were queued ahead of a convergence the device then flagged:
+    // they exited at once and are not counted.
+    void tcollect(int last_cycle = INT_MAX) {
         for (int i = 0; i < timer.used; ++i) {
             float ms = 0.f;
+            if (timer.cyc[i] > last_cycle) continue;
             if (hipEventElapsedTime(&ms, timer.ev[2 * i], timer.ev[2 * i + 1]) == hipSuccess) {
                 timer.launches[timer.kind[i]] += 1;
                 timer.ms[timer.kind[i]] += ms;
@@ -1532,6 +1539,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const int n = lay.lev[0].n;
     const bool mixed = P->p.prec == CCMG_MIXED;
     double *scal = P->scal();
+    P->tcycle = 0;
     hipError_t e = hipEventRecord(P->ev_t0, s);
 
     // statistics of f, reset of the flags, and the starting residual
@@ -1610,7 +1618,12 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         // most inner_max).  The first step runs 2 cycles and step 2 is queued
         // only once its residual is known: contraction rates range from about
         // 0.1 (Poisson) to below 1e-6 (strongly diagonal Helmholtz), and a
-        // blind guess either way costs whole cycles.
+        // blind guess either way costs whole cycles.  One a-priori bound is
+        // used: a red-black sweep of a diagonally dominant operator contracts
+        // the error by at least gamma = |4 beta / h^2| / |alpha + 4 beta / h^2|
+        // (max norm), so when gamma^(2 (nu1 + nu2)) <= 1e-3 a cycle's
+        // smoothing alone is worth three digits (its coarse correction, as
+        // measured, only adds to that) and the first step runs one cycle.
         auto mixed_rate = [&]() -> double {
             const int m = checked;
             if (m < 1 || !(rhos[m - 1] > 0.0) || !(rhos[m] > 0.0)) return 0.1;
@@ -1623,9 +1636,16 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             for (int i = checked + 1; i < j; ++i) r *= std::pow(rate, inner[i]);
             return r;
         };
+        const int first_inner = [&] {
+            const double h = P->lay.lev[0].h, c4 = 4.0 * P->p.beta / (h * h);
+            const double gamma = std::fabs(c4) / std::fabs(P->p.alpha + c4);
+            const bool diagonal = std::fabs(P->p.alpha + c4) > std::fabs(c4) &&
+                                  std::pow(gamma, 2.0 * (P->p.nu1 + P->p.nu2)) <= 1e-3;
+            return diagonal ? 1 : std::min(2, inner_max);
+        }();
         auto inner_for = [&](int j) -> int {
             if (inner_max <= 1) return 1;
-            if (j == 1 || checked == 0) return std::min(2, inner_max);
+            if (j == 1 || checked == 0) return first_inner;
             const double r = mixed_pred(j);
             if (!(r > P->p.rtol)) return 1;
             const int need = (int)std::ceil(std::log(P->p.rtol / r) / std::log(mixed_rate()));
@@ -1634,6 +1654,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
             hipError_t x;
+            P->tcycle = k;
             if (mixed) {
                 inner[k] = inner_for(k);
                 x = inner[k] >= 2 ? enqueue_mixed_step_inner(P, d_f, pitch, st, P->done(), k, inner[k])
@@ -1759,6 +1780,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (e != hipSuccess) return R->status = CCMG_EHIP;
     float ms = 0.f;
     hipEventElapsedTime(&ms, P->ev_t0, P->ev_t1);
+    P->tcycle = 0;
+    if (P->timer.on) P->tcollect(cycles);  // every launch has finished
     R->ms = ms;
     R->cycles = cycles;
     R->rel_resid = rho;

@@ -126,3 +126,23 @@ def test_fused_not_used_for_other_smoothing_counts():
     stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
     cc.ccmg_plan_profile(plan, False)
     assert stats["finest_fused"]["launches"] == 0
+
+
+@pytest.mark.parametrize("c", [0.1, 10.0])
+def test_kernel_stats_count_only_launches_that_ran(c):
+    """A well-conditioned Helmholtz solve converges in two or three cycles;
+    the launches queued ahead for the next cycle exit at once (the device
+    flags convergence first) and are left out of the timing statistics, so
+    the finest-level launches counted are exactly one per cycle plus the
+    first pre-smoothing."""
+    n = 1024
+    fv = W.gaussian_random_field(n, seed=4)
+    r, _, plan = solve(n, "PPPP", fv, alpha=1.0, beta=c / (2.0 * n * n))
+    cc.ccmg_plan_profile(plan, True)
+    phi = dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
+    stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
+    cc.ccmg_plan_profile(plan, False)
+    assert r.status == cc.OK
+    counted = sum(stats[k]["launches"] for k in ("finest_pre", "finest_post", "finest_fused"))
+    assert counted == r.cycles + 1, (counted, r.cycles)
