@@ -2,8 +2,8 @@
  * mg_oracle.c -- plain FP64 CPU multigrid for the cell-centred
  * constant-coefficient Helmholtz problem  (alpha - beta Lap) phi = f.
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
- * judged against.  Only tests/, the smoke check and the CPU-baseline leg of
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library's
+ * results are checked against.  Only tests/, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  It shares no code, header, table or constant
  * with the GPU library and includes nothing from it.
  *
