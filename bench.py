@@ -454,9 +454,13 @@ def roofline_of(meas, n_expected=None):
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(dom["name"], meas.get("fused_shape")) if n_expected == 4096 else None
+    # the counters' bytes over the same launch time (HBM traffic actually moved)
+    traffic_gbs = round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom["name"],
                 avg_launch_ms=round(avg_ms, 5), bytes_per_launch=bytes_per_launch,
+                traffic_gbs=traffic_gbs,
+                traffic_frac=round(traffic_gbs / HBM_PEAK_GBS, 4) if traffic_gbs else None,
                 all_kernels=[dict(name=k["name"], launches=k["launches"],
                                   avg_ms=round(k["ms"] / k["launches"], 5),
                                   gbs=round(k["bytes"] / k["launches"] / (k["ms"] / k["launches"] * 1e-3) / 1e9, 1))
@@ -571,7 +575,8 @@ def main():
     log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
         f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
     rl = roofline_of(m, n_expected=n)
-    log(f"dominant kernel {rl['kernel']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s ({rl['frac']:.3f})")
+    log(f"dominant kernel {rl['kernel']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s ({rl['frac']:.3f})"
+        + (f"; counter bytes {rl['traffic_gbs']} GB/s ({rl['traffic_frac']:.3f})" if rl["traffic_gbs"] else ""))
 
     also = {}
     if not args.quick:
@@ -624,7 +629,8 @@ def main():
                    "n": n, "bc": "periodic", "rtol": 1e-10, "cycles_per_solve": m["cycles_per_solve"],
                    "time_to_tol_ms": m["ms_per_solve"]},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "all_kernels")},
+        "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "traffic_gbs", "traffic_frac",
+                                                        "all_kernels")},
         "launch_shapes": {"levels": "finest first; (rows per band, waves per workgroup) of the nu1 and nu2 launches",
                           "value": m["shapes"], "fused": m["fused_shape"]},
         "cpu_baseline": cpu,
