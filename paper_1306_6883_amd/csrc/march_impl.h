@@ -225,9 +225,15 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     }
 
     const int tend = ye + C::LAST;
-    for (int tb = ys; tb < tend; tb += W) {
-        static_for<0, W>([&](auto kc) {
+    // One step of the march (row t = tb + k).  YBR: apply the y ghost rules.
+    // A y-side tile needs them only in the blocks of W steps whose rows reach
+    // y = 0 or y = n - 1 (the stages lag at most LAST rows behind t; the
+    // prolongation reads one coarse row on either side of row t); elsewhere
+    // its selects would all keep the neighbour, so the interior step is the
+    // same arithmetic with fewer instructions.
+    auto step = [&](auto kc, auto ybc, const int tb) {
             constexpr int k = decltype(kc)::value;
+            constexpr bool YBR = decltype(ybc)::value;
             const int t = tb + k;
             // 1. prefetch
             {
@@ -267,7 +273,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 T cm = Cw[((k >> 1) + 0) % WC];
                 const T c0 = Cw[((k >> 1) + 1) % WC];
                 T cp = Cw[((k >> 1) + 2) % WC];
-                if constexpr (YB) {
+                if constexpr (YBR) {
                     if (J - 1 < 0) cm = syl * cm;    // coarse ghost row below
                     if (J + 1 >= nc) cp = syh * cp;  // coarse ghost row above
                 }
@@ -302,7 +308,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.wedge) w = sxl * self;
                     }
                     T nn = P0[kp], ss = P0[km];
-                    if constexpr (YB) {
+                    if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
                     }
@@ -315,7 +321,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e = sxh * self;
                     }
                     T nn = P1[kp], ss = P1[km];
-                    if constexpr (YB) {
+                    if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
                     }
@@ -341,7 +347,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e1 = sxh * p1;
                     }
                     T n0 = P0[kp], n1 = P1[kp], s0 = SA[1 - sv], s1 = SB[1 - sv];
-                    if constexpr (YB) {
+                    if constexpr (YBR) {
                         if (y == nm) {
                             n0 = syh * p0;
                             n1 = syh * p1;
@@ -405,7 +411,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e1 = (double)sxh * p1;
                     }
                     double n0 = Q0[kp], n1 = Q1[kp], s0 = Q0[km], s1 = Q1[km];
-                    if constexpr (YB) {
+                    if constexpr (YBR) {
                         if (y == nm) {
                             n0 = (double)syh * p0;
                             n1 = (double)syh * p1;
@@ -444,7 +450,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e1 = sxh * p1;
                     }
                     T n0 = P0[kp], n1 = P1[kp], s0 = P0[km], s1 = P1[km];
-                    if constexpr (YB) {
+                    if constexpr (YBR) {
                         if (y == nm) {
                             n0 = syh * p0;
                             n1 = syh * p1;
@@ -494,7 +500,19 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     }
                 }
             }
-        });
+    };
+    // three runs of blocks (the first and last empty unless YB): near y = 0,
+    // between, near y = n - 1
+    int tb = ys;
+    if constexpr (YB) {
+        for (; tb < tend && tb <= C::LAST + 2; tb += W)
+            static_for<0, W>([&](auto kc) { step(kc, std::true_type{}, tb); });
+    }
+    for (; tb < tend && (!YB || tb + W + 2 < nm); tb += W)
+        static_for<0, W>([&](auto kc) { step(kc, std::false_type{}, tb); });
+    if constexpr (YB) {
+        for (; tb < tend; tb += W)
+            static_for<0, W>([&](auto kc) { step(kc, std::true_type{}, tb); });
     }
 
     if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
