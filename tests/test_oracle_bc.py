@@ -113,8 +113,11 @@ def test_side_data_solve_matches_the_extended_dense_system(bc, ab):
     assert np.abs(oracle.interior(phi) - want).max() <= 1e-10 * np.abs(want).max()
 
 
-@pytest.mark.parametrize("bc", ["DDDD", "NNDD", "DNND", "NNNN", "PPDN"])
-@pytest.mark.parametrize("ab", [(0.0, -1.0), (1.0, 0.01)])
+# (all-Neumann Poisson is singular: its data fix phi only up to a constant,
+# which the test below covers)
+@pytest.mark.parametrize("bc,ab", [(bc, ab) for bc in ["DDDD", "NNDD", "DNND", "NNNN", "PPDN"]
+                                   for ab in [(0.0, -1.0), (1.0, 0.01)]
+                                   if not (bc == "NNNN" and ab[0] == 0.0)])
 def test_linear_functions_are_reproduced(bc, ab):
     n = 32
     h = 1.0 / n
@@ -125,8 +128,6 @@ def test_linear_functions_are_reproduced(bc, ab):
     else:
         lin = lambda X, Y: 0.3 + 1.7 * X - 0.6 * Y
         dx, dy = (lambda X, Y: 1.7 + 0.0 * X), (lambda X, Y: -0.6 + 0.0 * X)
-    if bc == "NNNN" and alpha == 0.0:
-        pytest.skip("singular: data fix phi only up to a constant (tested below)")
     t = centres(n)
     X, Y = np.meshgrid(t, t)
     f = alpha * lin(X, Y)  # Lap of a linear function is zero
