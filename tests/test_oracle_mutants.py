@@ -1,11 +1,16 @@
 """The oracle's pins catch plausible mistakes (CPU): each mutant below plants
 one mistake in a copy of the C oracle (a wrong sign, index, weight, side
 rule, colour order or grid spacing), the copy is compiled and swapped in, and
-at least one pin of tests/test_oracle_pins.py must fail on it."""
+at least one pin of tests/test_oracle_pins.py must fail on it.  The Python
+parts of the oracle get the same treatment: a mistake planted in a copy of
+oracle/exact.py (the array-form operator) or oracle/net.py (the network's
+emulated roundings) must fail one of the checks of test_oracle_exact.py or
+test_oracle_net_rounding.py run on that copy."""
 import importlib.util
 import os
 import shutil
 import subprocess
+import types
 
 import numpy as np
 import pytest
@@ -65,6 +70,17 @@ def _bottom_pins():
 
 
 Q = _bottom_pins()
+
+
+def _load_test_module(name, fname):
+    spec = importlib.util.spec_from_file_location(name, os.path.join(HERE, fname))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+X = _load_test_module("oracle_exact_pins", "test_oracle_exact.py")
+R = _load_test_module("oracle_net_rounding_pins", "test_oracle_net_rounding.py")
 
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
 MUTANTS = {
@@ -165,3 +181,73 @@ def test_pins_catch_mutant(name, tmp_path, monkeypatch):
     assert src.count(old) == 1, name
     failed = _failures(monkeypatch, _build(src.replace(old, new), str(tmp_path)))
     assert failed, f"no pin caught the mutant {name}"
+
+
+# ---- mistakes planted in the Python parts of the oracle
+# name -> (file under oracle/, text, replacement, checks run on the mutated module)
+EXACT_BATTERY = [
+    lambda E: X.check_apply_operator_equals_assembled(E, "DNPP", (0.0, -1.0)),
+    lambda E: X.check_apply_operator_equals_assembled(E, "PPDN", (1.0, 0.37)),
+    lambda E: X.check_relative_residual_equals_assembled(E, "NDDD", (0.0, -1.0)),
+    lambda E: X.check_residual_equals_c_oracle(E, "DDNN", (1.0, 0.37)),
+    lambda E: X.check_exact_solutions_have_rounding_residual(E),
+]
+NET_BATTERY = [
+    lambda N: R.check_worked_example(N),
+    lambda N: R.check_worked_example_unrounded(N),
+    lambda N: R.check_bound(N, 0, True),
+    lambda N: R.check_bound(N, 1, False),
+]
+PY_MUTANTS = {
+    # the last layer's weight gradient from the activations' hi part only
+    "net_backward_drops_pair_lo": ("net.py", "grads[5] = conv_w(g, a[5], DIL[5])",
+                                   "grads[5] = conv_w(g, hi[5], DIL[5])", NET_BATTERY),
+    # the back-propagated gradient rounded before the adjoint convolution, not after
+    "net_backward_rounding_moved": ("net.py", "        g = r(conv_t(g, ws[l], DIL[l]))",
+                                    "        g = conv_t(r(g), ws[l], DIL[l])", NET_BATTERY),
+    # the output gradient left unrounded
+    "net_output_gradient_unrounded": ("net.py", "g = r(2.0 * (y - t) / n)[..., None]",
+                                      "g = (2.0 * (y - t) / n)[..., None]", NET_BATTERY),
+    # activations between layers carried as one bfloat16 (the lo part dropped)
+    "net_forward_drops_activation_lo": ("net.py", "a.append(h + bf16(v - h))", "a.append(h)", NET_BATTERY),
+    # Dirichlet ghost with the Neumann sign in the array-form operator
+    "exact_operator_dirichlet_sign": ("exact.py", "g[sl_ghost] = -g[sl_in]", "g[sl_ghost] = g[sl_in]",
+                                      EXACT_BATTERY),
+    # periodic ghost copied from the adjacent cell instead of the opposite side
+    "exact_operator_periodic_side": ("exact.py", "g[sl_ghost] = g[sl_opp]", "g[sl_ghost] = g[sl_in]",
+                                     EXACT_BATTERY),
+}
+
+
+def _py_mutant(fname, old, new):
+    """A copy of oracle/<fname> with `old` replaced by `new`, loaded as a
+    module of the oracle package (its relative imports resolve there)."""
+    src = open(os.path.join(ORACLE_DIR, fname)).read()
+    assert src.count(old) == 1, (fname, old)
+    mod = types.ModuleType("oracle._mutant_" + fname[:-3])
+    mod.__package__ = "oracle"
+    mod.__file__ = os.path.join(ORACLE_DIR, fname)
+    exec(compile(src.replace(old, new), mod.__file__, "exec"), mod.__dict__)
+    return mod
+
+
+def _py_failures(mod, battery):
+    failed = 0
+    for check in battery:
+        try:
+            with np.errstate(all="ignore"):
+                check(mod)
+        except Exception:
+            failed += 1
+    return failed
+
+
+@pytest.mark.parametrize("fname,battery", [("exact.py", EXACT_BATTERY), ("net.py", NET_BATTERY)])
+def test_unmutated_python_copies_pass_their_battery(fname, battery):
+    assert _py_failures(_py_mutant(fname, "import numpy as np", "import numpy as np"), battery) == 0
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_pins_catch_python_mutant(name):
+    fname, old, new, battery = PY_MUTANTS[name]
+    assert _py_failures(_py_mutant(fname, old, new), battery) > 0, f"no pin caught the mutant {name}"
