@@ -3,16 +3,19 @@
 
 A step is one whole solve to tolerance (V(2,2) cycles of red-black
 Gauss-Seidel, four-cell restriction, centred-slope prolongation, 2x2 bottom
-solve, FP64 stop test) of the headline workload:
+solve, FP64 stop test) of the headline workload, the largest single-GPU
+configuration of the plain FP64 V-cycle:
 
-  Poisson on 4096 x 4096 cells, periodic sides, f = sum of 64 seeded Fourier
-  modes (|k| <= 32, N(0,1) amplitudes), zero mean, relative residual 1e-10.
+  Poisson on 8192 x 8192 cells, homogeneous Dirichlet sides, f = sum of 64
+  seeded Fourier modes (|k| <= 32, N(0,1) amplitudes), relative residual 1e-10.
 
 Inputs are generated on the host, uploaded once, and resident in HBM when the
 timed region starts.  The printed JSON line reports grid-points x V-cycles per
 second over the K timed solves, the roofline of the dominant kernel (measured
-with HIP events in a separate pass of the same K solves), the same workload on
-8192^2 with Dirichlet sides, and the FP64 CPU oracle timed on a bounded sample.
+with HIP events in a separate pass of the same K solves), the FP64 CPU oracle
+timed on a bounded sample of the same workload, and in `also` the other
+workloads (4096^2 periodic, the mixed, batched and learned forms, the next
+rows) and a streaming probe of this device.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -116,7 +119,8 @@ def mixed_vs_plain(cc, torch, W, steps):
     """Mixed precision against the plain FP64 form on the same problems: the
     Crank-Nicolson Helmholtz solves (1 - (k dt/2) Lap) phi = g on 8192^2
     (k dt / h^2 = 0.1, 1, 10; g a Gaussian random field of correlation length
-    0.05, periodic) and the headline 4096^2 Poisson problem."""
+    0.05, periodic), the 4096^2 periodic Poisson problem and the 8192^2
+    Dirichlet headline problem."""
     out = {}
     n = 8192
     g = W.gaussian_random_field(n, seed=0)
@@ -139,6 +143,16 @@ def mixed_vs_plain(cc, torch, W, steps):
     row["speedup"] = round(row["plain_fp64"]["ms"] / row["mixed"]["ms"], 3)
     out["poisson_4096_periodic"] = row
     log(f"poisson 4096^2: plain {row['plain_fp64']['ms']:.3f} ms, mixed {row['mixed']['ms']:.3f} ms, x{row['speedup']}")
+    del fv
+    n = 8192
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    row = {}
+    for name, prec in (("plain_fp64", cc.FP64), ("mixed", cc.MIXED)):
+        row[name] = time_form(cc, torch, cc.Problem(n=n, bc="D", rtol=1e-10, prec=prec), fv, steps, 1)
+    row["speedup"] = round(row["plain_fp64"]["ms"] / row["mixed"]["ms"], 3)
+    out["poisson_8192_dirichlet"] = row
+    log(f"poisson 8192^2 Dirichlet: plain {row['plain_fp64']['ms']:.3f} ms, mixed {row['mixed']['ms']:.3f} ms, "
+        f"x{row['speedup']}")
     return out
 
 
@@ -227,8 +241,8 @@ def side_data_solves(cc, torch, W, reps):
 
 
 def bottom_solver(cc, torch, W, steps):
-    """The bottom of the V-cycle on the headline problem (4096^2 periodic
-    Poisson, FP64 and mixed): 50 relaxations on 2 x 2 against an exact solve
+    """The bottom of the V-cycle on the 4096^2 periodic Poisson problem (FP64
+    and mixed): 50 relaxations on 2 x 2 against an exact solve
     on 4 x 4 or 8 x 8 (inverse operator from LDS).  Time to 1e-10, best of
     two alternating rounds of `steps` solves each."""
     n = 4096
@@ -415,20 +429,22 @@ def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
     return out
 
 
-PMC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                           "march_finest_fused_poisson4096_pmc.md")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+# counter summaries of the fused finest launch, per workload
+PMC_SUMMARY = {8192: os.path.join(PROFILES, "march_finest_fused_dirichlet8192_pmc.md"),
+               4096: os.path.join(PROFILES, "march_finest_fused_poisson4096_pmc.md")}
 
 
-def measured_traffic(kernel: str, shape=None):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+def measured_traffic(kernel: str, shape, summary: str):
+    """HBM bytes per launch of `kernel` from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
     None when there is none, the kernel's sources changed since, or the
     autotuner chose another launch shape (rows per band, waves per workgroup)
     than the one the counters were taken with."""
     import hashlib
     try:
-        text = open(PMC_SUMMARY).read()
-    except OSError:
+        text = open(summary).read()
+    except (OSError, TypeError):
         return None
     fields = dict(re.findall(r"^\s+(\w+): (.+)$", text, flags=re.M))
     if fields.get("kernel") != kernel:
@@ -447,13 +463,13 @@ def measured_traffic(kernel: str, shape=None):
     return float(fields[key])
 
 
-def roofline_of(meas, n_expected=None):
+def roofline_of(meas):
     ks = [k for k in meas["kernels"] if k["launches"] > 0]
     dom = max(ks, key=lambda k: k["ms"])
     avg_ms = dom["ms"] / dom["launches"]
     bytes_per_launch = dom["bytes"] / dom["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom["name"], meas.get("fused_shape")) if n_expected == 4096 else None
+    traffic = measured_traffic(dom["name"], meas.get("fused_shape"), PMC_SUMMARY.get(meas["n"]))
     # the counters' bytes over the same launch time (HBM traffic actually moved)
     traffic_gbs = round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -469,7 +485,8 @@ def roofline_of(meas, n_expected=None):
 
 def cpu_baseline(fv, n, bc, budget_s=10.0):
     """The FP64 CPU oracle on a bounded sample of the same workload: whole
-    solves to 1e-10 repeated until about `budget_s` seconds have passed."""
+    solves to 1e-10 repeated until about `budget_s` seconds have passed (at
+    least one)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     p = oracle.Problem(n=n, h=1.0 / n, bc=bc, rtol=1e-10)
@@ -485,8 +502,11 @@ def cpu_baseline(fv, n, bc, budget_s=10.0):
             break
     return {"value": n * n * cycles / dt, "unit": "grid-pts*V-cycles/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{solves} whole {n}^2 periodic solves to 1e-10 ({cycles} V(2,2) cycles), "
-                      f"plain C + OpenMP, {dt:.1f} s"}
+            "sample": f"{solves} whole {n}^2 {SIDE_NAMES[bc]} solves to 1e-10 ({cycles} V(2,2) cycles), "
+                      f"plain C + OpenMP, {dt:.1f} s ({dt / solves:.2f} s per solve)"}
+
+
+SIDE_NAMES = {"DDDD": "Dirichlet", "PPPP": "periodic"}
 
 
 def cpu_single_thread(fv, n, bc):
@@ -513,8 +533,24 @@ def cpu_single_thread(fv, n, bc):
     except OSError:
         pass
     return dict(value=n * n * cycles / dt, unit="grid-pts*V-cycles/s", threads=1,
-                sample=f"one {n}^2 periodic solve to 1e-10 ({cycles} cycles), {dt:.1f} s",
+                sample=f"one {n}^2 {SIDE_NAMES[bc]} solve to 1e-10 ({cycles} cycles), {dt:.1f} s",
                 host_cpu=model, host_threads=os.cpu_count())
+
+
+def stream_probe(cc, torch, n):
+    """What this device's memory delivers for the fused launch's compulsory
+    pattern: c = a + b over three FP64 arrays of n^2 values (the library's
+    streaming probe, HIP events over 20 launches)."""
+    a = torch.full((n * n,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    ms = cc.ccmg_probe_stream(a, b, c, reps=20)
+    assert float(c[-1]) == 3.0
+    gbs = 3 * 8 * n * n / (ms * 1e-3) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    return dict(n=n, bytes_per_launch=3 * 8 * n * n, ms=round(ms, 5), gbs=round(gbs, 1),
+                frac_of_peak=round(gbs / HBM_PEAK_GBS, 4))
 
 
 def main():
@@ -523,7 +559,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the 8192^2 run and the other forms")
+    ap.add_argument("--quick", action="store_true", help="only the headline workload (no other legs)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess leg")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-guess leg and print its result (profiling aid)")
@@ -532,7 +568,7 @@ def main():
     ap.add_argument("--next-rows-only", action="store_true",
                     help="only the Crank-Nicolson, side-data and projection legs (one JSON line of their own)")
     ap.add_argument("--fused-shape", type=str, default=None,
-                    help="TY,WPB: rows per band and waves per workgroup of the 4096^2 fused launch, "
+                    help="TY,WPB: rows per band and waves per workgroup of the headline's fused launch, "
                          "instead of the autotuner's choice (for counter runs)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -555,9 +591,9 @@ def main():
                           "projection": projection(cc, torch, 5), "bottom_solver": bottom_solver(cc, torch, W, 20)}),
               flush=True)
         return
-    n = 4096
+    n = 8192
     log("generating inputs")
-    f4096 = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    f_head = W.fourier_modes(n, seed=0, count=64, kmax=32)
 
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -569,29 +605,33 @@ def main():
         log("copy probe: 1 GiB read + 1 GiB written")
         del a, b
 
-    log(f"{n}^2 periodic: {args.warmup} warmup + {args.steps} timed solves")
+    log(f"{n}^2 Dirichlet: {args.warmup} warmup + {args.steps} timed solves")
     fshape = tuple(int(x) for x in args.fused_shape.split(",")) if args.fused_shape else None
-    m = measure(cc, torch, n, "P", f4096, args.steps, args.warmup, fused_shape=fshape)
+    m = measure(cc, torch, n, "D", f_head, args.steps, args.warmup, fused_shape=fshape)
     log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
         f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
-    rl = roofline_of(m, n_expected=n)
-    log(f"dominant kernel {rl['kernel']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s ({rl['frac']:.3f})"
-        + (f"; counter bytes {rl['traffic_gbs']} GB/s ({rl['traffic_frac']:.3f})" if rl["traffic_gbs"] else ""))
+    rl = roofline_of(m)
+    log(f"dominant kernel {rl['kernel']} {m['fused_shape']}: {rl['avg_launch_ms']:.4f} ms, {rl['achieved']} GB/s "
+        f"({rl['frac']:.3f})" + (f"; counter bytes {rl['traffic_gbs']} GB/s ({rl['traffic_frac']:.3f})"
+                                  if rl["traffic_gbs"] else ""))
 
     also = {}
     if not args.quick:
-        n8 = 8192
-        f8 = W.fourier_modes(n8, seed=0, count=64, kmax=32)
-        log(f"{n8}^2 Dirichlet: 1 warmup + {max(args.steps // 4, 2)} timed solves")
-        m8 = measure(cc, torch, n8, "D", f8, max(args.steps // 4, 2), 1)
-        rl8 = roofline_of(m8)
-        also["dirichlet_8192"] = dict(ms_per_solve=round(m8["ms_per_solve"], 3),
-                                      cycles_per_solve=m8["cycles_per_solve"],
-                                      value=m8["pts_cycles_per_s"], rel_resid=m8["rel_resid"],
-                                      roofline=rl8)
-        log(f"8192^2: {m8['ms_per_solve']:.3f} ms/solve, {m8['pts_cycles_per_s'] / 1e9:.2f} G; "
-            f"{rl8['kernel']} {rl8['achieved']} GB/s")
-        del f8
+        also["stream_probe"] = [stream_probe(cc, torch, k) for k in (8192, 4096)]
+        log("stream probe (read 2, write 1): " + ", ".join(f"{p['n']}^2 {p['gbs']} GB/s" for p in also["stream_probe"]))
+        n4 = 4096
+        f4 = W.fourier_modes(n4, seed=0, count=64, kmax=32)
+        log(f"{n4}^2 periodic: {args.warmup} warmup + {args.steps} timed solves")
+        m4 = measure(cc, torch, n4, "P", f4, args.steps, args.warmup)
+        rl4 = roofline_of(m4)
+        also["periodic_4096"] = dict(ms_per_solve=round(m4["ms_per_solve"], 4),
+                                     cycles_per_solve=m4["cycles_per_solve"],
+                                     value=m4["pts_cycles_per_s"], rel_resid=m4["rel_resid"],
+                                     roofline=rl4, fused_shape=m4["fused_shape"])
+        log(f"{n4}^2: {m4['ms_per_solve']:.3f} ms/solve, {m4['pts_cycles_per_s'] / 1e9:.2f} G; "
+            f"{rl4['kernel']} {rl4['achieved']} GB/s" +
+            (f", counter bytes {rl4['traffic_gbs']} GB/s" if rl4["traffic_gbs"] else ""))
+        del f4
         also["mixed_precision"] = mixed_vs_plain(cc, torch, W, max(args.steps // 4, 3))
         also["batched"] = batched_vs_sequential(cc, torch, W, 3)
         also["cn_diffusion"] = cn_diffusion(cc, torch, 10)
@@ -604,10 +644,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("CPU oracle sample")
-        cpu = cpu_baseline(f4096, n, "PPPP")
-        log(f"oracle: {cpu['value'] / 1e9:.3f} G pts*cycles/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(f_head, n, "DDDD")
+        log(f"oracle: {cpu['value'] / 1e9:.3f} G pts*cycles/s on {cpu['cores']} threads ({cpu['sample']})")
         if not args.quick:
-            also["cpu_oracle_1_thread"] = cpu_single_thread(f4096, n, "PPPP")
+            also["cpu_oracle_1_thread"] = cpu_single_thread(f_head, n, "DDDD")
             log(f"oracle, 1 thread: {also['cpu_oracle_1_thread']['value'] / 1e9:.3f} G pts*cycles/s "
                 f"({also['cpu_oracle_1_thread']['host_cpu']})")
 
@@ -624,9 +664,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 V(2,2) Poisson 4096^2 periodic, 64 Fourier modes |k|<=32, "
-                               "zero mean, seed 0, to relative residual 1e-10",
-                   "n": n, "bc": "periodic", "rtol": 1e-10, "cycles_per_solve": m["cycles_per_solve"],
+        "config": {"workload": "plain FP64 V(2,2) Poisson 8192^2 homogeneous Dirichlet, 64 Fourier modes |k|<=32, "
+                               "seed 0, to relative residual 1e-10",
+                   "n": n, "bc": "Dirichlet", "rtol": 1e-10, "cycles_per_solve": m["cycles_per_solve"],
                    "time_to_tol_ms": m["ms_per_solve"]},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "traffic_gbs", "traffic_frac",

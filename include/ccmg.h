@@ -48,7 +48,7 @@ enum { CCMG_XLO = 0, CCMG_XHI = 1, CCMG_YLO = 2, CCMG_YHI = 3 };
  *               nu1 = nu2 = 2 a refinement step runs several FP32 V-cycles
  *               from a zero correction: the first step 2, later steps as
  *               many as the contraction measured so far says the tolerance
- *               needs, at most 3 (environment CCMG_MIXED_INNER, 1..8; one
+ *               needs, at most 3 (option CCMG_OPT_MIXED_INNER, 1..8; one
  *               more when that is expected to end the solve); the finest
  *               level's post-smoothing of one inner cycle and pre-smoothing
  *               of the next share one launch. */
@@ -98,25 +98,30 @@ typedef struct ccmg_plan ccmg_plan;
 /* Text for a status code (static storage). */
 const char *ccmg_status_str(int status);
 
-/* Fill *p with the defaults: unit square, all sides Dirichlet, Poisson,
- * V(2,2), 50 bottom relaxations, 100 cycles, rtol 1e-10, FP64. */
+/* Fill *p with the defaults: unit square, all sides Dirichlet, Poisson
+ * (Eq. helmholtz with alpha = 0, beta = -1), V(2,2), 50 bottom relaxations
+ * (Sec. 3.3, "by default"), 100 cycles, rtol 1e-10, FP64. */
 int ccmg_problem_init(ccmg_problem *p, int n);
 
-/* Validate a problem without touching the GPU. */
+/* Validate a problem without touching the GPU: n a power of two (the
+ * hierarchy n, n/2, ..., 2 of Sec. 3.3), square cells, known side types with
+ * periodic sides paired, counts in range. */
 int ccmg_problem_check(const ccmg_problem *p);
 
-/* Bytes of device workspace ccmg_plan_create needs for *p (0 if invalid). */
+/* Bytes of device workspace ccmg_plan_create needs for *p (0 if invalid): the
+ * coarse levels of the hierarchy (Sec. 3.3) and the solve's scalars. */
 size_t ccmg_workspace_bytes(const ccmg_problem *p);
 
-/* Create a plan in a caller-owned device workspace of >= ccmg_workspace_bytes
- * bytes, 256-byte aligned.  The workspace must outlive the plan and must not
+/* Create a plan (the grid hierarchy of Sec. 3.3 laid out in a caller-owned
+ * device workspace of >= ccmg_workspace_bytes bytes, 256-byte aligned).  The workspace must outlive the plan and must not
  * be shared with another live plan.  `stream` is a hipStream_t (or NULL). */
 int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *stream,
                      ccmg_plan **out);
 int ccmg_plan_destroy(ccmg_plan *plan);
 
-/* Solve (alpha - beta Lap) phi = f.  d_f, d_phi: device arrays of the finest
- * level, same pitch.  f's ghosts are ignored.  On entry d_phi holds the
+/* Solve (alpha - beta Lap) phi = f by V-cycles to the plan's tolerance
+ * (Sec. 3.3; stop test as in Sec. 3.3.1).  d_f, d_phi: device arrays of the
+ * finest level, same pitch.  f's ghosts are ignored.  On entry d_phi holds the
  * starting iterate if use_guess != 0 (else it is ignored and zero is used);
  * on return it holds the last iterate with its ghost cells filled.  Blocks
  * until the result is known (the stop test needs it).  Singular problems
@@ -124,14 +129,29 @@ int ccmg_plan_destroy(ccmg_plan *plan);
  * the zero-mean solution.  ||f|| == 0 gives phi = 0 and CCMG_OK.
  * `out` may be NULL.  FP64 plans with nu1 = nu2 = 2 and more than 32 cells
  * per side run the finest level's post-smoothing of one cycle and
- * pre-smoothing of the next in one launch (the same iterates; environment
- * CCMG_FUSED=0 turns this off, CCMG_FUSED_KEEP sets how far above the
- * tolerance the extrapolated residual may be for a cycle's own iterate to be
- * kept, default 100).  CCMG_PAIR=1 (read when a plan is created) makes the
- * pre-smoothing of pairs of levels with 128..512 cells per side one launch
- * of 2-D tiles (same iterates; off by default: not faster on the MI355X). */
+ * pre-smoothing of the next in one launch (the same iterates; see
+ * CCMG_OPT_FUSED). */
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
+
+/* Plan options (all optional; read at every solve).
+ *   CCMG_OPT_FUSED       0 or 1 (default 1): the fused finest launch of FP64
+ *                        V(2,2) solves (0: one launch per half cycle, the
+ *                        same iterates).
+ *   CCMG_OPT_FUSED_KEEP  >= 0 (default 100): a fused launch also writes the
+ *                        iterate after its post-smoothing (the solve's result
+ *                        if that cycle meets the tolerance) while the residual
+ *                        extrapolated from the last two cycles is within this
+ *                        factor of the tolerance; 0 never (the solve then
+ *                        returns the next cycle's pre-smoothed iterate, checked
+ *                        by its own residual).
+ *   CCMG_OPT_MIXED_INNER 1..8 (default 3): most FP32 V-cycles per refinement
+ *                        step of MIXED plans with V(2,2).
+ * ccmg_plan_set_option returns CCMG_EINVAL for an unknown option or a value
+ * outside its range; ccmg_plan_get_option writes the current value. */
+enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3 };
+int ccmg_plan_set_option(ccmg_plan *plan, int option, double value);
+int ccmg_plan_get_option(ccmg_plan *plan, int option, double *value);
 
 /* Bottom of the V-cycle (Sec. 3.3 leaves the coarsest solve open).
  * n_bottom = 2 (the default): nu_bottom red-black relaxations on the 2 x 2
@@ -204,8 +224,10 @@ int ccmg_cn_rhs(ccmg_plan *plan, const double *d_phi, double *d_f, ptrdiff_t pit
  * CCMG_EINVAL also when the plan's alpha is not 1.  Blocks like ccmg_solve. */
 int ccmg_cn_step(ccmg_plan *plan, double *d_phi, double *d_work, ptrdiff_t pitch, ccmg_result *out);
 
-/* Exactly one V-cycle (FP64 plans) or one refinement step (MIXED plans) on
- * the finest level, in place on d_phi, without a stop test.  Asynchronous. */
+/* Exactly one V-cycle (Sec. 3.3: nu1 relaxations, restriction of the
+ * residual, the coarse correction from zero, prolongation, nu2 relaxations)
+ * of FP64 plans, or one refinement step of MIXED plans, on the finest level,
+ * in place on d_phi, without a stop test.  Asynchronous. */
 int ccmg_vcycle(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
 
 /* ---- single steps at one level, for checking each kernel (asynchronous).
@@ -213,18 +235,30 @@ int ccmg_vcycle(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pit
  * the homogeneous version of the plan's side types and the plan's
  * alpha, beta.  Out-of-place: input and output arrays must not overlap. */
 
-/* Fill the ghost cells of d_a (level l) from its valid cells. */
+/* Fill the ghost cells of d_a (level l) from its valid cells with the
+ * homogeneous side rules (Sec. 3.3 ghost equations; periodic sides wrap). */
 int ccmg_fill_ghosts(ccmg_plan *plan, int level, double *d_a, ptrdiff_t pitch);
-/* phi_out = `iters` (1 or 2) red-black Gauss-Seidel iterations applied to phi_in. */
+/* phi_out = `iters` (1 or 2) red-black Gauss-Seidel iterations applied to
+ * phi_in (Sec. 3.3 smoother; the relaxation of Eq. helmholtz solved for the
+ * centre cell, red cells (i + j even) first, ghosts refreshed per colour). */
 int ccmg_smooth(ccmg_plan *plan, int level, int iters, const double *d_f, const double *d_phi_in,
                 double *d_phi_out, ptrdiff_t pitch);
-/* r = f - (alpha phi - beta Lap phi) on valid cells of level l. */
+/* r = f - (alpha phi - beta Lap phi) on valid cells of level l (the residual
+ * of Eq. helmholtz with the 5-point Laplacian, Sec. 2 / Sec. 3.3). */
 int ccmg_residual(ccmg_plan *plan, int level, const double *d_f, const double *d_phi, double *d_r,
                   ptrdiff_t pitch);
-/* d_fc (level l+1) = four-cell average of r = f - A phi (level l). */
+/* d_fc (level l+1) = four-cell average of r = f - A phi (level l): the
+ * residual restricted as a V-cycle does it (Sec. 3.3). */
 int ccmg_restrict_residual(ccmg_plan *plan, int level, const double *d_f, const double *d_phi,
                            ptrdiff_t pitch, double *d_fc, ptrdiff_t pitch_c);
-/* phi_out = phi_in + P e  with e on level l+1 (its ghosts are not read). */
+/* d_coarse (level l+1) = the average of the four cells of d_fine (level l)
+ * that cover each coarse cell (Sec. 3.3, restriction), valid cells only; the
+ * two arrays must not overlap. */
+int ccmg_restrict(ccmg_plan *plan, int level, const double *d_fine, ptrdiff_t pitch, double *d_coarse,
+                  ptrdiff_t pitch_c);
+/* phi_out = phi_in + P e  with e on level l+1 (its ghosts are not read):
+ * the prolongation of Sec. 3.3, centred slopes per coarse cell with the
+ * homogeneous side rules, bilinear without the xy term. */
 int ccmg_prolong_add(ccmg_plan *plan, int level, const double *d_ec, ptrdiff_t pitch_c,
                      const double *d_phi_in, double *d_phi_out, ptrdiff_t pitch);
 
@@ -251,11 +285,17 @@ size_t ccmg_batch_workspace_bytes(int m, const ccmg_problem *probs);
 int ccmg_batch_create(int m, const ccmg_problem *probs, void *d_ws, size_t ws_bytes, void *stream,
                       ccmg_batch **out);
 int ccmg_batch_destroy(ccmg_batch *batch);
-/* Solve all problems; out (m entries, may be NULL) receives each problem's
+/* Solve all problems (each as ccmg_solve would, Sec. 3.3 V-cycles with the
+ * refinement of CCMG_MIXED); out (m entries, may be NULL) receives each problem's
  * result, info (may be NULL) the batch summary.  Returns CCMG_OK if every
  * problem converged, else the first error status, else CCMG_NOT_CONVERGED. */
 int ccmg_batch_solve(ccmg_batch *batch, const double *const *d_f, double *const *d_phi, const ptrdiff_t *pitch,
                      int use_guess, ccmg_result *out, ccmg_batch_info *info);
+/* Batch options.  CCMG_BATCH_OPT_EAGER 0 or 1 (default 0): issue each batch
+ * step's launches directly instead of replaying the captured graphs (the same
+ * launches; for checking the replays).  CCMG_EINVAL for anything else. */
+enum { CCMG_BATCH_OPT_EAGER = 1 };
+int ccmg_batch_set_option(ccmg_batch *batch, int option, double value);
 /* Time the candidate rows-per-band of each level size class and the number of
  * persistent wavefronts over whole batch steps on the given arrays and keep the
  * fastest.  d_phi is used as scratch (overwritten). */
@@ -289,7 +329,8 @@ int ccmg_net_destroy(ccmg_net *net);
 /* Load parameters (device FP32); resets the optimiser state. */
 int ccmg_net_set_params(ccmg_net *net, const float *d_params);
 int ccmg_net_get_params(ccmg_net *net, float *d_params);
-/* y = net(x) for nb samples. */
+/* y = net(x) for nb samples (the network is not in the paper: it only
+ * supplies the starting iterate of a Sec. 3.3 solve). */
 int ccmg_net_forward(ccmg_net *net, const float *d_x, float *d_y, int nb);
 /* Mean squared error of net(x) against t and its gradient with respect to
  * every parameter (device FP32, may be NULL); *loss (host, may be NULL). */
@@ -308,7 +349,7 @@ int ccmg_net_encode(ccmg_net *net, const double *d_a, ptrdiff_t pitch, int n, co
 int ccmg_net_guess(ccmg_net *net, const double *d_f, ptrdiff_t pitch, int n, double length, int coarse_iters,
                    double *d_phi, ptrdiff_t phi_pitch);
 /* Learned solve for the problem the network is trained on (alpha = 0,
- * beta = -1, square domain; any sides): ccmg_net_guess, then ccmg_solve from
+ * beta = -1, square domain, all four sides periodic): ccmg_net_guess, then ccmg_solve from
  * that guess to the plan's tolerance.  A guess whose relative residual is not
  * finite or above 1e6 is discarded and the solve starts from zero instead
  * (*guess_used = 0, may be NULL).  out->ms covers guess and solve,
@@ -371,6 +412,16 @@ int ccmg_plan_profile(ccmg_plan *plan, int enable);
 /* Copy up to `max` kernel records into out; *count receives how many exist.
  * Call after the timed work has completed (e.g. after ccmg_solve returned). */
 int ccmg_plan_kernel_stats(ccmg_plan *plan, ccmg_kernel_stat *out, int max, int *count);
+
+/* Streaming probe (diagnostics): d_c = d_a + d_b over `count` doubles, each
+ * array read or written once -- the access pattern of a launch that reads two
+ * arrays and writes one -- timed with HIP events on `stream` over `reps`
+ * launches after one untimed launch; *ms receives the mean time per launch.
+ * It states what the device's memory system delivers for that pattern, beside
+ * the nameplate bandwidth.  count even, arrays 16-byte aligned and not
+ * overlapping, else CCMG_EINVAL.  Blocks until done. */
+int ccmg_probe_stream(const double *d_a, const double *d_b, double *d_c, size_t count, int reps, void *stream,
+                      float *ms);
 
 #ifdef __cplusplus
 }

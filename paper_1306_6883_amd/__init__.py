@@ -25,6 +25,8 @@ BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC = 0, 1, 2
 FP64, MIXED = 0, 1
 OK, NOT_CONVERGED, EINVAL, ESIZE, EBC, EINCOMPAT, ENONFINITE, EHIP, EWORKSPACE = 0, 1, -1, -2, -3, -4, -5, -6, -7
 HISTORY = 128
+OPT_FUSED, OPT_FUSED_KEEP, OPT_MIXED_INNER = 1, 2, 3
+BATCH_OPT_EAGER = 1
 _BC = {"D": BC_DIRICHLET, "N": BC_NEUMANN, "P": BC_PERIODIC,
        BC_DIRICHLET: BC_DIRICHLET, BC_NEUMANN: BC_NEUMANN, BC_PERIODIC: BC_PERIODIC}
 
@@ -86,6 +88,7 @@ def lib():
         L.ccmg_smooth.argtypes = [vp, i, i, dp, dp, dp, pd]
         L.ccmg_residual.argtypes = [vp, i, dp, dp, dp, pd]
         L.ccmg_restrict_residual.argtypes = [vp, i, dp, dp, pd, dp, pd]
+        L.ccmg_restrict.argtypes = [vp, i, dp, pd, dp, pd]
         L.ccmg_prolong_add.argtypes = [vp, i, dp, pd, dp, dp, pd]
         L.ccmg_plan_profile.argtypes = [vp, i]
         PP = ctypes.POINTER(ctypes.c_void_p)
@@ -126,6 +129,10 @@ def lib():
         L.ccmg_net_encode.argtypes = [vp, dp, pd, i, dp, pd, vp]
         L.ccmg_net_guess.argtypes = [vp, dp, pd, i, ctypes.c_double, i, dp, pd]
         L.ccmg_solve_learned.argtypes = [vp, vp, dp, dp, pd, i, ctypes.POINTER(ccmg_result), ip]
+        L.ccmg_probe_stream.argtypes = [dp, dp, dp, sz, i, vp, fp]
+        L.ccmg_plan_set_option.argtypes = [vp, i, ctypes.c_double]
+        L.ccmg_plan_get_option.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
+        L.ccmg_batch_set_option.argtypes = [vp, i, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -244,6 +251,16 @@ class Plan:
 
     def level_n(self, level: int) -> int:
         return self.prob.n >> level
+
+
+def ccmg_plan_set_option(plan: Plan, option: int, value: float) -> None:
+    _check(lib().ccmg_plan_set_option(plan.handle, option, float(value)), "ccmg_plan_set_option")
+
+
+def ccmg_plan_get_option(plan: Plan, option: int) -> float:
+    v = ctypes.c_double()
+    _check(lib().ccmg_plan_get_option(plan.handle, option, ctypes.byref(v)), "ccmg_plan_get_option")
+    return v.value
 
 
 def ccmg_solve(plan: Plan, f: torch.Tensor, phi: torch.Tensor, use_guess: bool = False) -> Result:
@@ -383,6 +400,13 @@ def ccmg_restrict_residual(plan: Plan, level: int, f, phi, fc) -> None:
     _check(lib().ccmg_restrict_residual(plan.handle, level, fp, pp, pitch, cp, pc), "ccmg_restrict_residual")
 
 
+def ccmg_restrict(plan: Plan, level: int, fine, coarse) -> None:
+    n = plan.level_n(level)
+    fp, pitch = _field_args(fine, n)
+    cp, pc = _field_args(coarse, n // 2)
+    _check(lib().ccmg_restrict(plan.handle, level, fp, pitch, cp, pc), "ccmg_restrict")
+
+
 def ccmg_prolong_add(plan: Plan, level: int, ec, phi_in, phi_out) -> None:
     n = plan.level_n(level)
     ep, pc = _field_args(ec, n // 2)
@@ -442,6 +466,20 @@ def ccmg_plan_kernel_stats(plan: Plan) -> list:
             for k in range(cnt.value)]
 
 
+def ccmg_probe_stream(a, b, c, reps: int = 20) -> float:
+    """c = a + b over the elements of three float64 CUDA tensors of equal size
+    (the library's streaming probe); returns the mean ms per launch."""
+    for t in (a, b, c):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("ccmg_probe_stream: contiguous float64 CUDA tensors")
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("ccmg_probe_stream: tensors of one size")
+    ms = ctypes.c_float()
+    _check(lib().ccmg_probe_stream(a.data_ptr(), b.data_ptr(), c.data_ptr(), a.numel(), reps, _stream_handle(),
+                                   ctypes.byref(ms)), "ccmg_probe_stream")
+    return ms.value
+
+
 class Batch:
     """A ccmg batch of independent problems with its own workspace tensor."""
 
@@ -497,6 +535,10 @@ def ccmg_batch_solve(batch: Batch, fs, phis, use_guess: bool = False):
         hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
         out.append(Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles))
     return out, dict(status=st, steps=info.steps, converged=info.converged, ms=info.ms)
+
+
+def ccmg_batch_set_option(batch: Batch, option: int, value: float) -> None:
+    _check(lib().ccmg_batch_set_option(batch.handle, option, float(value)), "ccmg_batch_set_option")
 
 
 def ccmg_batch_autotune(batch: Batch, fs, phis) -> None:

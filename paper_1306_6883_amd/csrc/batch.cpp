@@ -141,6 +141,7 @@ struct ccmg_batch {
     std::vector<double *> cphi;
     std::vector<long> cpitch;
     int c_guess = -1;
+    bool opt_eager = false;                    // CCMG_BATCH_OPT_EAGER
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -647,6 +648,15 @@ int ccmg_batch_create(int m, const ccmg_problem *probs, void *d_ws, size_t ws_by
     return CCMG_OK;
 }
 
+int ccmg_batch_set_option(ccmg_batch *B, int option, double value) {
+    if (!B) return CCMG_EINVAL;
+    if (option == CCMG_BATCH_OPT_EAGER && (value == 0.0 || value == 1.0)) {
+        B->opt_eager = value != 0.0;
+        return CCMG_OK;
+    }
+    return CCMG_EINVAL;
+}
+
 int ccmg_batch_destroy(ccmg_batch *B) {
     if (!B) return CCMG_EINVAL;
     if (B->stream) hipStreamSynchronize(B->stream);
@@ -694,10 +704,9 @@ int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_p
         return true;
     };
     int steps = 0;
-    // CCMG_BATCH_EAGER=1 issues each step's launches directly instead of
+    // CCMG_BATCH_OPT_EAGER issues each step's launches directly instead of
     // replaying the captured graphs (same launches; used to check the replays)
-    const char *eg = getenv("CCMG_BATCH_EAGER");
-    const bool eager = eg && eg[0] == '1';
+    const bool eager = B->opt_eager;
     auto run_step = [&](int k) -> hipError_t {
         return eager ? record_step(B, k & 1) : hipGraphLaunch(B->graph[k & 1], B->stream);
     };
@@ -741,6 +750,7 @@ int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_p
         q.n = B->prob[i].n;
         for (int s = 0; s < 4; ++s) q.bc[s] = B->prob[i].bc[s];
         q.shift = singular_of(B->prob[i]) ? B->at<double>(B->off_scal) + (size_t)kScal * i + S_PHIMEAN : nullptr;
+        q.zero = scal[(size_t)kScal * i + S_F2] == 0.0 ? 1 : 0;
         nmax = std::max(nmax, q.n);
     }
     e = hipMemcpyAsync(B->ws + B->off_fin, fin.data(), sizeof(BatchFinish) * m, hipMemcpyHostToDevice, B->stream);
@@ -774,6 +784,11 @@ int ccmg_batch_solve(ccmg_batch *B, const double *const *d_f, double *const *d_p
             R.rel_resid0 = R.history[0];
             R.rel_resid = rho;
             R.ms = ms;
+            if (sc[S_F2] == 0.0) {  // phi = 0 solves it exactly, as ccmg_solve reports
+                R.cycles = R.inner_cycles = 0;
+                R.rel_resid0 = R.rel_resid = 0.0;
+                for (int k = 0; k < CCMG_HISTORY; ++k) R.history[k] = 0.0;
+            }
         }
     }
     if (info) {

@@ -31,6 +31,7 @@ struct BatchFinish {
     int n;
     int bc[4];
     const double *shift;  // mean removed from singular problems (or null)
+    int zero;             // f == 0: the returned field is 0 (valid and ghost cells)
 };
 
 hipError_t launch_batch_fstats(const BatchProb *probs, int m, int blocks, hipStream_t s);

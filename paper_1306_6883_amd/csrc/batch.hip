@@ -102,14 +102,19 @@ __global__ __launch_bounds__(kRed) void k_batch_cycle_end(const BatchProb *__res
 
 // grid (rows, m): the returned field.  Valid cells: copy from where the last
 // step left the iterate (if that is not the caller's array) and remove the
-// mean of singular problems.
+// mean of singular problems; zeros for a zero right-hand side (whatever the
+// guess was), as a single solve returns.
 __global__ __launch_bounds__(kRed) void k_batch_finish_valid(const BatchFinish *__restrict__ fin) {
     const BatchFinish &q = fin[blockIdx.y];
     const double m = q.shift ? *q.shift : 0.0;
     for (int y = blockIdx.x; y < q.n; y += gridDim.x) {
         const double *src = q.src + (long)(y + 1) * q.psrc + 1;
         double *dst = q.dst + (long)(y + 1) * q.pdst + 1;
-        for (int x = threadIdx.x; x < q.n; x += kRed) dst[x] = src[x] - m;
+        if (q.zero) {
+            for (int x = threadIdx.x; x < q.n; x += kRed) dst[x] = 0.0;
+        } else {
+            for (int x = threadIdx.x; x < q.n; x += kRed) dst[x] = src[x] - m;
+        }
     }
 }
 

@@ -18,11 +18,12 @@ namespace ccmg {
 
 namespace {
 
-// Workgroup size NT (a template parameter, 64 .. 512): 512 gives one thread per
-// cell of a colour on the 32 x 32 level.  With NT = 64 (one wavefront) no
-// workgroup barrier is needed -- a wave's LDS operations complete in issue
-// order, so ordering the compiler's code is enough between phases.
-constexpr int kDefaultCoarseThreads = 512;
+// Workgroup size NT (a template parameter): 512 gives one thread per cell of a
+// colour on the 32 x 32 level (64, 128 and 256 measured slower).  With NT = 64
+// (one wavefront) no workgroup barrier would be needed -- a wave's LDS
+// operations complete in issue order, so ordering the compiler's code is
+// enough between phases.
+constexpr int kCoarseThreads = 512;
 
 template <int NT>
 __device__ __forceinline__ void sync() {
@@ -368,17 +369,6 @@ hipError_t launch_bottom_inverse(int nb, const int bc[4], double alpha, double b
     return hipGetLastError();
 }
 
-// Workgroup size of the tail: CCMG_COARSE_THREADS (64, 128, 256 or 512) if
-// set, else the default.
-int coarse_threads() {
-    static int nt = [] {
-        const char *e = std::getenv("CCMG_COARSE_THREADS");
-        const int v = e ? std::atoi(e) : 0;
-        return (v == 64 || v == 128 || v == 256 || v == 512) ? v : kDefaultCoarseThreads;
-    }();
-    return nt;
-}
-
 template <typename T>
 void coarse_fill_consts(CoarseArgs<T> &a) {
     for (int l = 0; (a.n_top >> l) >= 2 && l < 8; ++l) {
@@ -398,33 +388,16 @@ hipError_t launch_coarse(const CoarseArgs<T> &a0, hipStream_t s) {
     const bool direct = a.n_bottom >= 4;
     if (direct && (a.n_bottom > kDirectMax || a.n_bottom > a.n_top || (a.n_bottom & (a.n_bottom - 1)) || !a.ainv))
         return hipErrorInvalidValue;
-    if (direct) {
-        switch (coarse_threads()) {
-            case 64: hipLaunchKernelGGL((k_coarse<64, T, true>), dim3(1), dim3(64), 0, s, a); break;
-            case 128: hipLaunchKernelGGL((k_coarse<128, T, true>), dim3(1), dim3(128), 0, s, a); break;
-            case 256: hipLaunchKernelGGL((k_coarse<256, T, true>), dim3(1), dim3(256), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_coarse<512, T, true>), dim3(1), dim3(512), 0, s, a); break;
-        }
-        return hipGetLastError();
-    }
-    switch (coarse_threads()) {
-        case 64: hipLaunchKernelGGL((k_coarse<64, T, false>), dim3(1), dim3(64), 0, s, a); break;
-        case 128: hipLaunchKernelGGL((k_coarse<128, T, false>), dim3(1), dim3(128), 0, s, a); break;
-        case 256: hipLaunchKernelGGL((k_coarse<256, T, false>), dim3(1), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_coarse<512, T, false>), dim3(1), dim3(512), 0, s, a); break;
-    }
+    constexpr int NT = kCoarseThreads;
+    if (direct) hipLaunchKernelGGL((k_coarse<NT, T, true>), dim3(1), dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_coarse<NT, T, false>), dim3(1), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_coarse_list(const CoarseArgs<T> *list, int count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    switch (coarse_threads()) {
-        case 64: hipLaunchKernelGGL((k_coarse_list<64, T>), dim3(count), dim3(64), 0, s, list); break;
-        case 128: hipLaunchKernelGGL((k_coarse_list<128, T>), dim3(count), dim3(128), 0, s, list); break;
-        case 256: hipLaunchKernelGGL((k_coarse_list<256, T>), dim3(count), dim3(256), 0, s, list); break;
-        default: hipLaunchKernelGGL((k_coarse_list<512, T>), dim3(count), dim3(512), 0, s, list); break;
-    }
+    hipLaunchKernelGGL((k_coarse_list<kCoarseThreads, T>), dim3(count), dim3(kCoarseThreads), 0, s, list);
     return hipGetLastError();
 }
 

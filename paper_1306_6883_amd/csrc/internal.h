@@ -96,14 +96,6 @@ template <typename T>
 hipError_t launch_tile(const MarchArgs<T> &a, int nu, bool load_phi, bool prolong, int post, hipStream_t s,
                        int *ntiles_out);
 
-// Pre-smoothing (from zero) of levels l and l+1 in one launch of 2-D tiles
-// (tile.hip): a for level l (f, phi_out, aux = level l+1 rhs, partial), b for
-// level l+1 (phi_out, aux = level l+2 rhs, partial).  Level l has >= 128
-// cells per side.  *nblocks receives the number of partial sums written to
-// each of a.partial and b.partial.
-template <typename T>
-hipError_t launch_pair_down(const MarchArgs<T> &a, const MarchArgs<T> &b, int nu, hipStream_t s, int *nblocks);
-
 // Host launchers (march.hip).  nu in {0,1,2}; load_phi=false means phi starts at 0.
 // *ntiles_out receives the number of tiles (= partial-sum slots) of the launch.
 template <typename T>
@@ -198,6 +190,10 @@ hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, in
                          hipStream_t s);
 hipError_t launch_set(double *p, int count, double v, hipStream_t s);
 hipError_t launch_set_int(int *p, int count, int v, hipStream_t s);
+// coarse = four-cell average of fine (valid cells; nc cells per side of the coarse level).
+hipError_t launch_restrict(const double *fine, long pf, double *coarse, long pc, int nc, hipStream_t s);
+// c = a + b over `count` doubles (even count, 16-byte aligned): a streaming probe.
+hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, hipStream_t s);
 
 // The stream and finest size of a plan (for entry points outside plan.cpp).
 hipStream_t plan_stream(const ccmg_plan *P);

@@ -326,8 +326,12 @@ int ccmg_solve_learned(ccmg_plan *P, ccmg_net *N, const double *d_f, double *d_p
     const int n = plan_n(P);
     const ccmg_problem *pr = plan_problem(P);
     const double lx = pr->xmax - pr->xmin, ly = pr->ymax - pr->ymin;
+    // the network is trained on doubly periodic Poisson problems (circular
+    // padding, periodic decoder): nothing else is accepted
+    bool periodic = true;
+    for (int q = 0; q < 4; ++q) periodic = periodic && pr->bc[q] == CCMG_BC_PERIODIC;
     if (plan_stream(P) != N->stream || n < 2 * kNetG || n > N->nmax || pr->alpha != 0.0 || pr->beta != -1.0 ||
-        std::fabs(lx - ly) > 1e-12 * lx)
+        std::fabs(lx - ly) > 1e-12 * lx || !periodic)
         return R->status = CCMG_EINVAL;
     hipError_t e = hipEventRecord(N->ev0, N->stream);
     int st = e == hipSuccess ? ccmg_net_guess(N, d_f, pitch, n, lx, coarse_iters, d_phi, pitch) : CCMG_EHIP;

@@ -19,6 +19,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -112,9 +113,9 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
             v.a = take(bytes);
             v.b = take(bytes);
             v.f = take(bytes);
-            // partial sums from the launch on the level above, or from a
-            // two-level launch two levels above ((4n / 32)^2 blocks)
-            v.fpart_cap = std::max(max_tiles(v.n * 2), (v.n / 8) * (v.n / 8));
+            // partial sums from the launch on the level above: row-march tiles
+            // or 32 x 32 blocks of the 2-D tile kernel ((2n / 32)^2)
+            v.fpart_cap = std::max(max_tiles(v.n * 2), (v.n / 16) * (v.n / 16));
             v.fpart = take(sizeof(double) * v.fpart_cap);
         }
     }
@@ -135,18 +136,10 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
 // levels keep the redundant halo rows (2 x 6 per band) small; small levels
 // need short bands so that enough wavefronts run and each finishes quickly.
 MarchShape shape_for(int n) {
-    static int env_ty = -1, env_wpb = -1;
-    if (env_ty < 0) {
-        const char *e = getenv("CCMG_TY");
-        env_ty = e ? atoi(e) : 0;
-        const char *w = getenv("CCMG_WPB");
-        env_wpb = w ? atoi(w) : 0;
-    }
     MarchShape s;
-    s.wpb = env_wpb > 0 ? env_wpb : 1;
+    s.wpb = 1;
     int ty;
-    if (env_ty >= kMinTy && (env_ty & 1) == 0) ty = env_ty;
-    else if (n >= 4096) ty = 64;
+    if (n >= 4096) ty = 64;
     else if (n >= 2048) ty = 32;
     else if (n >= 512) ty = 16;
     else ty = 8;
@@ -179,7 +172,11 @@ struct ccmg_plan {
     MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
-    bool pair_down[kMaxLevels] = {};  // levels l, l+1 pre-smoothed in one launch (2-D tiles)
+    // options (ccmg_plan_set_option)
+    bool opt_fused = true;       // fused finest launch of FP64 V(2,2) solves
+    double opt_fused_keep = 100.0;  // keep a cycle's own iterate while the extrapolated residual is
+                                    // within this factor of the tolerance
+    int opt_mixed_inner = 3;     // most FP32 cycles per refinement step
     int n_bottom = 2;  // 4 or 8: exact solve on that level (ccmg_plan_set_bottom)
     int tcycle = 0;    // cycle being enqueued by the solve loop (tags timed launches)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
@@ -234,51 +231,21 @@ int ccmg::plan_n(const ccmg_plan *P) { return P->lay.lev[0].n; }
 const ccmg_problem *ccmg::plan_problem(const ccmg_plan *P) { return &P->p; }
 
 namespace {
-// Tuning knobs, read at every solve: CCMG_FUSED=0 turns the fused launches
-// off; CCMG_FUSED_KEEP (default 100) is how far above the tolerance the
-// extrapolated residual of a cycle may be for its post-smoothed iterate to be
-// kept.
+// The fused finest launch applies to FP64 plans with V(2,2) and levels below
+// the finest (option CCMG_OPT_FUSED turns it off).
 bool fused_eligible(const ccmg_plan *P) {
-    const char *e = std::getenv("CCMG_FUSED");
-    const bool off = e && e[0] == '0';
-    return !off && P->p.prec == CCMG_FP64 && P->lay.lt >= 1 && P->p.nu1 == 2 && P->p.nu2 == 2;
+    return P->opt_fused && P->p.prec == CCMG_FP64 && P->lay.lt >= 1 && P->p.nu1 == 2 && P->p.nu2 == 2;
 }
 // Mixed-precision steps with several FP32 V-cycles per FP64 refinement: the
-// most inner cycles per step (CCMG_MIXED_INNER, default 3; 1 = one cycle per
-// step; one more is allowed when it is expected to end the solve).  More
+// most inner cycles per step (CCMG_OPT_MIXED_INNER, default 3; 1 = one cycle
+// per step; one more is allowed when it is expected to end the solve).  More
 // cycles per step do not pay on ill-conditioned problems: the FP32 residual
 // of a smooth correction loses about log10(kappa) of its 7 digits, so a step
 // cannot reduce the FP64 residual by much more than about 1e-4 there (seen on
 // 4096^2 Poisson).  Needs the same cycle shape as the fused FP64 launch.
 int mixed_inner_max(const ccmg_plan *P) {
     if (P->p.prec != CCMG_MIXED || P->lay.lt < 1 || P->p.nu1 != 2 || P->p.nu2 != 2) return 1;
-    const char *e = std::getenv("CCMG_MIXED_INNER");
-    const int v = e ? std::atoi(e) : 3;
-    return v < 1 ? 1 : (v > 8 ? 8 : v);
-}
-// Pairs of levels whose pre-smoothing runs in one launch: from the first level
-// below the finest with at most kPairMaxN cells per side, (l, l+1), (l+2, l+3),
-// ... while level l has at least 128 cells per side and l+1 is not in the
-// one-workgroup tail.  Off unless the environment sets CCMG_PAIR=1 (read per
-// plan): on the MI355X the pair launch (17-19 us) takes as long as the two
-// launches it replaces, its longer chain of LDS sweeps and barriers eating
-// the saved launch.
-constexpr int kPairMaxN = 512;
-void choose_pairs(ccmg_plan *P) {
-    for (int l = 0; l < kMaxLevels; ++l) P->pair_down[l] = false;
-    const char *e = std::getenv("CCMG_PAIR");
-    if (!e || e[0] != '1') return;
-    const Layout &lay = P->lay;
-    int l = 1;
-    while (l < lay.lt && lay.lev[l].n > kPairMaxN) ++l;
-    for (; l + 1 < lay.lt && l + 1 < kMaxLevels; l += 2)
-        if (lay.lev[l].n >= 128) P->pair_down[l] = true;
-}
-double fused_keep_factor() {
-    const char *e = std::getenv("CCMG_FUSED_KEEP");
-    if (!e) return 100.0;
-    const double v = std::atof(e);
-    return v >= 0.0 ? v : 100.0;
+    return P->opt_mixed_inner;
 }
 
 }  // namespace
@@ -427,37 +394,6 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     if (io.coarse_only) fpart_count[1] = io.f1_count;
     for (int l = io.coarse_only ? 1 : 0; l < lay.lt; ++l) {
         setup_bufs(l);
-        if (l >= 1 && l + 1 < lay.lt && P->pair_down[l] && (P->p.nu1 == 1 || P->p.nu1 == 2)) {
-            // levels l and l+1 pre-smoothed (from zero) in one launch
-            setup_bufs(l + 1);
-            MarchArgs<T> a{}, b{};
-            level_consts(P, l, a);
-            level_consts(P, l + 1, b);
-            const Buf<T> fb = fptr(l);
-            a.f = fb.p;
-            a.pf = fb.pitch;
-            fmean(l, a);
-            a.phi_out = other[l].p;
-            a.pout = other[l].pitch;
-            a.aux = P->at<T>(lay.lev[l + 1].f);
-            a.paux = lay.lev[l + 1].pitch;
-            a.partial = P->at<double>(lay.lev[l + 1].fpart);
-            a.skip = io.skip;
-            b.phi_out = other[l + 1].p;
-            b.pout = other[l + 1].pitch;
-            b.aux = P->at<T>(lay.lev[l + 2].f);
-            b.paux = lay.lev[l + 2].pitch;
-            b.partial = P->at<double>(lay.lev[l + 2].fpart);
-            int nb = 0;
-            e = launch_pair_down<T>(a, b, P->p.nu1, s, &nb);
-            if (e != hipSuccess) return e;
-            fpart_count[l + 1] = nb;
-            fpart_count[l + 2] = nb;
-            std::swap(cur[l], other[l]);
-            std::swap(cur[l + 1], other[l + 1]);
-            ++l;
-            continue;
-        }
         const MarchShape sh = P->shp_pre[l];
         const std::vector<int> chain = split_nu(P->p.nu1);
         bool zero = (l > 0) || io.zero;
@@ -911,7 +847,6 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     }
     P->shp_fused = shape_for(P->lay.lev[0].n);
     P->shp_fused32 = shape_for(P->lay.lev[0].n);
-    choose_pairs(P);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
     if (e == hipSuccess)
@@ -1169,6 +1104,35 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     return CCMG_OK;
 }
 
+int ccmg_plan_set_option(ccmg_plan *P, int option, double value) {
+    if (!P || !std::isfinite(value)) return CCMG_EINVAL;
+    switch (option) {
+        case CCMG_OPT_FUSED:
+            if (value != 0.0 && value != 1.0) return CCMG_EINVAL;
+            P->opt_fused = value != 0.0;
+            return CCMG_OK;
+        case CCMG_OPT_FUSED_KEEP:
+            if (value < 0.0) return CCMG_EINVAL;
+            P->opt_fused_keep = value;
+            return CCMG_OK;
+        case CCMG_OPT_MIXED_INNER:
+            if (value != std::floor(value) || value < 1.0 || value > 8.0) return CCMG_EINVAL;
+            P->opt_mixed_inner = (int)value;
+            return CCMG_OK;
+        default: return CCMG_EINVAL;
+    }
+}
+
+int ccmg_plan_get_option(ccmg_plan *P, int option, double *value) {
+    if (!P || !value) return CCMG_EINVAL;
+    switch (option) {
+        case CCMG_OPT_FUSED: *value = P->opt_fused ? 1.0 : 0.0; return CCMG_OK;
+        case CCMG_OPT_FUSED_KEEP: *value = P->opt_fused_keep; return CCMG_OK;
+        case CCMG_OPT_MIXED_INNER: *value = (double)P->opt_mixed_inner; return CCMG_OK;
+        default: return CCMG_EINVAL;
+    }
+}
+
 int ccmg_plan_set_bottom(ccmg_plan *P, int n_bottom) {
     if (!P) return CCMG_EINVAL;
     if (n_bottom == 2) {
@@ -1338,6 +1302,31 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
         out[k].ms = P->timer.ms[k];
         out[k].bytes = P->timer.tbytes[k];
     }
+    return CCMG_OK;
+}
+
+int ccmg_probe_stream(const double *d_a, const double *d_b, double *d_c, size_t count, int reps, void *stream,
+                      float *ms) {
+    if (!d_a || !d_b || !d_c || !ms || reps < 1 || count == 0 || (count & 1) ||
+        ((reinterpret_cast<uintptr_t>(d_a) | reinterpret_cast<uintptr_t>(d_b) | reinterpret_cast<uintptr_t>(d_c)) & 15))
+        return CCMG_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int blocks = 8 * cus;  // eight 256-thread workgroups per compute unit
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CCMG_EHIP;
+    hipError_t e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return CCMG_EHIP;
+    *ms = t / (float)reps;
     return CCMG_OK;
 }
 
@@ -1592,7 +1581,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     std::vector<int> inner_used(P->p.max_cycles + 2, 1);  // ... and its FP32 V-cycles
     // FP64 with fused finest launches: the driver's state after each cycle
     const bool fused = !mixed && fused_eligible(P);
-    const double keep = fused_keep_factor();
+    const double keep = P->opt_fused_keep;
     FusedCtx fx{Buf<double>{d_phi, pitch}, false, !use_guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
@@ -1852,6 +1841,21 @@ int ccmg_restrict_residual(ccmg_plan *P, int level, const double *d_f, const dou
     int nt;
     return hip_status(
         launch_march<double>(a, 0, true, false, POST_RESTRICT, shape_for(a.n), P->stream, &nt));
+}
+
+int ccmg_restrict(ccmg_plan *P, int level, const double *d_fine, ptrdiff_t pitch, double *d_coarse,
+                  ptrdiff_t pitch_c) {
+    if (!P || !d_fine || !d_coarse) return CCMG_EINVAL;
+    if (check_pitch(P, level, pitch) != CCMG_OK || check_pitch(P, level + 1, pitch_c) != CCMG_OK)
+        return CCMG_EINVAL;
+    const int nc = P->lay.lev[level + 1].n;
+    // the coarse array must not overlap the fine one
+    const char *f0 = reinterpret_cast<const char *>(d_fine);
+    const char *f1 = f0 + sizeof(double) * (size_t)(P->lay.lev[level].n + 2) * (size_t)pitch;
+    const char *c0 = reinterpret_cast<const char *>(d_coarse);
+    const char *c1 = c0 + sizeof(double) * (size_t)(nc + 2) * (size_t)pitch_c;
+    if (c0 < f1 && f0 < c1) return CCMG_EINVAL;
+    return hip_status(launch_restrict(d_fine, pitch, d_coarse, pitch_c, nc, P->stream));
 }
 
 int ccmg_prolong_add(ccmg_plan *P, int level, const double *d_ec, ptrdiff_t pitch_c, const double *d_phi_in,

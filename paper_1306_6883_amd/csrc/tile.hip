@@ -224,248 +224,6 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const MarchArgs<T> a) {
     }
 }
 
-// ---- two levels' pre-smoothing in one launch ---------------------------------
-// On the way down, the pre-smoothing of level l (from zero), its residual's
-// four-cell averages (level l+1's right-hand side), the pre-smoothing of
-// level l+1 (from zero) and its residual's averages (level l+2's right-hand
-// side) need no global step between them except the removal of the level l+1
-// right-hand side's mean, which for a compatible singular problem is zero up
-// to rounding (the residual of a consistent problem sums to zero and the
-// averages keep sums).  So one workgroup can do both levels for a 32 x 32
-// block of level l and the 16 x 16 block of level l+1 under it, with halos
-// wide enough for every sweep: 2 nu + 1 coarse cells around the coarse block
-// (its sweeps and residual), and around the fine block twice that plus
-// 2 nu + 1 fine cells (the fine residual and sweeps).  Per cell the arithmetic
-// is the row march's, in the same order.
-template <typename T>
-struct Lvl {
-    int n, nm;
-    bool px, py;
-    T sxl, sxh, syl, syh;
-    T cc, invd, alpha, beta, ih2;
-};
-
-template <typename T>
-__device__ __forceinline__ Lvl<T> level_of(const MarchArgs<T> &a) {
-    Lvl<T> L;
-    L.n = a.n;
-    L.nm = a.n - 1;
-    L.px = a.bc[CCMG_XLO] == CCMG_BC_PERIODIC;
-    L.py = a.bc[CCMG_YLO] == CCMG_BC_PERIODIC;
-    L.sxl = a.bc[CCMG_XLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
-    L.sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
-    L.syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
-    L.syh = a.bc[CCMG_YHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
-    L.cc = a.cc;
-    L.invd = a.invd;
-    L.alpha = a.alpha;
-    L.beta = a.beta;
-    L.ih2 = a.ih2;
-    return L;
-}
-
-// global index of region index l (region origin o, may be negative); -1
-// outside a non-periodic domain
-__device__ __forceinline__ int wrap(int o, int l, bool per, int nm) {
-    const int g = o + l;
-    if (per) return g & nm;
-    return (g < 0 || g > nm) ? -1 : g;
-}
-
-// 2 nu colour sweeps from zero on an R x R region (row stride R + 1) whose
-// origin is (ox, oy): sweep p updates its colour in [p + 1, R - p - 1).  The
-// region origin has the parity of the block origin minus an odd or even halo;
-// colours are taken from global indices.
-template <typename T, int R, int SWEEPS>
-__device__ void relax_region(T *u, const T *fv, const Lvl<T> &L, int ox, int oy) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int p = 0; p < SWEEPS; ++p) {  // unrolled: the row length below is a constant
-        const int c = p & 1;
-        const int lo = p + 1, wr = R - 2 * p - 2, half = wr >> 1;
-        for (int k = tid; k < wr * half; k += kTileThreads) {
-            const int row = k / half, pos = k - row * half;
-            const int lj = lo + row;
-            // the cell of colour c among (lo + 2 pos, lo + 2 pos + 1) in this row
-            const int li = lo + 2 * pos + ((ox + lo + oy + lj + c) & 1);
-            const int gx = wrap(ox, li, L.px, L.nm), gy = wrap(oy, lj, L.py, L.nm);
-            if (gx < 0 || gy < 0) continue;
-            const int o = lj * (R + 1) + li;
-            const T self = u[o];
-            T e = u[o + 1], w = u[o - 1], nn = u[o + R + 1], ss = u[o - R - 1];
-            if (!L.px) {
-                if (gx == 0) w = L.sxl * self;
-                if (gx == L.nm) e = L.sxh * self;
-            }
-            if (!L.py) {
-                if (gy == L.nm) nn = L.syh * self;
-                if (gy == 0) ss = L.syl * self;
-            }
-            u[o] = (fv[o] + L.cc * (((e + w) + nn) + ss)) * L.invd;
-        }
-        __syncthreads();
-    }
-}
-
-// residual at region cell (li, lj) whose global indices (gx, gy) are inside the domain
-template <typename T, int R>
-__device__ __forceinline__ T resid_region(const T *u, const T *fv, const Lvl<T> &L, int li, int lj, int gx, int gy) {
-    const int o = lj * (R + 1) + li;
-    const T p = u[o];
-    T e = u[o + 1], w = u[o - 1], nn = u[o + R + 1], ss = u[o - R - 1];
-    if (!L.px) {
-        if (gx == 0) w = L.sxl * p;
-        if (gx == L.nm) e = L.sxh * p;
-    }
-    if (!L.py) {
-        if (gy == L.nm) nn = L.syh * p;
-        if (gy == 0) ss = L.syl * p;
-    }
-    const T lap = ((((e - p) + (w - p)) + (nn - p)) + (ss - p)) * L.ih2;
-    return fv[o] - (L.alpha * p - L.beta * lap);
-}
-
-template <typename T, int NU>
-__global__ __launch_bounds__(kTileThreads) void k_pair_down(const MarchArgs<T> a, const MarchArgs<T> b) {
-    constexpr int TC = TS / 2;           // coarse block side
-    constexpr int HC = 2 * NU + 1;       // coarse halo: sweeps + residual
-    constexpr int RC = TC + 2 * HC;      // coarse region side
-    constexpr int OF = 2 * NU + 1;       // fine region index of coarse region cell 0's first child
-    constexpr int HF = 2 * HC + OF;      // fine halo
-    constexpr int RF = TS + 2 * HF;      // fine region side
-    constexpr int NF = RF * (RF + 1), NC = RC * (RC + 1);
-    static_assert(2 * NC <= 2 * NF, "coarse arrays reuse the fine ones");
-    // fine u, f; the coarse u, f reuse the same memory once the fine level is done
-    __shared__ T sm[2 * NF];
-    __shared__ double red[4];
-    if (a.skip && *a.skip) return;  // uniform over the workgroup
-    T *u = sm, *fv = sm + NF;
-    T *uc = sm, *fc = sm + NC;
-
-    const Lvl<T> F = level_of(a), C = level_of(b);
-    const int tid = threadIdx.x;
-    const int tpr = F.n / TS, nb = tpr * tpr;
-    int bi = blockIdx.x;
-    if (nb >= 8 && (nb & 7) == 0) bi = (bi & 7) * (nb >> 3) + (bi >> 3);
-    const int X0 = (bi % tpr) * TS, Y0 = (bi / tpr) * TS;
-    const int ox = X0 - HF, oy = Y0 - HF;                 // fine region origin
-    const int cx = (X0 >> 1) - HC, cy = (Y0 >> 1) - HC;   // coarse region origin
-
-    // 1. f of level l (minus its mean shift) on the fine region; u = 0
-    constexpr int NL = (RF * RF + kTileThreads - 1) / kTileThreads;
-    T fr[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        const int k = tid + q * kTileThreads;
-        fr[q] = T(0);
-        if (k < RF * RF) {
-            const int lj = k / RF, li = k - lj * RF;
-            const int gx = wrap(ox, li, F.px, F.nm), gy = wrap(oy, lj, F.py, F.nm);
-            if (gx >= 0 && gy >= 0) fr[q] = a.f[(long)(gy + 1) * a.pf + 1 + gx];
-        }
-    }
-    T fsub = T(0);
-    if (a.fmean_part) {
-        const int cnt = a.fmean_count_ptr ? *a.fmean_count_ptr : a.fmean_count;
-        double s = 0.0;
-        for (int i = tid & 63; i < cnt; i += 16 * 64) {
-            double v[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = i + 64 * k < cnt ? a.fmean_part[i + 64 * k] : 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (i + 64 * k < cnt) s += v[k];
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        fsub = T(s / ((double)F.n * (double)F.n));
-    }
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-        const int k = tid + q * kTileThreads;
-        if (k < RF * RF) {
-            const int lj = k / RF, li = k - lj * RF;
-            T fval = fr[q];
-            if (a.fmean_part && wrap(ox, li, F.px, F.nm) >= 0 && wrap(oy, lj, F.py, F.nm) >= 0) fval -= fsub;
-            fv[lj * (RF + 1) + li] = fval;
-            u[lj * (RF + 1) + li] = T(0);
-        }
-    }
-    __syncthreads();
-
-    // 2. level l: 2 nu sweeps, then its block out
-    relax_region<T, RF, 2 * NU>(u, fv, F, ox, oy);
-    for (int k = tid; k < TS * TS; k += kTileThreads) {
-        const int j = k / TS, i = k - j * TS;
-        a.phi_out[(long)(Y0 + j + 1) * a.pout + 1 + X0 + i] = u[(HF + j) * (RF + 1) + HF + i];
-    }
-
-    // 3. level l+1's right-hand side on the coarse region (into registers,
-    // then over the fine arrays)
-    constexpr int NQ = (RC * RC + kTileThreads - 1) / kTileThreads;
-    T cf[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int k = tid + q * kTileThreads;
-        cf[q] = T(0);
-        if (k < RC * RC) {
-            const int cj = k / RC, ci = k - cj * RC;
-            const int I = wrap(cx, ci, C.px, C.nm), J = wrap(cy, cj, C.py, C.nm);
-            if (I >= 0 && J >= 0) {
-                const int li = OF + 2 * ci, lj = OF + 2 * cj;
-                const int gx = ox + li, gy = oy + lj;  // unwrapped: side rules only where not periodic
-                const T r00 = resid_region<T, RF>(u, fv, F, li, lj, gx, gy);
-                const T r01 = resid_region<T, RF>(u, fv, F, li + 1, lj, gx + 1, gy);
-                const T r10 = resid_region<T, RF>(u, fv, F, li, lj + 1, gx, gy + 1);
-                const T r11 = resid_region<T, RF>(u, fv, F, li + 1, lj + 1, gx + 1, gy + 1);
-                cf[q] = T(0.25) * (((r00 + r01) + r10) + r11);
-            }
-        }
-    }
-    __syncthreads();  // the fine arrays are free from here
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int k = tid + q * kTileThreads;
-        if (k < RC * RC) {
-            const int cj = k / RC, ci = k - cj * RC;
-            fc[cj * (RC + 1) + ci] = cf[q];
-            uc[cj * (RC + 1) + ci] = T(0);
-        }
-    }
-    __syncthreads();
-    {   // the coarse block's right-hand side out, with its block sum (one coarse cell per thread)
-        const int cj = tid >> 4, ci = tid & 15;
-        const T v = fc[(HC + cj) * (RC + 1) + HC + ci];
-        a.aux[(long)((Y0 >> 1) + cj + 1) * a.paux + 1 + (X0 >> 1) + ci] = v;
-        const double s = block_sum_256((double)v, red);
-        if (tid == 0) a.partial[blockIdx.x] = s;
-    }
-
-    // 4. level l+1: 2 nu sweeps, its block out
-    relax_region<T, RC, 2 * NU>(uc, fc, C, cx, cy);
-    {
-        const int cj = tid >> 4, ci = tid & 15;
-        b.phi_out[(long)((Y0 >> 1) + cj + 1) * b.pout + 1 + (X0 >> 1) + ci] = uc[(HC + cj) * (RC + 1) + HC + ci];
-    }
-
-    // 5. level l+2's right-hand side: the 8 x 8 averages of level l+1's residual
-    double s2 = 0.0;
-    if (tid < 64) {
-        const int kj = tid >> 3, ki = tid & 7;
-        const int ci = HC + 2 * ki, cj = HC + 2 * kj;
-        const int I = (X0 >> 1) + 2 * ki, J = (Y0 >> 1) + 2 * kj;
-        const T r00 = resid_region<T, RC>(uc, fc, C, ci, cj, I, J);
-        const T r01 = resid_region<T, RC>(uc, fc, C, ci + 1, cj, I + 1, J);
-        const T r10 = resid_region<T, RC>(uc, fc, C, ci, cj + 1, I, J + 1);
-        const T r11 = resid_region<T, RC>(uc, fc, C, ci + 1, cj + 1, I + 1, J + 1);
-        const T v = T(0.25) * (((r00 + r01) + r10) + r11);
-        b.aux[(long)((Y0 >> 2) + kj + 1) * b.paux + 1 + (X0 >> 2) + ki] = v;
-        s2 = (double)v;
-    }
-    const double t2 = block_sum_256(s2, red + 0);
-    if (tid == 0) b.partial[blockIdx.x] = t2;
-}
-
 template <typename T, int NU>
 hipError_t go_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, bool restrict_, int nb, hipStream_t s) {
     const dim3 g(nb), blk(kTileThreads);
@@ -495,26 +253,6 @@ hipError_t launch_tile(const MarchArgs<T> &a, int nu, bool load_phi, bool prolon
         default: return hipErrorInvalidValue;
     }
 }
-
-template <typename T>
-hipError_t launch_pair_down(const MarchArgs<T> &a, const MarchArgs<T> &b, int nu, hipStream_t s, int *nblocks) {
-    // level l: at least 128 cells per side (level l+1 is then not in the tail);
-    // no phi shift (both levels start from zero)
-    if (a.n < 2 * kTileMinN || (a.n & (a.n - 1)) || b.n * 2 != a.n || a.phi_shift) return hipErrorInvalidValue;
-    const int tpr = a.n / TS, nb = tpr * tpr;
-    if (nblocks) *nblocks = nb;
-    switch (nu) {
-        case 1: hipLaunchKernelGGL((k_pair_down<T, 1>), dim3(nb), dim3(kTileThreads), 0, s, a, b); break;
-        case 2: hipLaunchKernelGGL((k_pair_down<T, 2>), dim3(nb), dim3(kTileThreads), 0, s, a, b); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template hipError_t launch_pair_down<double>(const MarchArgs<double> &, const MarchArgs<double> &, int, hipStream_t,
-                                             int *);
-template hipError_t launch_pair_down<float>(const MarchArgs<float> &, const MarchArgs<float> &, int, hipStream_t,
-                                            int *);
 
 template hipError_t launch_tile<double>(const MarchArgs<double> &, int, bool, bool, int, hipStream_t, int *);
 template hipError_t launch_tile<float>(const MarchArgs<float> &, int, bool, bool, int, hipStream_t, int *);

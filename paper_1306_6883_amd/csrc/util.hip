@@ -189,3 +189,60 @@ hipError_t launch_set_int(int *p, int count, int v, hipStream_t s) {
 }
 
 }  // namespace ccmg
+
+namespace ccmg {
+
+// Streaming probe: c = a + b over `count` doubles (count even, 16-byte
+// aligned arrays), the access pattern of a launch that reads two arrays and
+// writes one.  Each thread moves four 16-byte pairs per step, all loads issued
+// before the first add.
+__global__ __launch_bounds__(256) void k_probe_stream(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                                                      double2 *__restrict__ c, long pairs) {
+    const long stride = (long)gridDim.x * blockDim.x;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < pairs; i += 4 * stride) {
+        double2 x[4], y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = a[i + k * stride];
+            y[k] = b[i + k * stride];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[i + k * stride] = make_double2(x[k].x + y[k].x, x[k].y + y[k].y);
+    }
+    for (; i < pairs; i += stride) {
+        const double2 x = a[i], y = b[i];
+        c[i] = make_double2(x.x + y.x, x.y + y.y);
+    }
+}
+
+hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_probe_stream, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2 *>(a),
+                       reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(c), count / 2);
+    return hipGetLastError();
+}
+
+}  // namespace ccmg
+
+namespace ccmg {
+
+// Four-cell average of a fine level into the coarse level below it (valid
+// cells only): coarse(I, J) = 1/4 of the fine cells (2I, 2J), (2I+1, 2J),
+// (2I, 2J+1), (2I+1, 2J+1), added in that order.  One thread per coarse cell;
+// blockIdx.y is the coarse row.
+__global__ __launch_bounds__(256) void k_restrict(const double *__restrict__ fine, long pf, double *__restrict__ coarse,
+                                                  long pc, int nc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y;
+    if (I >= nc) return;
+    const double *r0 = fine + (long)(2 * J + 1) * pf + 1 + 2 * I;
+    const double *r1 = r0 + pf;
+    coarse[(long)(J + 1) * pc + 1 + I] = 0.25 * (((r0[0] + r0[1]) + r1[0]) + r1[1]);
+}
+
+hipError_t launch_restrict(const double *fine, long pf, double *coarse, long pc, int nc, hipStream_t s) {
+    hipLaunchKernelGGL(k_restrict, dim3((nc + 255) / 256, nc), dim3(256), 0, s, fine, pf, coarse, pc, nc);
+    return hipGetLastError();
+}
+
+}  // namespace ccmg

@@ -57,12 +57,11 @@ def test_batch_mixed_sizes_and_sides():
         assert np.array_equal(h[1:-1, :], filled[1:-1, :]) and np.array_equal(h[:, 1:-1], filled[:, 1:-1])
 
 
-def test_batch_matches_single_mixed_solves(monkeypatch):
+def test_batch_matches_single_mixed_solves():
     """Each problem of a batch takes the same steps as solving it alone with a
     MIXED plan that runs one FP32 V-cycle per refinement step, as the batch
     does (the same arithmetic; tile shapes may differ, so compare to
     rounding)."""
-    monkeypatch.setenv("CCMG_MIXED_INNER", "1")
     items, probs = make_batch(seed=4, count=8, sizes=(64, 128, 256))
     batch = cc.Batch(probs)
     fs = [dev_field(oracle.embed(it.f)) for it in items]
@@ -70,6 +69,7 @@ def test_batch_matches_single_mixed_solves(monkeypatch):
     res, info = cc.ccmg_batch_solve(batch, fs, phis)
     for i, (it, r, phi, p) in enumerate(zip(items, res, phis, probs)):
         plan = cc.Plan(p)
+        cc.ccmg_plan_set_option(plan, cc.OPT_MIXED_INNER, 1)
         one = dev_field(oracle.field_zeros(it.n))
         r1 = cc.ccmg_solve(plan, fs[i], one)
         assert r1.cycles == r.cycles
@@ -123,7 +123,7 @@ def test_batch_rejects_other_cycle_shapes():
         cc.Batch([cc.Problem(n=64, nu1=1, prec=cc.MIXED)])
 
 
-def test_graph_replays_match_eager_launches(monkeypatch):
+def test_graph_replays_match_eager_launches():
     """Every replay of the captured step graphs gives the same bits as issuing
     the same launches directly, across several solves with other work and
     synchronisations in between."""
@@ -131,10 +131,10 @@ def test_graph_replays_match_eager_launches(monkeypatch):
     batch = cc.Batch(probs)
     fs = [dev_field(oracle.embed(it.f)) for it in items]
     phis = [dev_field(oracle.field_zeros(it.n)) for it in items]
-    monkeypatch.setenv("CCMG_BATCH_EAGER", "1")
+    cc.ccmg_batch_set_option(batch, cc.BATCH_OPT_EAGER, 1)
     res_e, _ = cc.ccmg_batch_solve(batch, fs, phis)
     eager = [host(p) for p in phis]
-    monkeypatch.setenv("CCMG_BATCH_EAGER", "0")
+    cc.ccmg_batch_set_option(batch, cc.BATCH_OPT_EAGER, 0)
     for rep in range(3):
         for p in phis:
             p.fill_(float(rep))  # unrelated eager work between replays
@@ -146,3 +146,26 @@ def test_graph_replays_match_eager_launches(monkeypatch):
                 hb[c] = a[c]
             assert np.array_equal(a, hb)
             assert ra.history == rb.history
+
+
+def test_zero_rhs_with_guess_returns_zero_like_a_single_solve():
+    """A problem with f = 0 in a batch, started from a non-zero guess, returns
+    phi = 0 (valid and ghost cells) with status OK, zero cycles and a zero
+    relative residual -- what ccmg_solve returns for it; the other problems of
+    the batch are unaffected."""
+    items, probs = make_batch(seed=11, count=4, sizes=(32, 64))
+    fs = [dev_field(oracle.embed(it.f)) for it in items]
+    fs[1] = dev_field(oracle.field_zeros(items[1].n))
+    rng = np.random.default_rng(12)
+    phis = [dev_field(oracle.embed(rng.standard_normal((it.n, it.n)))) for it in items]
+    batch = cc.Batch(probs)
+    res, info = cc.ccmg_batch_solve(batch, fs, phis, use_guess=True)
+    assert res[1].status == cc.OK and res[1].cycles == 0 and res[1].rel_resid == 0.0
+    assert not np.any(host(phis[1]))
+    one = cc.Plan(probs[1])
+    single = dev_field(oracle.embed(rng.standard_normal((items[1].n, items[1].n))))
+    r1 = cc.ccmg_solve(one, fs[1], single, use_guess=True)
+    assert r1.status == cc.OK and r1.cycles == 0 and not np.any(host(single))
+    for i in (0, 2, 3):
+        assert res[i].status == cc.OK and res[i].rel_resid <= 1e-10
+        check_against_exact(items[i], host(phis[i]))

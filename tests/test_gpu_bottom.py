@@ -151,10 +151,9 @@ def test_relaxation_bottom_restored_bitwise():
 
 
 @pytest.mark.parametrize("nb", [4, 8])
-def test_autotune_keeps_the_inverse(nb, monkeypatch):
+def test_autotune_keeps_the_inverse(nb):
     """Autotuning clears the plan's scratch, not the bottom's inverse: a tuned
     plan converges like an untuned one, to the same iterate."""
-    monkeypatch.setenv("CCMG_PAIR", "0")
     n, bc = 512, "PPPP"
     fv = W.fourier_modes(n, seed=6, count=64, kmax=32)
     fv = fv - fv.mean()

@@ -52,7 +52,7 @@ def check_against_transforms(prob, fv, bc, sol_tol=1e-9):
 
 
 def test_plain_poisson_4096_periodic():
-    """The headline: 4096^2 periodic, 64 Fourier modes |k| <= 32, seed 0."""
+    """4096^2 periodic, 64 Fourier modes |k| <= 32, seed 0."""
     n = 4096
     fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
     r = check_against_transforms(cc.Problem(n=n, bc="P", rtol=1e-10), fv, "PPPP")
@@ -60,7 +60,9 @@ def test_plain_poisson_4096_periodic():
 
 
 def test_plain_poisson_8192_dirichlet():
+    """The headline: 8192^2 Dirichlet, 64 Fourier modes |k| <= 32, seed 0."""
     n = 8192
+    print(f"plain FP64 Poisson n={n} Dirichlet", flush=True)
     fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
     check_against_transforms(cc.Problem(n=n, bc="D", rtol=1e-10), fv, "DDDD")
 
@@ -72,6 +74,26 @@ def test_mixed_crank_nicolson_8192(c):
     g = W.gaussian_random_field(n, seed=0)
     prob = cc.Problem(n=n, bc="P", alpha=1.0, beta=c / (2.0 * n * n), rtol=1e-10, prec=cc.MIXED)
     check_against_transforms(prob, g, "PPPP")
+
+
+@pytest.mark.parametrize("c", [0.1, 1.0, 10.0])
+def test_plain_fp64_helmholtz_8192(c):
+    """The same Crank-Nicolson Helmholtz solves in plain FP64 (the baseline
+    of the mixed form's speed-up), autotuned, fused finest launches."""
+    n = 8192
+    print(f"plain FP64 Helmholtz n={n} c={c}", flush=True)
+    g = W.gaussian_random_field(n, seed=0)
+    prob = cc.Problem(n=n, bc="P", alpha=1.0, beta=c / (2.0 * n * n), rtol=1e-10, prec=cc.FP64)
+    check_against_transforms(prob, g, "PPPP")
+
+
+def test_mixed_poisson_8192_dirichlet():
+    """The mixed form on the 8192^2 Dirichlet Poisson workload (FP32 cycles,
+    FP64 refinement), against the DST solve."""
+    n = 8192
+    print(f"mixed Poisson n={n} Dirichlet", flush=True)
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    check_against_transforms(cc.Problem(n=n, bc="D", rtol=1e-10, prec=cc.MIXED), fv, "DDDD")
 
 
 def test_batched_512_against_oracle_solves():

@@ -2,8 +2,6 @@
 the pre-smoothing of the next in one launch: the same iterates, residual
 history and result as the unfused cycles, for every side type, plus the path
 where the last cycle's post-smoothed iterate was not kept."""
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -29,24 +27,10 @@ def valid(t):
     return t[1:n + 1, 1:n + 1].cpu().numpy()
 
 
-class env:
-    def __init__(self, **kv):
-        self.kv = kv
-
-    def __enter__(self):
-        self.old = {k: os.environ.get(k) for k in self.kv}
-        os.environ.update({k: str(v) for k, v in self.kv.items()})
-
-    def __exit__(self, *a):
-        for k, v in self.old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-
-
-def solve(n, bc, fv, guess=None, **kw):
+def solve(n, bc, fv, guess=None, options=None, **kw):
     plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc), rtol=1e-10, **kw))
+    for opt, v in (options or {}).items():
+        cc.ccmg_plan_set_option(plan, opt, v)
     f = dev_field(oracle.embed(fv))
     phi = dev_field(oracle.embed(guess) if guess is not None else oracle.field_zeros(n))
     r = cc.ccmg_solve(plan, f, phi, use_guess=guess is not None)
@@ -59,8 +43,7 @@ def test_fused_solve_matches_unfused(bc, n):
     fv = W.fourier_modes(n, seed=4, count=16, kmax=8)
     if not exact.is_singular(0.0, bc):
         fv = fv + 0.3  # a mean, where the problem allows one
-    with env(CCMG_FUSED="0"):
-        r0, p0, _ = solve(n, bc, fv)
+    r0, p0, _ = solve(n, bc, fv, options={cc.OPT_FUSED: 0})
     r1, p1, plan = solve(n, bc, fv)
     assert r0.status == r1.status == cc.OK
     assert r0.cycles == r1.cycles
@@ -89,8 +72,7 @@ def test_fused_solve_with_guess_and_helmholtz(bc):
     fv -= fv.mean()
     guess = 0.01 * np.random.default_rng(2).standard_normal((n, n))
     for kw in ({}, {"alpha": 1.0, "beta": 0.5 / (n * n)}):
-        with env(CCMG_FUSED="0"):
-            r0, p0, _ = solve(n, bc, fv, guess, **kw)
+        r0, p0, _ = solve(n, bc, fv, guess, options={cc.OPT_FUSED: 0}, **kw)
         r1, p1, _ = solve(n, bc, fv, guess, **kw)
         assert r0.status == r1.status == cc.OK and r0.cycles == r1.cycles
         a, b = valid(p0), valid(p1)
@@ -103,8 +85,7 @@ def test_fused_solve_when_last_iterate_was_not_kept(bc):
     returns the next cycle's pre-smoothed iterate, checked by its own residual."""
     n = 512
     fv = W.fourier_modes(n, seed=9, count=16, kmax=8)
-    with env(CCMG_FUSED_KEEP="0"):
-        r, p, _ = solve(n, bc, fv)
+    r, p, _ = solve(n, bc, fv, options={cc.OPT_FUSED_KEEP: 0})
     assert r.status == cc.OK and r.rel_resid <= 1e-10
     got = valid(p)
     h = 1.0 / n
@@ -146,3 +127,16 @@ def test_kernel_stats_count_only_launches_that_ran(c):
     assert r.status == cc.OK
     counted = sum(stats[k]["launches"] for k in ("finest_pre", "finest_post", "finest_fused"))
     assert counted == r.cycles + 1, (counted, r.cycles)
+
+
+def test_plan_options_round_trip_and_reject_bad_values():
+    plan = cc.Plan(cc.Problem(n=64, bc="D"))
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_FUSED) == 1.0
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_FUSED_KEEP) == 100.0
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_MIXED_INNER) == 3.0
+    cc.ccmg_plan_set_option(plan, cc.OPT_MIXED_INNER, 5)
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_MIXED_INNER) == 5.0
+    for opt, bad in ((cc.OPT_FUSED, 2), (cc.OPT_FUSED_KEEP, -1), (cc.OPT_MIXED_INNER, 0), (cc.OPT_MIXED_INNER, 2.5),
+                     (cc.OPT_MIXED_INNER, 9), (99, 1), (cc.OPT_FUSED_KEEP, float("nan"))):
+        with pytest.raises(cc.CcmgError):
+            cc.ccmg_plan_set_option(plan, opt, bad)

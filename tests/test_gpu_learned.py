@@ -218,6 +218,11 @@ def test_learned_solve_rejects_bad_arguments(M):
     helm = M.Plan(M.Problem(n=256, bc="P", alpha=1.0, beta=-1.0))
     with pytest.raises(M.CcmgError):
         M.ccmg_solve_learned(helm, net, M.field(256), M.field(256))  # not the trained problem
+    for sides in ("D", ("P", "P", "D", "D"), ("N", "N", "P", "P")):
+        other = M.Plan(M.Problem(n=256, bc=sides))
+        with pytest.raises(M.CcmgError) as e:
+            M.ccmg_solve_learned(other, net, M.field(256), M.field(256))  # trained on periodic sides only
+        assert e.value.status == M.EINVAL
 
 
 def test_trained_network_gains_over_zero_guess(M):

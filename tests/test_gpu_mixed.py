@@ -122,11 +122,10 @@ def test_mixed_guess_and_history():
 
 
 @pytest.mark.parametrize("bc", ["DDDD", "PPPP", "DNPP"])
-def test_mixed_tile_kernel_matches_row_march(bc, monkeypatch):
+def test_mixed_tile_kernel_matches_row_march(bc):
     """The FP32 inner cycles give the same iterate whether the levels below the
     finest run as row-march bands or as 2-D LDS tiles (bitwise; singular
     problems to rounding, their coarse means being sums grouped by tile)."""
-    monkeypatch.setenv("CCMG_PAIR", "0")  # every level's own launches
     n = 1024
     fv = np.random.default_rng(33).standard_normal((n, n))
     if exact.is_singular(0.0, bc):
@@ -154,7 +153,7 @@ def test_mixed_tile_kernel_matches_row_march(bc, monkeypatch):
 
 @pytest.mark.parametrize("bc", ["PPPP", "DDDD", "DNPP"])
 @pytest.mark.parametrize("m", [1, 2, 3])
-def test_mixed_steps_with_inner_cycles_match_oracle(bc, m, monkeypatch):
+def test_mixed_steps_with_inner_cycles_match_oracle(bc, m):
     """Refinement steps of several FP32 V-cycles from a zero correction: the
     first step runs min(2, m) cycles, the second (its contraction now known,
     the tolerance far away) m; from phi = 0 the two steps together equal
@@ -165,8 +164,8 @@ def test_mixed_steps_with_inner_cycles_match_oracle(bc, m, monkeypatch):
     fv = np.random.default_rng(41).standard_normal((n, n))
     if sing:
         fv -= fv.mean()
-    monkeypatch.setenv("CCMG_MIXED_INNER", str(m))
     plan = mixed_plan(n, bc, max_cycles=2, rtol=1e-14)  # the tolerance asks for more cycles
+    cc.ccmg_plan_set_option(plan, cc.OPT_MIXED_INNER, m)
     d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
     r = cc.ccmg_solve(plan, d_f, d_phi)
     total = min(2, m) + m
@@ -182,7 +181,7 @@ def test_mixed_steps_with_inner_cycles_match_oracle(bc, m, monkeypatch):
 
 
 @pytest.mark.parametrize("bc", ["PPPP", "DDDD", "NNNN", "DNPP"])
-def test_mixed_inner_cycles_against_one_cycle_steps(bc, monkeypatch):
+def test_mixed_inner_cycles_against_one_cycle_steps(bc):
     """Several FP32 cycles per refinement step reach the same FP64 tolerance
     and the same solution as one cycle per step, in fewer steps and about the
     same number of FP32 cycles; the fused launch joins the inner cycles."""
@@ -194,8 +193,8 @@ def test_mixed_inner_cycles_against_one_cycle_steps(bc, monkeypatch):
         fv -= fv.mean()
     outs = {}
     for m in ("1", "3"):
-        monkeypatch.setenv("CCMG_MIXED_INNER", m)
         plan = mixed_plan(n, bc)
+        cc.ccmg_plan_set_option(plan, cc.OPT_MIXED_INNER, int(m))
         d_f, d_phi = dev_field(oracle.embed(fv)), dev_field(oracle.field_zeros(n))
         r = cc.ccmg_solve(plan, d_f, d_phi)
         assert r.status == cc.OK and r.rel_resid <= 1e-10

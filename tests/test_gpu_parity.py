@@ -101,6 +101,37 @@ def test_restrict_residual_matches_oracle(bc, n):
     assert np.max(np.abs(got - oracle.interior(want))) < 1e-12 * np.max(np.abs(oracle.interior(f)))
 
 
+@pytest.mark.parametrize("n", [2, 4, 64, 512, 2048])
+@pytest.mark.parametrize("level", [0, 1])
+def test_restrict_matches_oracle(n, level):
+    """The standalone four-cell average (Sec. 3.3) equals the oracle's
+    restriction bit for bit (same additions in the same order), on the finest
+    level and the one below it; the coarse ghosts and the fine array are left
+    alone."""
+    if n >> level < 2:
+        pytest.skip("no coarser level")
+    plan = plan_for(n, "DDDD")
+    nl = n >> level
+    fine = rand(nl, 30 + nl)
+    d_fine = dev_field(fine)
+    coarse = dev_field(np.full((nl // 2 + 2, nl // 2 + 2), 7.0))
+    cc.ccmg_restrict(plan, level, d_fine, coarse)
+    want = oracle.restrict(fine.copy())
+    got = host(coarse)
+    assert np.array_equal(oracle.interior(got), oracle.interior(want))
+    assert np.all(got[0, :] == 7.0) and np.all(got[-1, :] == 7.0) and np.all(got[:, 0] == 7.0)
+    assert np.array_equal(host(d_fine), fine)
+
+
+def test_restrict_rejects_bad_arguments():
+    plan = plan_for(64, "PPPP")
+    fine = dev_field(oracle.field_zeros(64))
+    with pytest.raises(cc.CcmgError):  # overlapping arrays
+        cc.ccmg_restrict(plan, 0, fine, fine[:34, :34])
+    with pytest.raises(cc.CcmgError):  # no level below the coarsest
+        cc.ccmg_restrict(plan_for(2, "PPPP"), 0, dev_field(oracle.field_zeros(2)), dev_field(oracle.field_zeros(1)))
+
+
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("n", [4, 8, 64, 256, 512])
 def test_prolong_add_matches_oracle(bc, n):
@@ -262,14 +293,13 @@ def test_deterministic_bitwise():
 
 
 @pytest.mark.parametrize("bc", ["PPPP", "DNDD"])
-def test_tile_shape_invariance(bc, monkeypatch):
+def test_tile_shape_invariance(bc):
     """Every cell's arithmetic is independent of how a level is cut into tiles:
     three V-cycles give bitwise-identical iterates for any launch shapes (row
     march bands, or the 2-D LDS tile kernel below the finest level), and
     after autotuning.  Singular problems (all periodic) also remove the mean of
     each coarse right-hand side, a sum whose grouping follows the tiles, so
     there the iterates agree to rounding instead."""
-    monkeypatch.setenv("CCMG_PAIR", "0")  # every level's own launches (pairs are tested on their own)
     n = 1024
     plan = plan_for(n, bc)
     fv = W.fourier_modes(n, seed=5, count=16, kmax=8)
