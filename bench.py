@@ -379,11 +379,15 @@ def batched_vs_sequential(cc, torch, W, reps):
     return out
 
 
-def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
+def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=256):
     """The learned form: periodic Poisson 1024^2 with Gaussian-blob right-hand
     sides.  Training pairs from plain multigrid solves of seeds 0..train_seeds-1,
-    training on the GPU, then time to 1e-10 with the learned guess (guess time
-    included) against the zero guess on unseen seeds 100000+."""
+    training on the GPU, then time to 1e-10 (guess time included) on unseen
+    seeds 100000..100000+eval_seeds-1 for: the zero guess, the learned guess,
+    the learned guess's decoder run on a zero network output (network weights
+    all zero), and k = 1, 2 V-cycles of the averaged problem on the network's
+    grid plus the same prolongations (non-learned guesses of about the
+    network's cost)."""
     from paper_1306_6883_amd import learned as L
     n = 1024
     net = L.new_net(batch=32, n_max=n, seed=0)
@@ -396,34 +400,25 @@ def learned_vs_plain(cc, torch, W, train_seeds, train_steps, eval_seeds=32):
     hist = L.train(net, data, steps=train_steps, batch=32, lr=1e-3, lr_final=1e-5, warmup=200)
     t_train = time.perf_counter() - t0
     del data
-    ev = L.make_dataset(net, n, range(100000, 100000 + 256), plan=plan)
+    ev = L.make_dataset(net, n, range(100000, 100000 + eval_seeds), plan=plan)
     err = L.target_error(net, ev)
     del ev
     log(f"learned: {train_steps} Adam steps (batch 32) in {t_train:.1f} s, loss {hist[-1][1]:.3e}, "
         f"held-out error on the network grid {err:.4f}")
-    cmp = L.compare(net, n, range(100000, 100000 + eval_seeds), plan=plan, reps=3)
-    # the guess alone
-    f = cc.field(n)
-    f[1:n + 1, 1:n + 1] = W.gaussian_blobs_torch(n, [100000])[0]
-    g = cc.field(n)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tg = []
-    for _ in range(20):
-        e0.record()
-        cc.ccmg_net_guess(net, f, g)
-        e1.record()
-        e1.synchronize()
-        tg.append(e0.elapsed_time(e1))
-    mz, ml = float(np.mean(cmp.ms_zero)), float(np.mean(cmp.ms_learned))
+    cmp = L.compare_guesses(net, n, range(100000, 100000 + eval_seeds), plan=plan, reps=2)
+    guesses = {k: dict(ms=round(float(np.mean(cmp.ms[k])), 4), cycles=round(float(np.mean(cmp.cycles[k])), 3),
+                       guess_ms=round(cmp.guess_ms[k], 4)) for k in cmp.ms}
+    mz = guesses["zero"]["ms"]
+    for k, g in guesses.items():
+        g["speedup_vs_zero"] = round(mz / g["ms"], 3)
     out = dict(n=n, train_solves=train_seeds, train_steps=train_steps, dataset_s=round(t_data, 1),
                train_s=round(t_train, 1), final_loss=hist[-1][1], heldout_error=round(err, 5),
                eval_seeds=f"100000..{100000 + eval_seeds - 1}", coarse_iters=cc.COARSE_ITERS,
-               cycles_zero=float(np.mean(cmp.cycles_zero)), cycles_learned=float(np.mean(cmp.cycles_learned)),
-               ms_zero=round(mz, 4), ms_learned=round(ml, 4), guess_ms=round(float(np.median(tg)), 4),
-               guess_error=round(float(np.mean(cmp.guess_error)), 5), speedup=round(mz / ml, 3),
-               all_reached_tol=True)
-    log(f"learned 1024^2: {out['cycles_zero']:.2f} -> {out['cycles_learned']:.2f} cycles, "
-        f"{mz:.3f} -> {ml:.3f} ms (guess {out['guess_ms']:.3f} ms), x{out['speedup']}")
+               cycles_zero=guesses["zero"]["cycles"], cycles_learned=guesses["learned"]["cycles"],
+               ms_zero=mz, ms_learned=guesses["learned"]["ms"], guess_ms=guesses["learned"]["guess_ms"],
+               speedup=guesses["learned"]["speedup_vs_zero"], guesses=guesses, all_reached_tol=True)
+    log("learned 1024^2 (" + out["eval_seeds"] + "): " +
+        ", ".join(f"{k} {g['cycles']:.2f} cyc {g['ms']:.3f} ms (guess {g['guess_ms']:.3f})" for k, g in guesses.items()))
     del net, plan
     torch.cuda.empty_cache()
     return out

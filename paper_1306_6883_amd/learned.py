@@ -24,7 +24,8 @@ import workloads as W
 
 from . import (NET_G, OK, Net, Plan, Problem, ccmg_net_encode, ccmg_net_forward, ccmg_net_get_params,
                ccmg_net_guess, ccmg_net_param_count, ccmg_net_set_params, ccmg_net_train_step,
-               ccmg_plan_autotune, ccmg_solve, ccmg_solve_learned, field)
+               ccmg_plan_autotune, ccmg_prolong_add, ccmg_restrict, ccmg_solve, ccmg_solve_learned, ccmg_vcycle,
+               field)
 
 # layer shapes in parameter order: (out channels, taps, in channels)
 _LAYERS = [(32, 9, 1), (32, 9, 32), (32, 9, 32), (32, 9, 32), (32, 9, 32), (1, 9, 32)]
@@ -184,6 +185,108 @@ def compare(net: Net, n: int, seeds, plan: Plan | None = None, reps: int = 1) ->
         out.ms_learned.append(best_l)
         out.rel_resid_guess.append(rl.rel_resid0)
         out.used.append(used)
+    return out
+
+
+@dataclass
+class GuessComparison:
+    """Time to tolerance (guess included) and V-cycles per problem for each
+    way of starting the solve, and each guess's own cost."""
+    seeds: list
+    ms: dict          # name -> [ms per seed]
+    cycles: dict      # name -> [cycles per seed]
+    guess_ms: dict    # name -> median ms of the guess alone
+
+
+class CoarseGuess:
+    """A non-learned guess of the same shape as the learned one: the right-hand
+    side averaged onto the network's grid (multigrid restriction), k V-cycles
+    of the Poisson problem there from zero, then multigrid prolongations back
+    to the full grid -- every step through the library's entry points."""
+
+    def __init__(self, plan: Plan, k: int):
+        n = plan.n
+        self.plan, self.k, self.n = plan, k, n
+        self.levels = int(round(math.log2(n // NET_G)))
+        dev = plan.workspace.device
+        self.coarse_plan = Plan(periodic_poisson(NET_G), device=dev, stream=plan.stream)
+        self.f = [None] + [field(n >> l, device=dev) for l in range(1, self.levels + 1)]
+        self.e = [None] + [field(n >> l, device=dev) for l in range(1, self.levels + 1)]
+        self.zero = [field(n >> l, device=dev) for l in range(self.levels)]
+
+    def __call__(self, f: torch.Tensor, phi: torch.Tensor) -> None:
+        L = self.levels
+        src = f
+        for l in range(L):
+            ccmg_restrict(self.plan, l, src, self.f[l + 1])
+            src = self.f[l + 1]
+        self.e[L].zero_()
+        for _ in range(self.k):
+            ccmg_vcycle(self.coarse_plan, self.f[L], self.e[L])
+        for l in range(L - 1, -1, -1):
+            ccmg_prolong_add(self.plan, l, self.e[l + 1], self.zero[l], phi if l == 0 else self.e[l])
+
+
+def compare_guesses(net: Net, n: int, seeds, plan: Plan | None = None, reps: int = 1, coarse_k=(1, 2)):
+    """Zero guess, the learned guess, the learned guess's decoder run on a zero
+    network output (a network with all weights zero: 32 relaxations on the
+    network's grid, then the prolongations), and k V-cycles of the averaged
+    problem on the network's grid plus the prolongations: the time to
+    tolerance of each (guess included) and its V-cycles, on the same
+    problems and the same plan."""
+    dev = net.device
+    plan = plan or Plan(periodic_poisson(n), device=dev, stream=net.stream)
+    zero_net = Net(batch=1, n_max=n, device=dev, stream=net.stream)
+    ccmg_net_set_params(zero_net, torch.zeros(ccmg_net_param_count(), dtype=torch.float32, device=dev))
+    coarse = {k: CoarseGuess(plan, k) for k in coarse_k}
+    f = field(n, device=dev)
+    phi = field(n, device=dev)
+    names = ["zero", "learned", "decoder_only"] + [f"coarse_vcycles_{k}" for k in coarse_k]
+    out = GuessComparison(list(seeds), {k: [] for k in names}, {k: [] for k in names}, {})
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gtimes = {k: [] for k in names}
+
+    def timed_guess(fn):
+        e0.record(plan.stream)
+        fn()
+        e1.record(plan.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    with torch.cuda.stream(plan.stream):
+        for s in seeds:
+            f[1:n + 1, 1:n + 1] = W.gaussian_blobs_torch(n, [s], device=dev)[0]
+            best = {k: float("inf") for k in names}
+            cyc = {}
+            for _ in range(reps):
+                phi.zero_()
+                r = ccmg_solve(plan, f, phi)
+                best["zero"] = min(best["zero"], r.ms)
+                cyc["zero"] = r.cycles
+                for name, nt in (("learned", net), ("decoder_only", zero_net)):
+                    phi.zero_()
+                    r, used = ccmg_solve_learned(plan, nt, f, phi)
+                    if not used:
+                        raise RuntimeError(f"seed {s}: {name} guess discarded")
+                    best[name] = min(best[name], r.ms)
+                    cyc[name] = r.cycles
+                for k, g in coarse.items():
+                    name = f"coarse_vcycles_{k}"
+                    phi.zero_()
+                    gms = timed_guess(lambda: g(f, phi))
+                    r = ccmg_solve(plan, f, phi, use_guess=True)
+                    if r.status != OK:
+                        raise RuntimeError(f"seed {s}: {name} status {r.status}")
+                    best[name] = min(best[name], gms + r.ms)
+                    cyc[name] = r.cycles
+                    gtimes[name].append(gms)
+                for name, nt in (("learned", net), ("decoder_only", zero_net)):
+                    gtimes[name].append(timed_guess(lambda: ccmg_net_guess(nt, f, phi)))
+            for k in names:
+                out.ms[k].append(best[k])
+                out.cycles[k].append(cyc[k])
+    out.guess_ms = {k: float(np.median(v)) for k, v in gtimes.items() if v}
+    out.guess_ms["zero"] = 0.0
     return out
 
 

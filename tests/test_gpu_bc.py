@@ -130,18 +130,21 @@ def test_solve_bc_against_exact_discrete_solution(bc, n, ab):
 def test_linear_data_reproduced_at_full_size(prec):
     """Laplace on 4096^2 with the side data of a linear function (Dirichlet on
     x-lo and y-hi, Neumann on x-hi and y-lo), autotuned plan: the solution is
-    that function at the cell centres."""
+    that function at the cell centres (relative error <= 1e-9).  Tolerance
+    1e-11, the paper's (Sec. 3.3.1): the right-hand side is only the data's
+    part next to the sides, and at 1e-10 the error of any iterate can exceed
+    1e-9 (1.6e-9 seen)."""
     n = 4096
     bc = "DNND"
     lin = lambda X, Y: 0.3 + 1.7 * X - 0.6 * Y
     dx, dy = (lambda X, Y: 1.7 + 0.0 * X), (lambda X, Y: -0.6 + 0.0 * X)
     b = side_data(bc, lin, dx, dy, n)
-    plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc), rtol=1e-10, prec=prec))
+    plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc), rtol=1e-11, prec=prec))
     d_f = torch.zeros((n + 2, n + 2), dtype=torch.float64, device="cuda")
     d_phi, d_w = torch.zeros_like(d_f), torch.zeros_like(d_f)
     cc.ccmg_plan_autotune(plan, d_f, d_phi)
     r = cc.ccmg_solve_bc(plan, d_f, d_phi, dev_sides(b), d_w)
-    assert r.status == cc.OK and r.rel_resid <= 1e-10
+    assert r.status == cc.OK and r.rel_resid <= 1e-11
     t = torch.from_numpy(centres(n)).cuda()
     want = 0.3 + 1.7 * t[None, :] - 0.6 * t[:, None]
     # the linear function is the exact discrete solution: relative error

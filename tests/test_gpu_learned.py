@@ -68,11 +68,16 @@ def test_loss_and_every_layer_gradient_match_oracle(M):
     g = g.cpu().numpy()
     lb, gb = ON.loss_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64), bf=True)
     assert abs(loss - lb) <= 1e-3 * lb
+    # Same rounding points; the GPU sums in FP32 (the oracle in FP64), so a
+    # back-propagated value within ~sqrt(288) 2^-24 of a bfloat16 midpoint
+    # rounds the other way (one bfloat16 unit, 2^-8): about 1e-3 of the values
+    # per layer, ~1e-4 of a layer's norm, accumulating over the five rounded
+    # stages below the output -- bound 1e-3 (seen: <= 2.7e-4).
     o = 0
     for l, sz in enumerate(ON.SIZES):
         e = rel(g[o:o + sz], gb[o:o + sz])
         print(f"layer {l + 1}: gradient rel err {e:.2e}")
-        assert e < 5e-3, l
+        assert e < 1e-3, l
         o += sz
 
 
@@ -227,8 +232,12 @@ def test_learned_solve_rejects_bad_arguments(M):
 
 def test_trained_network_gains_over_zero_guess(M):
     """A network trained on the GPU on plain-multigrid solutions (training
-    seeds 0..4095) guesses unseen problems (seeds 100000+) well enough to save
-    V-cycles, and the solve from its guess still reaches the tolerance."""
+    seeds 0..4095) guesses unseen problems (seeds 100000..100255) well enough
+    to save V-cycles, and every solve from a guess still reaches the
+    tolerance.  Beside it, for attribution: the same decoder run on a zero
+    network output, and non-learned guesses of about the network's cost
+    (k V-cycles of the averaged problem on the network's grid, then the
+    prolongations)."""
     from paper_1306_6883_amd import learned as L
     n = 1024
     net = L.new_net(batch=32, n_max=n, seed=0)
@@ -239,8 +248,11 @@ def test_trained_network_gains_over_zero_guess(M):
     assert hist[-1][1] < 1e-3 * hist[0][1]
     cmp = L.compare(net, n, range(100000, 100008), plan=plan)
     print("guess error", np.round(cmp.guess_error, 4))
-    print("cycles zero", cmp.cycles_zero, "learned", cmp.cycles_learned)
-    print("ms zero", np.round(cmp.ms_zero, 3), "learned", np.round(cmp.ms_learned, 3))
     assert all(cmp.used)
     assert np.mean(cmp.guess_error) < 0.05
-    assert np.mean(cmp.cycles_learned) <= np.mean(cmp.cycles_zero) - 1
+    g = L.compare_guesses(net, n, range(100000, 100256), plan=plan)
+    for k in g.ms:
+        print(f"{k}: cycles {np.mean(g.cycles[k]):.2f}, ms {np.mean(g.ms[k]):.3f} (guess {g.guess_ms[k]:.3f})")
+    assert len(g.cycles["learned"]) == 256
+    assert np.mean(g.cycles["learned"]) <= np.mean(g.cycles["zero"]) - 1
+    assert np.mean(g.cycles["decoder_only"]) <= np.mean(g.cycles["zero"])
