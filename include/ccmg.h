@@ -230,6 +230,24 @@ int ccmg_cn_step(ccmg_plan *plan, double *d_phi, double *d_work, ptrdiff_t pitch
  * in place on d_phi, without a stop test.  Asynchronous. */
 int ccmg_vcycle(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): ccmg_vcycle of the FP64
+ * problem *p without a plan or workspace.  Exactly one V-cycle in place on
+ * d_phi (same kernels, launch shapes and iterates as ccmg_vcycle on an
+ * untuned plan of *p), enqueued on `stream` (a hipStream_t, NULL = default)
+ * and asynchronous.  The levels below the finest live in a static device
+ * array of ccmg_noalloc_scratch_bytes() bytes (32 MiB), one per device, which
+ * every call on that device shares and which keeps the last call's contents;
+ * a V-cycle writes every part of it before reading it.  Nothing is allocated,
+ * on the device or the host.  Returns CCMG_EWORKSPACE when the problem's
+ * coarse levels need more than the scratch (FP64 grids of more than
+ * 1024 x 1024 cells), CCMG_EINVAL for a MIXED problem, NULL arrays, a bad
+ * pitch or a device index of 16 or more, and ccmg_problem_check's status for
+ * an invalid problem.  Calls that overlap on one device race on the scratch:
+ * order them on one stream (calls on distinct devices are independent). */
+int ccmg_vcycle_noalloc(const ccmg_problem *p, const double *d_f, double *d_phi, ptrdiff_t pitch, void *stream);
+size_t ccmg_noalloc_scratch_bytes(void);
+
 /* ---- single steps at one level, for checking each kernel (asynchronous).
  * `level` l has n >> l cells per side and spacing h * 2^l; every level uses
  * the homogeneous version of the plan's side types and the plan's

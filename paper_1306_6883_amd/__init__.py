@@ -133,6 +133,9 @@ def lib():
         L.ccmg_plan_set_option.argtypes = [vp, i, ctypes.c_double]
         L.ccmg_plan_get_option.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
         L.ccmg_batch_set_option.argtypes = [vp, i, ctypes.c_double]
+        L.ccmg_vcycle_noalloc.argtypes = [P, dp, dp, pd, vp]
+        L.ccmg_noalloc_scratch_bytes.restype = sz
+        L.ccmg_noalloc_scratch_bytes.argtypes = []
         _lib = L
     return _lib
 
@@ -251,6 +254,21 @@ class Plan:
 
     def level_n(self, level: int) -> int:
         return self.prob.n >> level
+
+
+def ccmg_vcycle_noalloc(prob: Problem, f: torch.Tensor, phi: torch.Tensor, stream=None) -> None:
+    """One V-cycle of `prob` in place on phi without a plan: the library's
+    static device scratch holds the coarse levels (nothing is allocated)."""
+    fp, pitch = _field_args(f, prob.n)
+    pp, p2 = _field_args(phi, prob.n)
+    if pitch != p2:
+        raise ValueError("f and phi must share one pitch")
+    c = prob.to_c()
+    _check(lib().ccmg_vcycle_noalloc(ctypes.byref(c), fp, pp, pitch, _stream_handle(stream)), "ccmg_vcycle_noalloc")
+
+
+def ccmg_noalloc_scratch_bytes() -> int:
+    return lib().ccmg_noalloc_scratch_bytes()
 
 
 def ccmg_plan_set_option(plan: Plan, option: int, value: float) -> None:

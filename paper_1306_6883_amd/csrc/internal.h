@@ -195,6 +195,11 @@ hipError_t launch_restrict(const double *fine, long pf, double *coarse, long pc,
 // c = a + b over `count` doubles (even count, 16-byte aligned): a streaming probe.
 hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, hipStream_t s);
 
+// The library's static device scratch (noalloc.hip): its address on device
+// `dev` (looked up once per device, with that device current) and its size.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+hipError_t static_scratch(int dev, void **ptr, size_t *bytes);
+
 // The stream and finest size of a plan (for entry points outside plan.cpp).
 hipStream_t plan_stream(const ccmg_plan *P);
 int plan_n(const ccmg_plan *P);

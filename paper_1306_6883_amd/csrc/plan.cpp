@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -57,11 +58,13 @@ struct LevelLay {
     int fpart_cap = 0;
 };
 
+constexpr int kMaxLevels = 16;  // n <= 16384: at most 14 levels
+
 struct Layout {
     int L = 0;             // levels n, n/2, ..., 2
     int lt = 0;            // first level handled by the one-workgroup tail
     size_t elem = 8;       // bytes per value of the relaxed levels (8 FP64, 4 MIXED)
-    std::vector<LevelLay> lev;
+    LevelLay lev[kMaxLevels];
     size_t qb = 0;         // MIXED: second FP64 iterate buffer (finest level)
     size_t normpart = 0;
     int normpart_cap = 0;
@@ -79,7 +82,7 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     lay.elem = mixed ? sizeof(float) : sizeof(double);
     lay.L = 0;
     while ((n >> lay.L) >= 2) ++lay.L;
-    lay.lev.assign(lay.L, LevelLay());
+    for (int l = 0; l < kMaxLevels; ++l) lay.lev[l] = LevelLay();
     const double h0 = (p.xmax - p.xmin) / n;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -164,8 +167,6 @@ struct KernelTimer {
     double ms[kKinds] = {}, tbytes[kKinds] = {};
 };
 
-constexpr int kMaxLevels = 16;
-
 struct ccmg_plan {
     ccmg_problem p;
     KernelTimer timer;
@@ -226,6 +227,14 @@ struct ccmg_plan {
     int *done() const { return at<int>(lay.flags); }
 };
 
+// Host side of ccmg_vcycle_noalloc: one plan object per device (guarded by
+// a mutex each), built at library load, re-initialised by every call.
+namespace {
+constexpr int kNoallocDevices = 16;
+ccmg_plan g_noalloc_plan[kNoallocDevices];
+std::mutex g_noalloc_mu[kNoallocDevices];
+}  // namespace
+
 hipStream_t ccmg::plan_stream(const ccmg_plan *P) { return P->stream; }
 int ccmg::plan_n(const ccmg_plan *P) { return P->lay.lev[0].n; }
 const ccmg_problem *ccmg::plan_problem(const ccmg_plan *P) { return &P->p; }
@@ -269,15 +278,23 @@ void level_consts(const ccmg_plan *P, int l, MarchArgs<T> &a) {
     for (int s = 0; s < 4; ++s) a.bc[s] = P->p.bc[s];
 }
 
-// Split nu relaxations into launches of at most two iterations.
-std::vector<int> split_nu(int nu) {
-    std::vector<int> v;
+// Split nu (0..8) relaxations into launches of at most two iterations.
+struct NuChain {
+    int k[5];
+    int count;
+    size_t size() const { return (size_t)count; }
+    int operator[](size_t i) const { return k[i]; }
+    int front() const { return k[0]; }
+    int back() const { return k[count - 1]; }
+};
+NuChain split_nu(int nu) {
+    NuChain v{};
     if (nu == 0) {
-        v.push_back(0);
+        v.k[v.count++] = 0;
         return v;
     }
-    if (nu & 1) v.push_back(1);
-    for (int i = 0; i < nu / 2; ++i) v.push_back(2);
+    if (nu & 1) v.k[v.count++] = 1;
+    for (int i = 0; i < nu / 2; ++i) v.k[v.count++] = 2;
     return v;
 }
 
@@ -341,8 +358,8 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     const Layout &lay = P->lay;
     hipStream_t s = P->stream;
     hipError_t e;
-    std::vector<Buf<T>> cur(lay.L), other(lay.L);
-    std::vector<int> fpart_count(lay.L, 0);
+    Buf<T> cur[kMaxLevels] = {}, other[kMaxLevels] = {};
+    int fpart_count[kMaxLevels] = {};
     const bool f64 = sizeof(T) == sizeof(double);
     *norm_tiles = 0;
 
@@ -395,7 +412,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     for (int l = io.coarse_only ? 1 : 0; l < lay.lt; ++l) {
         setup_bufs(l);
         const MarchShape sh = P->shp_pre[l];
-        const std::vector<int> chain = split_nu(P->p.nu1);
+        const NuChain chain = split_nu(P->p.nu1);
         bool zero = (l > 0) || io.zero;
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
@@ -455,7 +472,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     // up
     for (int l = lay.lt - 1; l >= (io.coarse_only ? 1 : 0); --l) {
         const MarchShape sh = P->shp_post[l];
-        const std::vector<int> chain = split_nu(P->p.nu2);
+        const NuChain chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
             MarchArgs<T> a{};
@@ -737,6 +754,25 @@ hipError_t enqueue_mixed_step_inner(ccmg_plan *P, const double *d_f, long pf, Mi
                             skip ? P->drho + slot : nullptr, s);
 }
 
+// Host-side state of a plan for problem p (validated): layout, side type
+// flags, default launch shapes and options.  No device or host allocation.
+void plan_init_host(ccmg_plan *P, const ccmg_problem &p) {
+    P->p = p;
+    build_layout(p, P->lay);
+    P->singular = p.alpha == 0.0 && p.bc[0] != CCMG_BC_DIRICHLET && p.bc[1] != CCMG_BC_DIRICHLET &&
+                  p.bc[2] != CCMG_BC_DIRICHLET && p.bc[3] != CCMG_BC_DIRICHLET;
+    for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
+    P->shp_fused = shape_for(P->lay.lev[0].n);
+    P->shp_fused32 = shape_for(P->lay.lev[0].n);
+    P->n_bottom = 2;
+    P->tcycle = 0;
+    P->timer.on = false;
+    P->timer.used = 0;
+    P->opt_fused = true;
+    P->opt_fused_keep = 100.0;
+    P->opt_mixed_inner = 3;
+}
+
 // pitch >= n + 2, and the array holds fewer than 2^31 elements (the kernels
 // form row offsets in 32 bits)
 int check_pitch(const ccmg_plan *P, int level, ptrdiff_t pitch) {
@@ -828,25 +864,19 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     if (st != CCMG_OK) return st;
     ccmg_plan *P = new (std::nothrow) ccmg_plan();
     if (!P) return CCMG_EINVAL;
-    P->p = *p;
-    build_layout(*p, P->lay);
+    plan_init_host(P, *p);
     if (!d_ws || ws_bytes < P->lay.total || (reinterpret_cast<uintptr_t>(d_ws) & 255)) {
         delete P;
         return CCMG_EWORKSPACE;
     }
     P->ws = static_cast<char *>(d_ws);
     P->stream = static_cast<hipStream_t>(stream);
-    P->singular = p->alpha == 0.0 && p->bc[0] != CCMG_BC_DIRICHLET && p->bc[1] != CCMG_BC_DIRICHLET &&
-                  p->bc[2] != CCMG_BC_DIRICHLET && p->bc[3] != CCMG_BC_DIRICHLET;
-    for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
             P->simds = 4 * ncu;
     }
-    P->shp_fused = shape_for(P->lay.lev[0].n);
-    P->shp_fused32 = shape_for(P->lay.lev[0].n);
     hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&P->hpin), sizeof(double) * (CCMG_HISTORY + kScal),
                                  hipHostMallocDefault);
     if (e == hipSuccess)
@@ -1510,6 +1540,32 @@ int ccmg_vcycle(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch)
     if (e == hipSuccess) e = copy_valid(d_phi, pitch, st.q, st.pq, P->lay.lev[0].n, P->stream);
     return hip_status(e);
 }
+
+// One V-cycle without a plan or workspace: the levels below the finest live in
+// the library's static device scratch (one copy per device, see
+// noalloc.hip).  The host side of the plan is a per-device static object, so
+// nothing is allocated, on the device or the host.
+int ccmg_vcycle_noalloc(const ccmg_problem *p, const double *d_f, double *d_phi, ptrdiff_t pitch, void *stream) {
+    const int st = ccmg_problem_check(p);
+    if (st != CCMG_OK) return st;
+    if (!d_f || !d_phi || p->prec != CCMG_FP64) return CCMG_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CCMG_EHIP;
+    if (dev < 0 || dev >= kNoallocDevices) return CCMG_EINVAL;
+    void *scratch = nullptr;
+    size_t cap = 0;
+    if (static_scratch(dev, &scratch, &cap) != hipSuccess) return CCMG_EHIP;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+    ccmg_plan *P = &g_noalloc_plan[dev];
+    plan_init_host(P, *p);
+    if (P->lay.total > cap) return CCMG_EWORKSPACE;
+    P->ws = static_cast<char *>(scratch);
+    P->stream = static_cast<hipStream_t>(stream);
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    return hip_status(enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, false, nullptr, false, 0));
+}
+
+size_t ccmg_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 
 }  // extern "C"
 
