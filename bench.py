@@ -535,17 +535,19 @@ def cpu_single_thread(fv, n, bc):
 def stream_probe(cc, torch, n):
     """What this device's memory delivers for the fused launch's compulsory
     pattern: c = a + b over three FP64 arrays of n^2 values (the library's
-    streaming probe, HIP events over 20 launches)."""
+    streaming probe: the fastest of its launch shapes, ordinary or
+    nontemporal accesses, HIP events over 20 launches each)."""
     a = torch.full((n * n,), 1.0, dtype=torch.float64, device="cuda")
     b = torch.full_like(a, 2.0)
     c = torch.empty_like(a)
-    ms = cc.ccmg_probe_stream(a, b, c, reps=20)
+    ms, cfg = cc.ccmg_probe_stream(a, b, c, reps=20)
     assert float(c[-1]) == 3.0
     gbs = 3 * 8 * n * n / (ms * 1e-3) / 1e9
     del a, b, c
     torch.cuda.empty_cache()
     return dict(n=n, bytes_per_launch=3 * 8 * n * n, ms=round(ms, 5), gbs=round(gbs, 1),
-                frac_of_peak=round(gbs / HBM_PEAK_GBS, 4))
+                frac_of_peak=round(gbs / HBM_PEAK_GBS, 4), workgroups_per_cu=cfg % 1000,
+                nontemporal=cfg >= 1000)
 
 
 def main():

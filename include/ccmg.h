@@ -433,13 +433,16 @@ int ccmg_plan_kernel_stats(ccmg_plan *plan, ccmg_kernel_stat *out, int max, int 
 
 /* Streaming probe (diagnostics): d_c = d_a + d_b over `count` doubles, each
  * array read or written once -- the access pattern of a launch that reads two
- * arrays and writes one -- timed with HIP events on `stream` over `reps`
- * launches after one untimed launch; *ms receives the mean time per launch.
- * It states what the device's memory system delivers for that pattern, beside
- * the nameplate bandwidth.  count even, arrays 16-byte aligned and not
- * overlapping, else CCMG_EINVAL.  Blocks until done. */
+ * arrays and writes one -- in several launch shapes (2, 4, 8, 32 and 128
+ * workgroups of 256 threads per compute unit, 16-byte accesses, ordinary and
+ * nontemporal), each timed with HIP events on `stream` over `reps` launches
+ * after one untimed launch.  *ms receives the fastest mean time per launch,
+ * *config (may be NULL) its shape: workgroups per compute unit, plus 1000 if
+ * nontemporal.  It states what the device's memory system delivers for that
+ * pattern, beside the nameplate bandwidth.  count even, arrays 16-byte aligned
+ * and not overlapping, else CCMG_EINVAL.  Blocks until done. */
 int ccmg_probe_stream(const double *d_a, const double *d_b, double *d_c, size_t count, int reps, void *stream,
-                      float *ms);
+                      float *ms, int *config);
 
 #ifdef __cplusplus
 }

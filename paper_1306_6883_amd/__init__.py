@@ -129,7 +129,7 @@ def lib():
         L.ccmg_net_encode.argtypes = [vp, dp, pd, i, dp, pd, vp]
         L.ccmg_net_guess.argtypes = [vp, dp, pd, i, ctypes.c_double, i, dp, pd]
         L.ccmg_solve_learned.argtypes = [vp, vp, dp, dp, pd, i, ctypes.POINTER(ccmg_result), ip]
-        L.ccmg_probe_stream.argtypes = [dp, dp, dp, sz, i, vp, fp]
+        L.ccmg_probe_stream.argtypes = [dp, dp, dp, sz, i, vp, fp, ctypes.POINTER(ctypes.c_int)]
         L.ccmg_plan_set_option.argtypes = [vp, i, ctypes.c_double]
         L.ccmg_plan_get_option.argtypes = [vp, i, ctypes.POINTER(ctypes.c_double)]
         L.ccmg_batch_set_option.argtypes = [vp, i, ctypes.c_double]
@@ -484,18 +484,20 @@ def ccmg_plan_kernel_stats(plan: Plan) -> list:
             for k in range(cnt.value)]
 
 
-def ccmg_probe_stream(a, b, c, reps: int = 20) -> float:
+def ccmg_probe_stream(a, b, c, reps: int = 20):
     """c = a + b over the elements of three float64 CUDA tensors of equal size
-    (the library's streaming probe); returns the mean ms per launch."""
+    (the library's streaming probe, fastest of its launch shapes); returns
+    (mean ms per launch, shape: workgroups per compute unit, + 1000 if
+    nontemporal)."""
     for t in (a, b, c):
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
             raise ValueError("ccmg_probe_stream: contiguous float64 CUDA tensors")
     if not (a.numel() == b.numel() == c.numel()):
         raise ValueError("ccmg_probe_stream: tensors of one size")
-    ms = ctypes.c_float()
+    ms, cfg = ctypes.c_float(), ctypes.c_int()
     _check(lib().ccmg_probe_stream(a.data_ptr(), b.data_ptr(), c.data_ptr(), a.numel(), reps, _stream_handle(),
-                                   ctypes.byref(ms)), "ccmg_probe_stream")
-    return ms.value
+                                   ctypes.byref(ms), ctypes.byref(cfg)), "ccmg_probe_stream")
+    return ms.value, cfg.value
 
 
 class Batch:

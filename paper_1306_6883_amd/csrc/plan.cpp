@@ -1335,28 +1335,56 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     return CCMG_OK;
 }
 
+}  // extern "C"
+
+namespace ccmg {
+// c = a + b over `count` doubles (even count, 16-byte aligned): the streaming
+// probe with `blocks` workgroups of 256 threads, nontemporal accesses if nt
+// (util.hip).
+hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, bool nt,
+                               hipStream_t s);
+}  // namespace ccmg
+
+extern "C" {
+
 int ccmg_probe_stream(const double *d_a, const double *d_b, double *d_c, size_t count, int reps, void *stream,
-                      float *ms) {
+                      float *ms, int *config) {
     if (!d_a || !d_b || !d_c || !ms || reps < 1 || count == 0 || (count & 1) ||
         ((reinterpret_cast<uintptr_t>(d_a) | reinterpret_cast<uintptr_t>(d_b) | reinterpret_cast<uintptr_t>(d_c)) & 15))
         return CCMG_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int blocks = 8 * cus;  // eight 256-thread workgroups per compute unit
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CCMG_EHIP;
-    hipError_t e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, s);  // warm-up
-    if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float t = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    // workgroups per compute unit x {ordinary, nontemporal}: keep the fastest
+    static const int kPerCu[] = {2, 4, 8, 32, 128};
+    float best = 0.f;
+    int best_cfg = 0;
+    hipError_t e = hipSuccess;
+    for (int nt = 0; nt < 2 && e == hipSuccess; ++nt)
+        for (int w : kPerCu) {
+            const int blocks = w * cus;
+            e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, nt != 0, s);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = launch_probe_stream(d_a, d_b, d_c, (long)count, blocks, nt != 0, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) break;
+            t /= (float)reps;
+            if (best == 0.f || t < best) {
+                best = t;
+                best_cfg = 1000 * nt + w;
+            }
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (e != hipSuccess) return CCMG_EHIP;
-    *ms = t / (float)reps;
+    *ms = best;
+    if (config) *config = best_cfg;
     return CCMG_OK;
 }
 

@@ -194,31 +194,35 @@ namespace ccmg {
 
 // Streaming probe: c = a + b over `count` doubles (count even, 16-byte
 // aligned arrays), the access pattern of a launch that reads two arrays and
-// writes one.  Each thread moves four 16-byte pairs per step, all loads issued
-// before the first add.
-__global__ __launch_bounds__(256) void k_probe_stream(const double2 *__restrict__ a, const double2 *__restrict__ b,
-                                                      double2 *__restrict__ c, long pairs) {
+// writes one.  Grid-stride over 16-byte pairs; NT: nontemporal loads and
+// stores (streaming hints), else ordinary ones.
+typedef double probe_v2 __attribute__((ext_vector_type(2)));
+hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, bool nt,
+                               hipStream_t s);
+template <bool NT>
+__global__ __launch_bounds__(256) void k_probe_stream(const probe_v2 *__restrict__ a, const probe_v2 *__restrict__ b,
+                                                      probe_v2 *__restrict__ c, long pairs) {
     const long stride = (long)gridDim.x * blockDim.x;
-    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < pairs; i += 4 * stride) {
-        double2 x[4], y[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            x[k] = a[i + k * stride];
-            y[k] = b[i + k * stride];
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < pairs; i += stride) {
+        if constexpr (NT) {
+            const probe_v2 x = __builtin_nontemporal_load(a + i), y = __builtin_nontemporal_load(b + i);
+            __builtin_nontemporal_store(x + y, c + i);
+        } else {
+            c[i] = a[i] + b[i];
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[i + k * stride] = make_double2(x[k].x + y[k].x, x[k].y + y[k].y);
-    }
-    for (; i < pairs; i += stride) {
-        const double2 x = a[i], y = b[i];
-        c[i] = make_double2(x.x + y.x, x.y + y.y);
     }
 }
 
 hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_probe_stream, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2 *>(a),
-                       reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(c), count / 2);
+    return launch_probe_stream(a, b, c, count, blocks, false, s);
+}
+
+hipError_t launch_probe_stream(const double *a, const double *b, double *c, long count, int blocks, bool nt,
+                               hipStream_t s) {
+    const probe_v2 *pa = reinterpret_cast<const probe_v2 *>(a), *pb = reinterpret_cast<const probe_v2 *>(b);
+    probe_v2 *pc = reinterpret_cast<probe_v2 *>(c);
+    if (nt) hipLaunchKernelGGL(k_probe_stream<true>, dim3(blocks), dim3(256), 0, s, pa, pb, pc, count / 2);
+    else hipLaunchKernelGGL(k_probe_stream<false>, dim3(blocks), dim3(256), 0, s, pa, pb, pc, count / 2);
     return hipGetLastError();
 }
 
