@@ -562,6 +562,7 @@ def main():
                     help="run only the learned-guess leg and print its result (profiling aid)")
     ap.add_argument("--learned-solves", type=int, default=20000, help="training solves of the learned leg")
     ap.add_argument("--learned-steps", type=int, default=30000, help="training steps of the learned leg")
+    ap.add_argument("--learned-eval", type=int, default=256, help="held-out seeds the learned leg evaluates on")
     ap.add_argument("--next-rows-only", action="store_true",
                     help="only the Crank-Nicolson, side-data and projection legs (one JSON line of their own)")
     ap.add_argument("--fused-shape", type=str, default=None,
@@ -579,19 +580,6 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    if args.learned_only:
-        print(json.dumps({"learned": learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)}),
-              flush=True)
-        return
-    if args.next_rows_only:
-        print(json.dumps({"cn_diffusion": cn_diffusion(cc, torch, 10), "side_data": side_data_solves(cc, torch, W, 5),
-                          "projection": projection(cc, torch, 5), "bottom_solver": bottom_solver(cc, torch, W, 20)}),
-              flush=True)
-        return
-    n = 8192
-    log("generating inputs")
-    f_head = W.fourier_modes(n, seed=0, count=64, kmax=32)
-
     if args.probe_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -601,6 +589,19 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 1 GiB read + 1 GiB written")
         del a, b
+
+    if args.learned_only:
+        print(json.dumps({"learned": learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps,
+                                                      args.learned_eval)}), flush=True)
+        return
+    if args.next_rows_only:
+        print(json.dumps({"cn_diffusion": cn_diffusion(cc, torch, 10), "side_data": side_data_solves(cc, torch, W, 5),
+                          "projection": projection(cc, torch, 5), "bottom_solver": bottom_solver(cc, torch, W, 20)}),
+              flush=True)
+        return
+    n = 8192
+    log("generating inputs")
+    f_head = W.fourier_modes(n, seed=0, count=64, kmax=32)
 
     log(f"{n}^2 Dirichlet: {args.warmup} warmup + {args.steps} timed solves")
     fshape = tuple(int(x) for x in args.fused_shape.split(",")) if args.fused_shape else None
@@ -636,7 +637,8 @@ def main():
         also["projection"] = projection(cc, torch, 5)
         also["bottom_solver"] = bottom_solver(cc, torch, W, 20)
         if not args.no_learned:
-            also["learned"] = learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps)
+            also["learned"] = learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps,
+                                               args.learned_eval)
 
     cpu = None
     if not args.no_cpu:

@@ -38,6 +38,14 @@ __device__ __forceinline__ int tap_dx(int t, int d) { return (t % 3 - 1) * d; }
 
 __device__ __forceinline__ bf16x8 load8(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
 
+// Workgroups are dealt to the 8 XCDs round robin; when the grid divides by 8,
+// give each XCD a contiguous run of workgroup indices instead, so that the
+// rows one XCD's waves read for their (dilated) taps stay in its L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
 }  // namespace
 
 // out[b][y][x][co] = sum_{tap, ci} w[co][tap][ci] * in[b][y + dy][x + dx][ci]
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(256) void k_conv32(const __bf16 *__restrict__ in, c
                                                 int dil) {
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wave = SPLIT == 1 ? blockIdx.x * 4 + wib : blockIdx.x;
+    const int wave = SPLIT == 1 ? xcd_block() * 4 + wib : xcd_block();
     const int tiles_per_row = kNetG / 32;
     if (wave >= nb * kNetG * tiles_per_row) return;  // uniform over the workgroup when SPLIT > 1
     const int b = wave / (kNetG * tiles_per_row);
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(256) void k_conv32_wgrad(const __bf16 *__restrict__
     __shared__ __attribute__((aligned(16))) __bf16 lds[4][4][kNetC][16];
     const int lane = threadIdx.x & 63;
     const int wl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wave = blockIdx.x * 4 + wl;
+    const int wave = xcd_block() * 4 + wl;
     const int nchunks = (npix + chunk - 1) / chunk;
     if (wave >= 3 * nchunks) return;
     const int ck = wave / 3, trow = wave - 3 * ck;  // pixel chunk, tap row (taps 3 trow .. 3 trow + 2)
