@@ -347,6 +347,16 @@ int ccmg_net_destroy(ccmg_net *net);
 /* Load parameters (device FP32); resets the optimiser state. */
 int ccmg_net_set_params(ccmg_net *net, const float *d_params);
 int ccmg_net_get_params(ccmg_net *net, float *d_params);
+/* Training state, for checkpoints: ccmg_net_state_count() FP32 values -- the
+ * parameters, then Adam's first and second moments, each in parameter order
+ * (3 x ccmg_net_param_count()) -- and Adam's step counter (its bias
+ * corrections depend on it).  get copies the state to the device array
+ * d_state (asynchronous on the net's stream) and *step (host); set restores
+ * both, so that the next ccmg_net_train_step continues exactly where the
+ * saved net stopped. */
+int ccmg_net_state_count(void);
+int ccmg_net_get_state(ccmg_net *net, float *d_state, int *step);
+int ccmg_net_set_state(ccmg_net *net, const float *d_state, int step);
 /* y = net(x) for nb samples (the network is not in the paper: it only
  * supplies the starting iterate of a Sec. 3.3 solve). */
 int ccmg_net_forward(ccmg_net *net, const float *d_x, float *d_y, int nb);

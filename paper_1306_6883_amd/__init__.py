@@ -122,6 +122,9 @@ def lib():
         L.ccmg_net_create.argtypes = [i, i, vp, sz, vp, ctypes.POINTER(vp)]
         L.ccmg_net_destroy.argtypes = [vp]
         L.ccmg_net_set_params.argtypes = [vp, vp]
+        L.ccmg_net_state_count.argtypes = []
+        L.ccmg_net_get_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
+        L.ccmg_net_set_state.argtypes = [vp, vp, i]
         L.ccmg_net_get_params.argtypes = [vp, vp]
         L.ccmg_net_forward.argtypes = [vp, vp, vp, i]
         L.ccmg_net_loss_grad.argtypes = [vp, vp, vp, i, vp, fp]
@@ -635,6 +638,26 @@ def ccmg_net_get_params(net: Net) -> torch.Tensor:
     out = torch.empty(ccmg_net_param_count(), dtype=torch.float32, device=net.device)
     _check(lib().ccmg_net_get_params(net.handle, out.data_ptr()), "ccmg_net_get_params")
     return out
+
+
+def ccmg_net_state_count() -> int:
+    return lib().ccmg_net_state_count()
+
+
+def ccmg_net_get_state(net: Net):
+    """(state, step): parameters and Adam moments as one FP32 device tensor,
+    and Adam's step counter."""
+    out = torch.empty(ccmg_net_state_count(), dtype=torch.float32, device=net.device)
+    step = ctypes.c_int()
+    _check(lib().ccmg_net_get_state(net.handle, out.data_ptr(), ctypes.byref(step)), "ccmg_net_get_state")
+    return out, step.value
+
+
+def ccmg_net_set_state(net: Net, state: torch.Tensor, step: int) -> None:
+    if state.dtype != torch.float32 or not state.is_cuda or not state.is_contiguous() or \
+            state.numel() != ccmg_net_state_count():
+        raise ValueError("ccmg_net_set_state: a contiguous float32 CUDA tensor of ccmg_net_state_count() values")
+    _check(lib().ccmg_net_set_state(net.handle, state.data_ptr(), int(step)), "ccmg_net_set_state")
 
 
 def ccmg_net_forward(net: Net, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:

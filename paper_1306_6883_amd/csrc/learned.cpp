@@ -223,6 +223,31 @@ int ccmg_net_set_params(ccmg_net *N, const float *d_params) {
     return hs(e);
 }
 
+int ccmg_net_state_count(void) { return 3 * kNetParams; }
+
+int ccmg_net_get_state(ccmg_net *N, float *d_state, int *step) {
+    if (!N || !d_state || !step) return CCMG_EINVAL;
+    const size_t b = sizeof(float) * kNetParams;
+    hipError_t e = hipMemcpyAsync(d_state, N->w(), b, hipMemcpyDeviceToDevice, N->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_state + kNetParams, N->at<float>(N->L.m), b, hipMemcpyDeviceToDevice, N->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_state + 2 * kNetParams, N->at<float>(N->L.v), b, hipMemcpyDeviceToDevice, N->stream);
+    *step = N->step;
+    return hs(e);
+}
+
+int ccmg_net_set_state(ccmg_net *N, const float *d_state, int step) {
+    if (!N || !d_state || step < 0) return CCMG_EINVAL;
+    const size_t b = sizeof(float) * kNetParams;
+    hipError_t e = hipMemcpyAsync(N->w(), d_state, b, hipMemcpyDeviceToDevice, N->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(N->at<float>(N->L.m), d_state + kNetParams, b, hipMemcpyDeviceToDevice, N->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(N->at<float>(N->L.v), d_state + 2 * kNetParams, b, hipMemcpyDeviceToDevice, N->stream);
+    if (e == hipSuccess) e = refresh_bf16(N);
+    if (e == hipSuccess) N->step = step;
+    return hs(e);
+}
+
 int ccmg_net_get_params(ccmg_net *N, float *d_params) {
     if (!N || !d_params) return CCMG_EINVAL;
     return hs(hipMemcpyAsync(d_params, N->w(), sizeof(float) * kNetParams, hipMemcpyDeviceToDevice, N->stream));

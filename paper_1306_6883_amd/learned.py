@@ -23,7 +23,8 @@ import torch
 import workloads as W
 
 from . import (NET_G, OK, Net, Plan, Problem, ccmg_net_encode, ccmg_net_forward, ccmg_net_get_params,
-               ccmg_net_guess, ccmg_net_param_count, ccmg_net_set_params, ccmg_net_train_step,
+               ccmg_net_get_state, ccmg_net_guess, ccmg_net_param_count, ccmg_net_set_params, ccmg_net_set_state,
+               ccmg_net_train_step,
                ccmg_plan_autotune, ccmg_prolong_add, ccmg_restrict, ccmg_solve, ccmg_solve_learned, ccmg_vcycle,
                field)
 
@@ -92,23 +93,33 @@ def make_dataset(net: Net, n: int, seeds, chunk: int = 64, plan: Plan | None = N
 
 
 def train(net: Net, data: Dataset, steps: int, batch: int = 32, lr: float = 1e-3, lr_final: float = 1e-5,
-          warmup: int = 100, seed: int = 0, log=None, log_every: int = 250):
-    """Adam with a linear warm-up then a cosine decay; minibatches drawn without
-    replacement each epoch.  Returns the loss history [(step, loss)]."""
+          warmup: int = 100, seed: int = 0, log=None, log_every: int = 250, start: int = 0,
+          stop: int | None = None, checkpoint: str | None = None, checkpoint_every: int = 0):
+    """Adam with a linear warm-up then a cosine decay over `steps` steps;
+    minibatches drawn without replacement, a fresh permutation per epoch
+    (seeded by the epoch).  Runs steps start .. stop - 1 of that schedule
+    (stop defaults to steps): a net restored with load_checkpoint at step
+    `start` continues exactly as an uninterrupted run would.  With
+    `checkpoint`, the state is saved there every `checkpoint_every` steps and
+    at the end.  Returns the loss history [(step, loss)]."""
     S = data.x.shape[0]
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    perm = torch.randperm(S, generator=g)
-    pos = 0
+    per_epoch = S // batch
+    if per_epoch < 1:
+        raise ValueError("fewer training samples than one batch")
     hist = []
     xb = torch.empty((batch, NET_G, NET_G), dtype=torch.float32, device=net.device)
     tb = torch.empty_like(xb)
     t0 = time.time()
-    for k in range(steps):
-        if pos + batch > S:
+    perm, epoch = None, -1
+    stop = steps if stop is None else stop
+    for k in range(start, stop):
+        e = k // per_epoch
+        if e != epoch:
+            epoch = e
+            g = torch.Generator(device="cpu").manual_seed(seed * 1000003 + epoch)
             perm = torch.randperm(S, generator=g)
-            pos = 0
+        pos = (k % per_epoch) * batch
         idx = perm[pos:pos + batch].to(net.device)
-        pos += batch
         torch.index_select(data.x, 0, idx, out=xb)
         torch.index_select(data.t, 0, idx, out=tb)
         if k < warmup:
@@ -116,14 +127,39 @@ def train(net: Net, data: Dataset, steps: int, batch: int = 32, lr: float = 1e-3
         else:
             u = (k - warmup) / max(1, steps - warmup)
             rate = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * u))
-        want = (k % log_every == 0) or k == steps - 1
+        want = (k % log_every == 0) or k == stop - 1
         loss = ccmg_net_train_step(net, xb, tb, rate, want_loss=want)
         if want:
             hist.append((k, loss))
             if log:
                 log(f"step {k} loss {loss:.4e} lr {rate:.2e} ({time.time() - t0:.1f} s)")
+        if checkpoint and checkpoint_every and (k + 1) % checkpoint_every == 0:
+            save_checkpoint(net, checkpoint)
+    if checkpoint:
+        save_checkpoint(net, checkpoint)
     torch.cuda.synchronize(net.device)
     return hist
+
+
+def save_checkpoint(net: Net, path: str) -> None:
+    """Parameters, Adam moments and step counter to an .npz file (plain
+    arrays, no pickled objects)."""
+    state, step = ccmg_net_get_state(net)
+    torch.cuda.synchronize(net.device)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, state=state.cpu().numpy(), step=np.array([step], dtype=np.int64))
+    import os
+    os.replace(tmp, path)
+
+
+def load_checkpoint(net: Net, path: str) -> int:
+    """Restore a state saved by save_checkpoint; returns its step counter."""
+    with np.load(path, allow_pickle=False) as z:
+        state = torch.as_tensor(z["state"], dtype=torch.float32).to(net.device).contiguous()
+        step = int(z["step"][0])
+    ccmg_net_set_state(net, state, step)
+    torch.cuda.synchronize(net.device)
+    return step
 
 
 def target_error(net: Net, data: Dataset, batch: int | None = None) -> float:

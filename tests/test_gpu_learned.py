@@ -256,3 +256,28 @@ def test_trained_network_gains_over_zero_guess(M):
     assert len(g.cycles["learned"]) == 256
     assert np.mean(g.cycles["learned"]) <= np.mean(g.cycles["zero"]) - 1
     assert np.mean(g.cycles["decoder_only"]) <= np.mean(g.cycles["zero"])
+
+
+def test_checkpoint_resume_continues_exactly(M, tmp_path):
+    """Training stopped at step 17 of a 40-step schedule, checkpointed
+    (parameters, Adam moments, step counter) and resumed in a fresh net ends
+    with the same parameters, bit for bit, as an uninterrupted run."""
+    from paper_1306_6883_amd import learned as L
+    n = 256
+    plan = M.Plan(L.periodic_poisson(n))
+    a = L.new_net(batch=8, n_max=n, seed=1)
+    data = L.make_dataset(a, n, range(48), plan=plan)
+    L.train(a, data, steps=40, batch=8, warmup=10)
+    b = L.new_net(batch=8, n_max=n, seed=1)
+    path = str(tmp_path / "net.npz")
+    L.train(b, data, steps=40, batch=8, warmup=10, stop=17, checkpoint=path)
+    c = L.new_net(batch=8, n_max=n, seed=5)  # other weights: all of them come from the checkpoint
+    assert L.load_checkpoint(c, path) == 17
+    L.train(c, data, steps=40, batch=8, warmup=10, start=17)
+    pa, pc = M.ccmg_net_get_params(a), M.ccmg_net_get_params(c)
+    assert torch.equal(pa, pc)
+    sa, ka = M.ccmg_net_get_state(a)
+    sc, kc = M.ccmg_net_get_state(c)
+    assert ka == kc == 40 and torch.equal(sa, sc)
+    with pytest.raises(ValueError):
+        M.ccmg_net_set_state(c, sa[:10].contiguous(), 3)
