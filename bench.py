@@ -568,6 +568,8 @@ def main():
     ap.add_argument("--fused-shape", type=str, default=None,
                     help="TY,WPB: rows per band and waves per workgroup of the headline's fused launch, "
                          "instead of the autotuner's choice (for counter runs)")
+    ap.add_argument("--workload", choices=("dirichlet8192", "periodic4096"), default="dirichlet8192",
+                    help="the measured workload of a --quick run (counter runs of the 4096^2 line)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -599,13 +601,16 @@ def main():
                           "projection": projection(cc, torch, 5), "bottom_solver": bottom_solver(cc, torch, W, 20)}),
               flush=True)
         return
-    n = 8192
+    if args.workload == "periodic4096" and not args.quick:
+        print(json.dumps({"error": "--workload periodic4096 is for --quick counter runs"}))
+        sys.exit(2)
+    n, side = (8192, "D") if args.workload == "dirichlet8192" else (4096, "P")
     log("generating inputs")
     f_head = W.fourier_modes(n, seed=0, count=64, kmax=32)
 
-    log(f"{n}^2 Dirichlet: {args.warmup} warmup + {args.steps} timed solves")
+    log(f"{n}^2 {'Dirichlet' if side == 'D' else 'periodic'}: {args.warmup} warmup + {args.steps} timed solves")
     fshape = tuple(int(x) for x in args.fused_shape.split(",")) if args.fused_shape else None
-    m = measure(cc, torch, n, "D", f_head, args.steps, args.warmup, fused_shape=fshape)
+    m = measure(cc, torch, n, side, f_head, args.steps, args.warmup, fused_shape=fshape)
     log(f"{m['ms_per_solve']:.3f} ms/solve, {m['cycles_per_solve']:.1f} cycles, "
         f"{m['pts_cycles_per_s'] / 1e9:.2f} G pts*cycles/s")
     rl = roofline_of(m)
@@ -663,10 +668,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 V(2,2) Poisson 8192^2 homogeneous Dirichlet, 64 Fourier modes |k|<=32, "
+        "config": {"workload": f"plain FP64 V(2,2) Poisson {n}^2 "
+                               f"{'homogeneous Dirichlet' if side == 'D' else 'periodic'}, 64 Fourier modes |k|<=32, "
                                "seed 0, to relative residual 1e-10",
-                   "n": n, "bc": "Dirichlet", "rtol": 1e-10, "cycles_per_solve": m["cycles_per_solve"],
-                   "time_to_tol_ms": m["ms_per_solve"]},
+                   "n": n, "bc": "Dirichlet" if side == "D" else "periodic", "rtol": 1e-10,
+                   "cycles_per_solve": m["cycles_per_solve"], "time_to_tol_ms": m["ms_per_solve"]},
         "roofline": {k: rl[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "traffic_gbs", "traffic_frac",
                                                         "all_kernels")},
