@@ -177,6 +177,8 @@ void set_tiles(MarchArgs<T> &a, int outw, int ty) {
     a.strips = (a.n + a.outw - 1) / a.outw;
     a.chunks = (a.n + a.ty - 1) / a.ty;
     a.ntiles = a.strips * a.chunks;
+    a.ety = a.ty;
+    a.echunks = 0;  // work lists keep one band height for every strip
     a.groups_per_xcd = 0;
 }
 

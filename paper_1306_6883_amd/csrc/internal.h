@@ -49,6 +49,10 @@ struct MarchArgs {
     T cc, invd;          // relaxation: phi = (f + cc * sum of neighbours) * invd
     T alpha, beta, ih2;  // residual: r = f - (alpha phi - beta ih2 * lap)
     int strips, chunks, ty, outw, ntiles, groups_per_xcd;
+    // Edge strips (x sides Dirichlet or Neumann): the first and last strip run
+    // bands of ety rows (echunks of them, after the (strips - 2) * chunks
+    // interior tiles); echunks = 0: every strip runs bands of ty rows.
+    int ety, echunks;
     // mixed precision (POST_IR / POST_R32)
     const double *q_in;  // FP64 iterate, read (POST_IR)
     int pq_in;
@@ -82,6 +86,13 @@ constexpr int march_halo_x(int nu, bool prolong, bool post) {
     return (2 * nu + (post ? 1 : 0) + (prolong ? 2 : 0) + 1) & ~1;
 }
 constexpr int march_outw(int nu, bool prolong, bool post) { return 128 - 2 * march_halo_x(nu, prolong, post); }
+
+// A tile on a Dirichlet or Neumann x side applies the ghost rule in every
+// stage (about a quarter more instructions per row), so with one wave per band
+// it would finish last: bands of at least kEdgeSplitMinTy rows are halved in
+// the two edge strips.
+constexpr int kEdgeSplitMinTy = 64;
+constexpr int edge_band_rows(int ty) { return ((ty / 2) + 1) & ~1; }
 
 // Launch description chosen by the host for one level.
 struct MarchShape {

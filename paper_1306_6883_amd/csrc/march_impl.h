@@ -545,7 +545,21 @@ __device__ __forceinline__ void march_one(const MarchArgs<T> &a, const int tile)
     using C = Cfg<NU, PROLONG, POST>;
     const int lane = threadIdx.x & 63;
     if (a.skip && *a.skip) return;
-    const int strip = tile % a.strips, chunk = tile / a.strips;
+    // interior strips first (row-major: a band's strips are consecutive
+    // tiles), then the edge strips' shorter bands
+    const int reg = a.echunks ? a.strips - 2 : a.strips;
+    const int nreg = reg * a.chunks;
+    int strip, ya, yh;
+    if (tile < nreg) {
+        strip = (a.echunks ? 1 : 0) + tile % reg;
+        yh = a.ty;
+        ya = (tile / reg) * yh;
+    } else {
+        const int e = tile - nreg;
+        strip = (e & 1) ? a.strips - 1 : 0;
+        yh = a.ety;
+        ya = (e >> 1) * yh;
+    }
 
     Tile tl;
     tl.n = a.n;
@@ -567,8 +581,8 @@ __device__ __forceinline__ void march_one(const MarchArgs<T> &a, const int tile)
     tl.cwedge = !tl.px && tl.I == 0;
     tl.ceedge = !tl.px && tl.I == tl.nc - 1;
     // rows
-    tl.y0 = chunk * a.ty;
-    tl.y1 = min(tl.y0 + a.ty, tl.n);
+    tl.y0 = ya;
+    tl.y1 = min(ya + yh, tl.n);
     tl.ys = tl.py ? tl.y0 - C::HY : max(tl.y0 - C::HY, 0);
     tl.ye = tl.py ? tl.y1 + C::HY : min(tl.y1 + C::HY, tl.n);
 
@@ -623,6 +637,13 @@ static hipError_t go(const MarchArgs<T> &a0, MarchShape sh, hipStream_t s, int *
     a.strips = (a.n + a.outw - 1) / a.outw;
     a.chunks = (a.n + a.ty - 1) / a.ty;
     a.ntiles = a.strips * a.chunks;
+    a.ety = a.ty;
+    a.echunks = 0;
+    if (a.bc[CCMG_XLO] != CCMG_BC_PERIODIC && a.strips >= 3 && a.ty >= kEdgeSplitMinTy) {
+        a.ety = edge_band_rows(a.ty);
+        a.echunks = (a.n + a.ety - 1) / a.ety;
+        a.ntiles = (a.strips - 2) * a.chunks + 2 * a.echunks;
+    }
     if (nt) *nt = a.ntiles;
     const int wpb = sh.wpb;
     const int blocks = (a.ntiles + wpb - 1) / wpb;

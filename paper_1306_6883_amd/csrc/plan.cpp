@@ -44,7 +44,19 @@ bool pow2(int n) { return n >= 2 && (n & (n - 1)) == 0; }
 int max_tiles(int n) {
     const int strips = (n + kMinOutw - 1) / kMinOutw;
     const int chunks = (n + kMinTy - 1) / kMinTy;
-    return strips * chunks;
+    // plus the edge strips' halved bands (at least kEdgeSplitMinTy / 2 rows)
+    const int ety = kEdgeSplitMinTy / 2;
+    return strips * chunks + 2 * ((n + ety - 1) / ety);
+}
+
+// Tiles of a row-march launch of an n^2 level in bands of ty rows (as the
+// launcher cuts it: x-edge strips in halved bands when `xwalls`).
+int march_tiles(int n, int outw, int ty, bool xwalls) {
+    const int strips = (n + outw - 1) / outw;
+    const int chunks = (n + ty - 1) / ty;
+    if (!xwalls || strips < 3 || ty < kEdgeSplitMinTy) return strips * chunks;
+    const int ety = edge_band_rows(ty);
+    return (strips - 2) * chunks + 2 * ((n + ety - 1) / ety);
 }
 
 struct LevelLay {
@@ -904,16 +916,19 @@ namespace {
 // count leaves some SIMDs a whole band more to march than the rest (at
 // 4096^2 the fused launch takes 136 us with 1280 waves on 1024 SIMDs and
 // 116 us with 1000).
-std::vector<int> balanced_tys(int n, int outw, int simds, int kmax) {
+std::vector<int> balanced_tys(int n, int outw, int simds, int kmax, bool xwalls) {
     std::vector<int> out;
     const int strips = (n + outw - 1) / outw;
     for (int k = 1; k <= kmax; ++k) {
-        const int chunks = k * simds / strips;
-        if (chunks < 1) continue;
-        int ty = (n + chunks - 1) / chunks;
-        ty += ty & 1;
-        if (ty < kMinTy || ty >= n) continue;
-        if (std::find(out.begin(), out.end(), ty) == out.end()) out.push_back(ty);
+        // the most bands whose waves (edge strips' halved bands included) fit
+        for (int chunks = k * simds / strips; chunks >= 1; --chunks) {
+            int ty = (n + chunks - 1) / chunks;
+            ty += ty & 1;
+            if (ty >= n) break;
+            if (ty < kMinTy || march_tiles(n, outw, ty, xwalls) > k * simds) continue;
+            if (std::find(out.begin(), out.end(), ty) == out.end()) out.push_back(ty);
+            break;
+        }
     }
     return out;
 }
@@ -926,6 +941,7 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
     const Layout &lay = P->lay;
     hipStream_t s = P->stream;
     const bool f64 = sizeof(T) == sizeof(double);
+    const bool xwalls = P->p.bc[CCMG_XLO] != CCMG_BC_PERIODIC;  // edge strips run halved bands
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1008,7 +1024,7 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
                 if (ty > n) continue;
                 for (int wpb : wpbs) cands.push_back(MarchShape{ty < n ? ty : n, wpb});
             }
-            for (int ty : balanced_tys(n, march_outw(nu, prolong, post != POST_NONE), P->simds, 4))
+            for (int ty : balanced_tys(n, march_outw(nu, prolong, post != POST_NONE), P->simds, 4, xwalls))
                 cands.push_back(MarchShape{ty, 1});
             for (const MarchShape &sh : cands) {
                 {
@@ -1068,7 +1084,7 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             if (ty > n && ty != 16) continue;
             for (int wpb : {1, 2}) cands.push_back(MarchShape{ty < n ? ty : n, wpb});
         }
-        for (int ty : balanced_tys(n, march_outw(4, true, true), P->simds, 4)) cands.push_back(MarchShape{ty, 1});
+        for (int ty : balanced_tys(n, march_outw(4, true, true), P->simds, 4, xwalls)) cands.push_back(MarchShape{ty, 1});
         for (const MarchShape &sh : cands) {
             {
                 int nt;

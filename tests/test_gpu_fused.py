@@ -65,6 +65,31 @@ def test_fused_solve_matches_unfused(bc, n):
     assert 1 <= stats["finest_pre"]["launches"] <= 2
 
 
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_edge_strip_bands_leave_iterates_unchanged(n):
+    """With Dirichlet or Neumann x sides, bands of 64 rows or more are halved
+    in the two edge strips (their tiles apply the ghost rule in every stage).
+    That is only another cut of the level into tiles: the solve's iterates are
+    bitwise those of bands too short to be split, on every level and in the
+    fused launch (ragged last bands included: 2048 rows in bands of 342 and
+    edge bands of 172)."""
+    fv = W.fourier_modes(n, seed=6, count=16, kmax=8) + 0.2
+    outs = []
+    for ty_fused, ty_levels in ((16, (16, 8)), (342, (128, 256)), (128, (64, 96))):
+        plan = cc.Plan(cc.Problem(n=n, bc=("D", "N", "N", "D"), rtol=1e-10))
+        cc.ccmg_plan_set_shape(plan, 0, 2, ty_fused, 1)
+        for level in range(4):
+            cc.ccmg_plan_set_shape(plan, level, 0, ty_levels[0], 1)
+            cc.ccmg_plan_set_shape(plan, level, 1, ty_levels[1], 2)
+        phi = dev_field(oracle.field_zeros(n))
+        r = cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
+        assert r.status == cc.OK
+        outs.append((valid(phi), r.cycles))
+    for o, cyc in outs[1:]:
+        assert cyc == outs[0][1]
+        assert np.array_equal(o, outs[0][0])
+
+
 @pytest.mark.parametrize("bc", ["DDDD", "PPPP"])
 def test_fused_solve_with_guess_and_helmholtz(bc):
     n = 256
