@@ -112,6 +112,10 @@ struct Cfg {
     static constexpr int WC = W / 2;            // coarse-row window
     static constexpr int DC = WC - 3;           // coarse prefetch distance
     static constexpr int OUTW = march_outw(NU, PROLONG, POST != 0);  // output columns per tile
+    // Rows are stored as 16-byte aligned pairs (cells x0 - 1, x0 of lane x0),
+    // which needs the column on either side of the output to be correct too:
+    // true when the halo has a column to spare beyond the last stage.
+    static constexpr bool PAIRST = HX >= 2 * NU + (PROLONG ? 2 : 0) + 1;
     static_assert(D >= 1 && DC >= 0, "window too small");
 };
 
@@ -120,6 +124,7 @@ struct Tile {
     int n, nm, nc;
     int xo0, x0, xl, I, Il;   // output column start; lane columns; loads; coarse column
     bool px, py, wedge, eedge, cwedge, ceedge, outl;
+    bool st2;                 // aligned row store of cells x0 - 1, x0 (see march_tile)
     int y0, y1, ys, ye;       // output rows [y0, y1); march rows [ys, ye)
 };
 
@@ -138,6 +143,27 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     // wave-uniform values
     const unsigned nrows = (unsigned)(y1 - y0);
     auto inrow = [&](int y) { return (unsigned)(y - y0) < nrows; };
+    // Store one row of the tile, two values per lane (cells x0, x0 + 1), into
+    // row base `o` (element 1 + x holds cell x).  PAIRST variants re-pair the
+    // cells so that every lane writes cells x0 - 1 and x0 as one 16-byte
+    // aligned store (a misaligned one is split in two by the memory path):
+    // each tile writes its output columns and one correct column either side,
+    // which the neighbouring tile writes with the same bits; on a periodic x
+    // side that column is the ghost, written with its periodic image.  Tiles
+    // on a Dirichlet or Neumann x side keep to their own columns.  Call with
+    // the whole wavefront active (cross-lane move).
+    auto store_row = [&](auto *o, const auto v0, const auto v1) {
+        if constexpr (C::PAIRST && !XB) {
+            const auto vl = from_left(v1);
+            if (tl.st2) {
+                o[tl.x0] = vl;
+                o[tl.x0 + 1] = v0;
+            }
+        } else if (tl.outl) {
+            o[1 + tl.x0] = v0;
+            o[2 + tl.x0] = v1;
+        }
+    };
     const T sxl = a.bc[CCMG_XLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T sxh = a.bc[CCMG_XHI] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
     const T syl = a.bc[CCMG_YLO] == CCMG_BC_DIRICHLET ? T(-1) : T(1);
@@ -357,19 +383,17 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             s1 = syl * p1;
                         }
                     }
-                    if (inrow(y) && tl.outl) {
-                        const T ih2 = a.ih2;
-                        const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
-                        const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
-                        const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
-                        const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
-                        accN0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
-                        accN1 += (double)p0 + (double)p1;
-                        if (a.phi_mid) {
-                            T *o = a.phi_mid + row_off(y + 1, a.pmid);
-                            o[1 + tl.x0] = p0;
-                            o[2 + tl.x0] = p1;
+                    if (inrow(y)) {
+                        if (tl.outl) {
+                            const T ih2 = a.ih2;
+                            const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                            const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                            const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
+                            const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
+                            accN0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                            accN1 += (double)p0 + (double)p1;
                         }
+                        if (a.phi_mid) store_row(a.phi_mid + row_off(y + 1, a.pmid), p0, p1);
                     }
                     SA[sv] = p0;
                     SB[sv] = p1;
@@ -385,15 +409,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 if constexpr (IR) {
                     Q0[kk] += (double)P0[kk];
                     Q1[kk] += (double)P1[kk];
-                    if (inrow(y) && tl.outl) {
-                        double *o = a.q_out + row_off(y + 1, a.pq_out);
-                        o[1 + tl.x0] = Q0[kk];
-                        o[2 + tl.x0] = Q1[kk];
-                    }
-                } else if ((FUSED || a.phi_out) && inrow(y) && tl.outl) {  // the fused launch always stores
-                    T *o = a.phi_out + row_off(y + 1, a.pout);
-                    o[1 + tl.x0] = P0[kk];
-                    o[2 + tl.x0] = P1[kk];
+                    if (inrow(y)) store_row(a.q_out + row_off(y + 1, a.pq_out), Q0[kk], Q1[kk]);
+                } else if ((FUSED || a.phi_out) && inrow(y)) {  // the fused launch always stores
+                    store_row(a.phi_out + row_off(y + 1, a.pout), P0[kk], P1[kk]);
                 }
             }
             // 5. residual of the finished rows and what is made from it
@@ -426,11 +444,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const double lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
                     const double r0 = G0[kk] - (a.alpha64 * p0 - a.beta64 * lap0);
                     const double r1 = G1[kk] - (a.alpha64 * p1 - a.beta64 * lap1);
+                    const float q0 = (float)r0, q1 = (float)r1;
+                    store_row(a.r_out + row_off(y + 1, a.pr), q0, q1);
                     if (tl.outl) {
-                        const float q0 = (float)r0, q1 = (float)r1;
-                        float *o = a.r_out + row_off(y + 1, a.pr);
-                        o[1 + tl.x0] = q0;
-                        o[2 + tl.x0] = q1;
                         acc0 += r0 * r0 + r1 * r1;
                         acc1 += p0 + p1;
                         acc2 += (double)q0 + (double)q1;
@@ -482,11 +498,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             acc1 += (double)p0 + (double)p1;
                         }
                     } else if constexpr (POST == POST_R32) {
+                        const float q0 = (float)r0, q1 = (float)r1;
+                        store_row(a.r_out + row_off(y + 1, a.pr), q0, q1);
                         if (tl.outl) {
-                            const float q0 = (float)r0, q1 = (float)r1;
-                            float *o = a.r_out + row_off(y + 1, a.pr);
-                            o[1 + tl.x0] = q0;
-                            o[2 + tl.x0] = q1;
                             acc0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
                             acc1 += (double)p0 + (double)p1;
                             acc2 += (double)q0 + (double)q1;
@@ -576,6 +590,9 @@ __device__ __forceinline__ void march_one(const MarchArgs<T> &a, const int tile)
     tl.wedge = !tl.px && tl.x0 == 0;
     tl.eedge = !tl.px && tl.x0 + 1 == tl.nm;
     tl.outl = tl.x0 >= tl.xo0 && tl.x0 < tl.xo0 + a.outw && tl.x0 >= 0 && tl.x0 < tl.n;
+    // aligned row stores: columns [xo0 - 1, min(xo0 + outw, n)] (-1 and n:
+    // the ghosts of a periodic x side), i.e. lanes x0 in [xo0, min(xo0 + outw, n)]
+    tl.st2 = tl.x0 >= tl.xo0 && tl.x0 <= min(tl.xo0 + a.outw, tl.n);
     tl.I = tl.x0 >> 1;
     tl.Il = PROLONG ? (tl.px ? (tl.I & (tl.nc - 1)) : min(max(tl.I, 0), tl.nc - 1)) : 0;
     tl.cwedge = !tl.px && tl.I == 0;
