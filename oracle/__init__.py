@@ -85,6 +85,7 @@ def _load(path: str):
     lib.og_mean.argtypes = [ctypes.c_int, dp]
     lib.og_mean.restype = ctypes.c_double
     lib.og_vcycle.argtypes = [ctypes.POINTER(_Params), dp, dp]
+    lib.og_fmg.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.og_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
                              ctypes.POINTER(_Result)]
     lib.og_smooth_solve.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int,
@@ -222,6 +223,18 @@ def vcycle(p: Problem, phi: np.ndarray, f: np.ndarray) -> np.ndarray:
     st = _lib().og_vcycle(ctypes.byref(p._c()), _ptr(phi), _ptr(f))
     if st != OK:
         raise ValueError("oracle vcycle: bad problem")
+    return phi
+
+
+def fmg(p: Problem, f: np.ndarray, top_n: int = 2, ncyc_top: int = 1, ncyc: int = 1) -> np.ndarray:
+    """Full multigrid start (mg_oracle.c og_fmg): f restricted down to the
+    level of top_n cells per side, ncyc_top V-cycles there from zero, then per
+    finer level the prolongated coarse phi and ncyc V-cycles.  Returns the
+    finest phi (ghosts filled)."""
+    phi = field_zeros(p.n)
+    st = _lib().og_fmg(ctypes.byref(p._c()), _ptr(phi), _ptr(f), top_n, ncyc_top, ncyc)
+    if st != OK:
+        raise ValueError("oracle fmg: bad arguments")
     return phi
 
 

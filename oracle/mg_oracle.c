@@ -342,6 +342,49 @@ int og_solve(const og_params *p, double *phi, const double *f, int use_guess, og
     return status;
 }
 
+/* Full multigrid (FMG): a start for the V-cycles that the paper does not
+ * describe (its Sec. 3.3 cycles from a zero guess and leaves the coarse-grid
+ * solver open); this is the standard nested iteration of the multigrid
+ * literature (Brandt 1977; Briggs, Henson and McCormick, "A Multigrid
+ * Tutorial", 2nd ed., Ch. 3), assembled from the operators above.
+ *   1. f is restricted (four-cell mean) level by level down to the FMG's
+ *      coarsest level, the one of top_n cells per side; on a singular problem
+ *      each restricted f has its mean removed.
+ *   2. There phi starts at zero and gets ncyc_top V-cycles.
+ *   3. On each finer level, phi = P phi_coarse (the prolongation of Sec. 3.3
+ *      added to a zero field), then ncyc V-cycles against that level's f.
+ *      The V-cycles are those of og_vcycle, rooted at that level; a singular
+ *      problem gets the mean of phi removed after each, as og_solve does.
+ * The result is the finest phi with its ghosts filled. */
+int og_fmg(const og_params *p, double *phi, const double *f, int top_n, int ncyc_top, int ncyc) {
+    if (!valid_n(p->n) || !valid_n(top_n) || top_n > p->n || ncyc_top < 0 || ncyc < 0) return OG_EINVAL;
+    int singular = is_singular(p->alpha, p->bc);
+    double **P, **F, *r;
+    int L = alloc_levels(p, phi, f, &P, &F, &r);
+    int c = 0;
+    while ((p->n >> c) > top_n) ++c;
+    for (int l = 1; l <= c; ++l) {
+        og_restrict(p->n >> (l - 1), F[l - 1], F[l]);
+        if (singular) add_const(p->n >> l, F[l], -og_mean(p->n >> l, F[l]));
+    }
+    memset(P[c], 0, sizeof(double) * og_field_len(p->n >> c));
+    for (int k = 0; k < ncyc_top; ++k) {
+        vcycle(p, c, P, F, r, singular);
+        if (singular) add_const(p->n >> c, P[c], -og_mean(p->n >> c, P[c]));
+    }
+    for (int l = c - 1; l >= 0; --l) {
+        memset(P[l], 0, sizeof(double) * og_field_len(p->n >> l));
+        og_prolong_add(p->n >> (l + 1), p->bc, P[l + 1], P[l]);
+        for (int k = 0; k < ncyc; ++k) {
+            vcycle(p, l, P, F, r, singular);
+            if (singular) add_const(p->n >> l, P[l], -og_mean(p->n >> l, P[l]));
+        }
+    }
+    og_fill(p->n, p->bc, phi);
+    free_levels(L, P, F, r);
+    return OG_OK;
+}
+
 /* Relaxation alone (no coarse grids), the paper's first suggested exercise:
  * whole red-black iterations until the same stopping rule holds. */
 int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_iters,

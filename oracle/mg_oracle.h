@@ -52,6 +52,7 @@ double og_norm(int n, double h, const double *a);
 double og_mean(int n, const double *a);
 int og_vcycle(const og_params *p, double *phi, const double *f);
 int og_solve(const og_params *p, double *phi, const double *f, int use_guess, og_result *out);
+int og_fmg(const og_params *p, double *phi, const double *f, int top_n, int ncyc_top, int ncyc);
 int og_smooth_solve(const og_params *p, double *phi, const double *f, int max_iters,
                     og_result *out);
 void og_cn_rhs(int n, double h, double beta, const int bc[4], double *phi, double *f);

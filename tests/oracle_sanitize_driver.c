@@ -92,6 +92,14 @@ int main(void) {
                         const int s2 = og_solve(&q, phi, f, 0, &res);
                         check(s2 == OG_OK && res.rel_resid <= 1e-10, "solve_exact_bottom", n, bc);
                     }
+                    {  /* full multigrid start from 2^2 and from the middle level */
+                        double *g = field(n);
+                        const int s6 = og_fmg(&p, g, f, 2, 1, 1);
+                        check(s6 == OG_OK, "fmg", n, bc);
+                        const int s7 = og_fmg(&p, g, f, n > 4 ? n / 4 : n, 2, 2);
+                        check(s7 == OG_OK, "fmg_top", n, bc);
+                        free(g);
+                    }
                     if (n <= 16) {
                         double *g = field(n);
                         og_params q = p;

@@ -80,6 +80,7 @@ def _load_test_module(name, fname):
 
 
 X = _load_test_module("oracle_exact_pins", "test_oracle_exact.py")
+G = _load_test_module("oracle_fmg_pins", "test_oracle_fmg.py")
 R = _load_test_module("oracle_net_rounding_pins", "test_oracle_net_rounding.py")
 
 # name -> (text in mg_oracle.c, replacement); each text occurs exactly once
@@ -115,6 +116,16 @@ MUTANTS = {
                                    "for (int q = 0; q < m; ++q) row[q] += (q == k ? c : 0.0);"),
     "direct_back_substitution": ("s -= A[(size_t)k * w + q] * A[(size_t)q * w + m];",
                                  "s -= A[(size_t)k * w + q] * A[(size_t)k * w + m];"),
+    # FMG: each level starts from zero instead of the prolongated coarse phi
+    "fmg_skips_prolongation": ("og_prolong_add(p->n >> (l + 1), p->bc, P[l + 1], P[l]);\n        for (int k",
+                               "(void)0;\n        for (int k"),
+    # FMG: every level's f restricted from the finest array with the wrong size
+    "fmg_restricts_wrong_level": ("og_restrict(p->n >> (l - 1), F[l - 1], F[l]);",
+                                  "og_restrict(p->n >> (l - 1), F[0], F[l]);"),
+    # FMG: the coarse phi added to the finer level twice
+    "fmg_prolongation_doubled": ("og_prolong_add(p->n >> (l + 1), p->bc, P[l + 1], P[l]);\n        for (int k",
+                                 "og_prolong_add(p->n >> (l + 1), p->bc, P[l + 1], P[l]);\n"
+                                 "        og_prolong_add(p->n >> (l + 1), p->bc, P[l + 1], P[l]);\n        for (int k"),
 }
 # Not a mutant: dropping the removal of each restricted right-hand side's mean
 # (singular problems) changes the iterates only by rounding -- the residual of
@@ -143,6 +154,9 @@ BATTERY = [
     (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("DNPP", (1.0, 0.5 / 64), 8)),
     (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("PPPP", (0.0, -1.0), 4)),
     (Q.test_direct_bottom_on_the_top_level_is_the_dense_solution, ("NDDN", (0.0, -1.0), 8)),
+    (G.test_fmg_reaches_discretization_accuracy, (64,)),
+    (G.test_fmg_with_many_cycles_is_the_discrete_solution, ("NDDN", (0.0, -1.0))),
+    (G.test_fmg_is_linear_in_f, ()),
 ]
 
 
