@@ -134,6 +134,22 @@ int ccmg_plan_destroy(ccmg_plan *plan);
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 
+/* Full multigrid (FMG) into d_phi: a start for the V-cycles that the paper
+ * does not describe (Sec. 3.3 cycles from zero and leaves the coarse solve
+ * open); it is the nested iteration of the multigrid literature (Brandt
+ * 1977; Briggs, Henson and McCormick, A Multigrid Tutorial, ch. 3) built from
+ * the operators of Sec. 3.3.  f is restricted (four-cell means) down to the
+ * top level of the plan's coarse tail (32 x 32 cells, or the finest level if
+ * smaller); there phi starts at zero and gets ncyc_top V-cycles; on each
+ * finer level phi = P (coarser phi), the Sec. 3.3 prolongation added to a
+ * zero field, then ncyc V-cycles of that level (on the finest level too).
+ * FP64 plans only; 1 <= ncyc_top <= 16, 0 <= ncyc <= 16; d_f and d_phi as
+ * for ccmg_solve (d_phi's contents on entry are not read; its ghosts are
+ * filled on return).  Uses the plan's workspace; enqueues device work on the
+ * plan's stream and returns without waiting.  For singular problems the
+ * result is defined up to an additive constant. */
+int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int ncyc_top, int ncyc);
+
 /* Plan options (all optional; read at every solve).
  *   CCMG_OPT_FUSED       0 or 1 (default 1): the fused finest launch of FP64
  *                        V(2,2) solves (0: one launch per half cycle, the
@@ -147,9 +163,14 @@ int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitc
  *                        by its own residual).
  *   CCMG_OPT_MIXED_INNER 1..8 (default 3): most FP32 V-cycles per refinement
  *                        step of MIXED plans with V(2,2).
+ *   CCMG_OPT_FMG         0..4 (default 0, off): FP64 solves without a guess
+ *                        start from a full multigrid pass (ccmg_fmg with this
+ *                        many V-cycles on every level but the finest) instead
+ *                        of zero; the V-cycles on the finest level are then
+ *                        the solve's own, counted in `cycles` as usual.
  * ccmg_plan_set_option returns CCMG_EINVAL for an unknown option or a value
  * outside its range; ccmg_plan_get_option writes the current value. */
-enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3 };
+enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3, CCMG_OPT_FMG = 4 };
 int ccmg_plan_set_option(ccmg_plan *plan, int option, double value);
 int ccmg_plan_get_option(ccmg_plan *plan, int option, double *value);
 

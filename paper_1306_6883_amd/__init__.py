@@ -25,7 +25,7 @@ BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC = 0, 1, 2
 FP64, MIXED = 0, 1
 OK, NOT_CONVERGED, EINVAL, ESIZE, EBC, EINCOMPAT, ENONFINITE, EHIP, EWORKSPACE = 0, 1, -1, -2, -3, -4, -5, -6, -7
 HISTORY = 128
-OPT_FUSED, OPT_FUSED_KEEP, OPT_MIXED_INNER = 1, 2, 3
+OPT_FUSED, OPT_FUSED_KEEP, OPT_MIXED_INNER, OPT_FMG = 1, 2, 3, 4
 BATCH_OPT_EAGER = 1
 _BC = {"D": BC_DIRICHLET, "N": BC_NEUMANN, "P": BC_PERIODIC,
        BC_DIRICHLET: BC_DIRICHLET, BC_NEUMANN: BC_NEUMANN, BC_PERIODIC: BC_PERIODIC}
@@ -84,6 +84,7 @@ def lib():
         L.ccmg_plan_destroy.argtypes = [vp]
         L.ccmg_solve.argtypes = [vp, dp, dp, pd, i, ctypes.POINTER(ccmg_result)]
         L.ccmg_vcycle.argtypes = [vp, dp, dp, pd]
+        L.ccmg_fmg.argtypes = [vp, dp, dp, pd, i, i]
         L.ccmg_fill_ghosts.argtypes = [vp, i, dp, pd]
         L.ccmg_smooth.argtypes = [vp, i, i, dp, dp, dp, pd]
         L.ccmg_residual.argtypes = [vp, i, dp, dp, dp, pd]
@@ -295,6 +296,15 @@ def ccmg_solve(plan: Plan, f: torch.Tensor, phi: torch.Tensor, use_guess: bool =
     _check(st, "ccmg_solve", allow=(OK, NOT_CONVERGED))
     hist = [r.history[k] for k in range(min(r.cycles + 1, HISTORY))]
     return Result(r.status, r.cycles, r.rel_resid0, r.rel_resid, hist, r.ms, r.inner_cycles)
+
+
+def ccmg_fmg(plan: Plan, f: torch.Tensor, phi: torch.Tensor, ncyc_top: int = 1, ncyc: int = 1) -> None:
+    """Full multigrid pass into phi (enqueued on the plan's stream)."""
+    fp, pitch = _field_args(f, plan.n)
+    pp, pitch2 = _field_args(phi, plan.n)
+    if pitch != pitch2:
+        raise ValueError("f and phi must share one pitch")
+    _check(lib().ccmg_fmg(plan.handle, fp, pp, pitch, ncyc_top, ncyc), "ccmg_fmg")
 
 
 def _side_data(plan: Plan, b) -> "ctypes.Array":

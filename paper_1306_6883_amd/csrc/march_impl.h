@@ -676,7 +676,15 @@ template <typename T, int NU>
 hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int post,
                               MarchShape sh, hipStream_t s, int *nt) {
     if (prolong) {
-        if (!load_phi) return hipErrorInvalidValue;
+        if (!load_phi) {
+            // the prolongation alone into a zero field (full multigrid), with
+            // or without the residual norm of the result
+            if constexpr (NU == 0) {
+                if (post == POST_NONE) return go<T, 0, false, true, POST_NONE>(a, sh, s, nt);
+                if (post == POST_NORM) return go<T, 0, false, true, POST_NORM>(a, sh, s, nt);
+            }
+            return hipErrorInvalidValue;
+        }
         if (post == POST_NONE) return go<T, NU, true, true, POST_NONE>(a, sh, s, nt);
         if (post == POST_NORM) return go<T, NU, true, true, POST_NORM>(a, sh, s, nt);
         if constexpr (std::is_same<T, float>::value) {

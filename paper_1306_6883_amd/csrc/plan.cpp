@@ -190,6 +190,7 @@ struct ccmg_plan {
     double opt_fused_keep = 100.0;  // keep a cycle's own iterate while the extrapolated residual is
                                     // within this factor of the tolerance
     int opt_mixed_inner = 3;     // most FP32 cycles per refinement step
+    int opt_fmg = 0;             // FMG start of FP64 solves without a guess: V-cycles per level (0: off)
     int n_bottom = 2;  // 4 or 8: exact solve on that level (ccmg_plan_set_bottom)
     int tcycle = 0;    // cycle being enqueued by the solve loop (tags timed launches)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
@@ -347,6 +348,12 @@ struct CycleIO {
     bool coarse_only = false;
     int f1_count = 0;                 // partial sums of the level-1 rhs already restricted
     Buf<T> *l1_out = nullptr;         // receives the buffer holding level 1's final iterate
+    // a cycle rooted at level top >= 1 (full multigrid): its rhs is that
+    // level's f buffer, its iterate top_in (one of the level's two buffers;
+    // ignored when `zero`), the buffer holding the result goes to *top_out
+    int top = 0;
+    Buf<T> top_in{nullptr, 0};
+    Buf<T> *top_out = nullptr;
 };
 
 template <typename T>
@@ -379,6 +386,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         if (l == 0) return Buf<T>{const_cast<T *>(io.f0), io.pf0};
         return Buf<T>{P->at<T>(lay.lev[l].f), lay.lev[l].pitch};
     };
+    const int top = io.coarse_only ? 1 : io.top;
     auto setup_bufs = [&](int l) {
         if (l == 0) {
             cur[0] = Buf<T>{io.phi0, io.pp0};
@@ -386,6 +394,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         } else {
             cur[l] = Buf<T>{P->at<T>(lay.lev[l].a), lay.lev[l].pitch};
             other[l] = Buf<T>{P->at<T>(lay.lev[l].b), lay.lev[l].pitch};
+            if (l == top && !io.coarse_only && io.top_in.p && io.top_in.p != cur[l].p) std::swap(cur[l], other[l]);
         }
     };
     auto fmean = [&](int l, MarchArgs<T> &a) {
@@ -421,11 +430,11 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
 
     // down
     if (io.coarse_only) fpart_count[1] = io.f1_count;
-    for (int l = io.coarse_only ? 1 : 0; l < lay.lt; ++l) {
+    for (int l = top; l < lay.lt; ++l) {
         setup_bufs(l);
         const MarchShape sh = P->shp_pre[l];
         const NuChain chain = split_nu(P->p.nu1);
-        bool zero = (l > 0) || io.zero;
+        bool zero = io.coarse_only || l > top || io.zero;
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
             MarchArgs<T> a{};
@@ -468,7 +477,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         const Buf<T> fb = fptr(l);
         c.f = fb.p;
         c.pf = fb.pitch;
-        c.load_phi = (l == 0 && !io.zero) ? 1 : 0;
+        c.load_phi = (l == top && !io.coarse_only && !io.zero) ? 1 : 0;
         c.phi_in = cur[l].p;
         c.pin = cur[l].pitch;
         c.phi_out = cur[l].p;  // the tail reads everything into LDS first
@@ -482,7 +491,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
         if (e != hipSuccess) return e;
     }
     // up
-    for (int l = lay.lt - 1; l >= (io.coarse_only ? 1 : 0); --l) {
+    for (int l = lay.lt - 1; l >= top; --l) {
         const MarchShape sh = P->shp_post[l];
         const NuChain chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
@@ -524,6 +533,10 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     }
     if (io.coarse_only) {
         if (io.l1_out) *io.l1_out = cur[1];
+        return hipSuccess;
+    }
+    if (top > 0) {
+        if (io.top_out) *io.top_out = cur[top];
         return hipSuccess;
     }
     // the result must end in phi0
@@ -571,6 +584,102 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
         e = launch_cycle_end(P->at<double>(P->lay.normpart), nt, P->lay.lev[0].n, P->singular ? 1 : 0,
                              P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(),
                              P->drho + slot, P->stream);
+    return e;
+}
+
+// Full multigrid start (FP64).  f is restricted (four-cell means) level by
+// level down to the coarse tail's top level c; there phi starts at zero and
+// gets ncyc_top V-cycles of the tail; on each finer level phi is the
+// prolongation of the coarser phi into a zero field, followed by ncyc
+// V-cycles rooted at that level (its coarser levels' buffers serve as the
+// cycle's corrections, the coarser phi being no longer needed).  Level 0's
+// phi goes to phi0.  With norm_slot >= 0 the level-0 prolongation also takes
+// the residual norm of its result and the cycle-end kernel files it in that
+// history slot (the solve's starting residual), and no V-cycle runs on level
+// 0; otherwise ncyc plain V-cycles follow there.  ncyc_top >= 1.
+hipError_t enqueue_fmg(ccmg_plan *P, const double *f0, long pf0, double *phi0, long pp0, int ncyc_top, int ncyc,
+                       int norm_slot) {
+    const Layout &lay = P->lay;
+    hipStream_t s = P->stream;
+    const int c = lay.lt;
+    hipError_t e = hipSuccess;
+    int nt = 0;
+    if (c > 0) {
+        // 1. the right-hand side on every level down to c
+        for (int l = 1; l <= c && e == hipSuccess; ++l) {
+            const double *src = l == 1 ? f0 : P->at<double>(lay.lev[l - 1].f);
+            const long ps = l == 1 ? pf0 : lay.lev[l - 1].pitch;
+            e = launch_restrict(src, ps, P->at<double>(lay.lev[l].f), lay.lev[l].pitch, lay.lev[l].n, s);
+        }
+        // 2. level c: V-cycles of the tail from zero
+        Buf<double> cur{P->at<double>(lay.lev[c].a), lay.lev[c].pitch};
+        for (int k = 0; k < ncyc_top && e == hipSuccess; ++k) {
+            CycleIO<double> io;
+            io.top = c;
+            io.zero = k == 0;
+            io.top_in = cur;
+            io.top_out = &cur;
+            e = enqueue_cycle<double>(P, io, &nt);
+        }
+        // 3. levels c - 1 .. 1: prolongate, then V-cycles rooted there
+        for (int l = c - 1; l >= 1 && e == hipSuccess; --l) {
+            MarchArgs<double> a{};
+            level_consts(P, l, a);
+            a.f = P->at<double>(lay.lev[l].f);
+            a.pf = lay.lev[l].pitch;
+            a.phi_out = P->at<double>(lay.lev[l].a);
+            a.pout = lay.lev[l].pitch;
+            a.ec = cur.p;
+            a.pc = cur.pitch;
+            e = launch_march<double>(a, 0, false, true, POST_NONE, shape_for(lay.lev[l].n), s, &nt);
+            cur = Buf<double>{P->at<double>(lay.lev[l].a), lay.lev[l].pitch};
+            for (int k = 0; k < ncyc && e == hipSuccess; ++k) {
+                CycleIO<double> io;
+                io.top = l;
+                io.top_in = cur;
+                io.top_out = &cur;
+                e = enqueue_cycle<double>(P, io, &nt);
+            }
+        }
+        // 4. level 0
+        if (e == hipSuccess) {
+            MarchArgs<double> a{};
+            level_consts(P, 0, a);
+            a.f = f0;
+            a.pf = pf0;
+            a.phi_out = phi0;
+            a.pout = pp0;
+            a.ec = cur.p;
+            a.pc = cur.pitch;
+            a.partial = P->at<double>(lay.normpart);
+            e = launch_march<double>(a, 0, false, true, norm_slot >= 0 ? POST_NORM : POST_NONE,
+                                     shape_for(lay.lev[0].n), s, &nt);
+        }
+        if (e == hipSuccess && norm_slot >= 0)
+            return launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0,
+                                    P->scal() + S_F2, P->p.rtol, P->hist() + norm_slot, P->scal() + S_PHIMEAN,
+                                    P->done(), P->drho + norm_slot, s);
+        for (int k = 0; k < ncyc && e == hipSuccess; ++k)
+            e = enqueue_vcycle64(P, f0, pf0, phi0, pp0, false, nullptr, false, 0);
+        return e;
+    }
+    // the finest level is the tail's top: V-cycles from zero there
+    for (int k = 0; k < ncyc_top && e == hipSuccess; ++k)
+        e = enqueue_vcycle64(P, f0, pf0, phi0, pp0, k == 0, nullptr, false, 0);
+    if (e == hipSuccess && norm_slot >= 0) {
+        MarchArgs<double> a{};
+        level_consts(P, 0, a);
+        a.f = f0;
+        a.pf = pf0;
+        a.phi_in = phi0;
+        a.pin = pp0;
+        a.partial = P->at<double>(lay.normpart);
+        e = launch_march<double>(a, 0, true, false, POST_NORM, shape_for(lay.lev[0].n), s, &nt);
+        if (e == hipSuccess)
+            e = launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, P->singular ? 1 : 0,
+                                 P->scal() + S_F2, P->p.rtol, P->hist() + norm_slot, P->scal() + S_PHIMEAN,
+                                 P->done(), P->drho + norm_slot, s);
+    }
     return e;
 }
 
@@ -1165,6 +1274,10 @@ int ccmg_plan_set_option(ccmg_plan *P, int option, double value) {
             if (value != std::floor(value) || value < 1.0 || value > 8.0) return CCMG_EINVAL;
             P->opt_mixed_inner = (int)value;
             return CCMG_OK;
+        case CCMG_OPT_FMG:
+            if (value != std::floor(value) || value < 0.0 || value > 4.0) return CCMG_EINVAL;
+            P->opt_fmg = (int)value;
+            return CCMG_OK;
         default: return CCMG_EINVAL;
     }
 }
@@ -1175,6 +1288,7 @@ int ccmg_plan_get_option(ccmg_plan *P, int option, double *value) {
         case CCMG_OPT_FUSED: *value = P->opt_fused ? 1.0 : 0.0; return CCMG_OK;
         case CCMG_OPT_FUSED_KEEP: *value = P->opt_fused_keep; return CCMG_OK;
         case CCMG_OPT_MIXED_INNER: *value = (double)P->opt_mixed_inner; return CCMG_OK;
+        case CCMG_OPT_FMG: *value = (double)P->opt_fmg; return CCMG_OK;
         default: return CCMG_EINVAL;
     }
 }
@@ -1636,6 +1750,11 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (e == hipSuccess) e = launch_set(scal, kScal, 0.0, s);
     if (e == hipSuccess)
         e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
+    // full multigrid start (FP64 solves without a guess, option CCMG_OPT_FMG):
+    // its last launch also gives the starting residual, as a guess's would
+    const bool fmg = P->opt_fmg > 0 && !use_guess && !mixed;
+    if (e == hipSuccess && fmg) e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, 0);
+    const bool guess = use_guess || fmg;
     MixedState st = mixed_state(P, d_phi, pitch, !use_guess);
     if (e == hipSuccess && mixed) {
         e = enqueue_mixed_start(P, d_f, pitch, st, use_guess != 0, 0);  // r32, rho0 -> hist[0]
@@ -1668,7 +1787,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     }
     if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
 
-    const double rho0 = (use_guess || mixed) ? P->hrho[0] : 1.0;
+    const double rho0 = (guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
     if (use_guess && std::isfinite(guess_reject) && !(rho0 <= guess_reject)) return R->status = kGuessRejected;
@@ -1682,7 +1801,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     // FP64 with fused finest launches: the driver's state after each cycle
     const bool fused = !mixed && fused_eligible(P);
     const double keep = P->opt_fused_keep;
-    FusedCtx fx{Buf<double>{d_phi, pitch}, false, !use_guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
+    FusedCtx fx{Buf<double>{d_phi, pitch}, false, !guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;
@@ -1759,7 +1878,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 x = enqueue_fused_cycle(P, fx, d_f, pitch, Buf<double>{d_phi, pitch}, k, end_fused, with_mid);
                 fafter[k] = fx;
             } else {
-                x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !use_guess, shift, true, k);
+                x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !guess, shift, true, k);
             }
             if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
             return x;
@@ -1883,6 +2002,15 @@ extern "C" {
 int ccmg_solve(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out) {
     return solve_impl(P, d_f, d_phi, pitch, use_guess, out, INFINITY);
+}
+
+int ccmg_fmg(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int ncyc_top, int ncyc) {
+    if (!P || !d_f || !d_phi || P->p.prec != CCMG_FP64) return CCMG_EINVAL;
+    if (ncyc_top < 1 || ncyc_top > 16 || ncyc < 0 || ncyc > 16) return CCMG_EINVAL;
+    if (check_pitch(P, 0, pitch) != CCMG_OK) return CCMG_EINVAL;
+    hipError_t e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, ncyc_top, ncyc, -1);
+    if (e == hipSuccess) e = launch_fill_ghosts_f64(d_phi, pitch, P->lay.lev[0].n, P->p.bc, nullptr, P->stream);
+    return hip_status(e);
 }
 
 // ---- single steps -----------------------------------------------------------
