@@ -167,7 +167,11 @@ int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch,
  *                        start from a full multigrid pass (ccmg_fmg with this
  *                        many V-cycles on every level but the finest) instead
  *                        of zero; the V-cycles on the finest level are then
- *                        the solve's own, counted in `cycles` as usual.
+ *                        the solve's own, counted in `cycles` as usual.  With
+ *                        the fused finest launch the finest level's
+ *                        prolongation runs inside the first pre-smoothing and
+ *                        the start's residual is not formed: rel_resid0 and
+ *                        history[0] are NaN.
  * ccmg_plan_set_option returns CCMG_EINVAL for an unknown option or a value
  * outside its range; ccmg_plan_get_option writes the current value. */
 enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3, CCMG_OPT_FMG = 4 };

@@ -199,6 +199,9 @@ hipError_t launch_cycle_end(const double *partial, int count, int n, int singula
 // Statistics of f (sum, sum |f|, sum f^2, non-finite count) -> out4; `blocks` partials.
 hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
                          hipStream_t s);
+// The same, and coarse (n/2 cells, pitch pc) = the four-cell restriction of f.
+hipError_t launch_fstats_restrict(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
+                                  double *coarse, long pc, hipStream_t s);
 hipError_t launch_set(double *p, int count, double v, hipStream_t s);
 hipError_t launch_set_int(int *p, int count, int v, hipStream_t s);
 // coarse = four-cell average of fine (valid cells; nc cells per side of the coarse level).

@@ -683,6 +683,11 @@ hipError_t dispatch_nu(const MarchArgs<T> &a, bool load_phi, bool prolong, int p
                 if (post == POST_NONE) return go<T, 0, false, true, POST_NONE>(a, sh, s, nt);
                 if (post == POST_NORM) return go<T, 0, false, true, POST_NORM>(a, sh, s, nt);
             }
+            // ... or followed by the pre-smoothing and restriction (the first
+            // cycle of an FP64 solve from a full multigrid start)
+            if constexpr (NU == 2 && std::is_same<T, double>::value) {
+                if (post == POST_RESTRICT) return go<T, 2, false, true, POST_RESTRICT>(a, sh, s, nt);
+            }
             return hipErrorInvalidValue;
         }
         if (post == POST_NONE) return go<T, NU, true, true, POST_NONE>(a, sh, s, nt);

@@ -598,7 +598,7 @@ hipError_t enqueue_vcycle64(ccmg_plan *P, const double *f0, long pf0, double *ph
 // history slot (the solve's starting residual), and no V-cycle runs on level
 // 0; otherwise ncyc plain V-cycles follow there.  ncyc_top >= 1.
 hipError_t enqueue_fmg(ccmg_plan *P, const double *f0, long pf0, double *phi0, long pp0, int ncyc_top, int ncyc,
-                       int norm_slot) {
+                       int norm_slot, Buf<double> *l1_out = nullptr, bool f1_ready = false) {
     const Layout &lay = P->lay;
     hipStream_t s = P->stream;
     const int c = lay.lt;
@@ -606,7 +606,7 @@ hipError_t enqueue_fmg(ccmg_plan *P, const double *f0, long pf0, double *phi0, l
     int nt = 0;
     if (c > 0) {
         // 1. the right-hand side on every level down to c
-        for (int l = 1; l <= c && e == hipSuccess; ++l) {
+        for (int l = f1_ready ? 2 : 1; l <= c && e == hipSuccess; ++l) {
             const double *src = l == 1 ? f0 : P->at<double>(lay.lev[l - 1].f);
             const long ps = l == 1 ? pf0 : lay.lev[l - 1].pitch;
             e = launch_restrict(src, ps, P->at<double>(lay.lev[l].f), lay.lev[l].pitch, lay.lev[l].n, s);
@@ -641,7 +641,12 @@ hipError_t enqueue_fmg(ccmg_plan *P, const double *f0, long pf0, double *phi0, l
                 e = enqueue_cycle<double>(P, io, &nt);
             }
         }
-        // 4. level 0
+        // 4. level 0 (or, with l1_out, left to the caller: the fused solve
+        // prolongates inside its first pre-smoothing launch)
+        if (l1_out) {
+            *l1_out = cur;
+            return e;
+        }
         if (e == hipSuccess) {
             MarchArgs<double> a{};
             level_consts(P, 0, a);
@@ -1574,6 +1579,8 @@ struct FusedCtx {
     int f1_count;        // partial sums of the level-1 rhs
     Buf<double> res;     // where the last enqueued cycle's post-smoothed iterate is (p = null: not kept)
     Buf<double> next;    // the pre-smoothed iterate of the following cycle (fused end)
+    Buf<double> first_ec{nullptr, 0};  // full multigrid start: the level-1 phi that the first
+                                       // pre-smoothing prolongates into a zero field
 };
 
 // One V-cycle of the fused driver: [level-0 pre] + levels >= 1 + level-0 end
@@ -1607,9 +1614,20 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
         a.aux = P->at<double>(lay.lev[1].f);
         a.paux = lay.lev[1].pitch;
         a.partial = P->at<double>(lay.lev[1].fpart);
-        const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? 2.0 : 3.0) + 0.25));
-        e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
-        P->tstop(ti);
+        if (cx.first_ec.p) {
+            // phi = P (level-1 phi of the full multigrid pass), then the pre-smoothing
+            a.ec = cx.first_ec.p;
+            a.pc = cx.first_ec.pitch;
+            a.phi_shift = nullptr;
+            const int ti = P->tstart(0, sizeof(double) * nn * 2.5);
+            e = launch_march<double>(a, 2, false, true, POST_RESTRICT, P->shp_pre[0], s, &nt);
+            P->tstop(ti);
+            cx.first_ec = Buf<double>{nullptr, 0};
+        } else {
+            const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? 2.0 : 3.0) + 0.25));
+            e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
+            P->tstop(ti);
+        }
         if (e != hipSuccess) return e;
         cx.f1_count = nt;
         cx.cur = out;
@@ -1748,12 +1766,22 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     // statistics of f, reset of the flags, and the starting residual
     if (e == hipSuccess) e = launch_set_int(P->done(), 1, 0, s);
     if (e == hipSuccess) e = launch_set(scal, kScal, 0.0, s);
-    if (e == hipSuccess)
+    // full multigrid start: f's statistics and its restriction to level 1 from one read
+    const bool fmg_f1 = P->opt_fmg > 0 && !use_guess && !mixed && lay.lt >= 1;
+    if (e == hipSuccess && fmg_f1)
+        e = launch_fstats_restrict(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM,
+                                   P->at<double>(lay.lev[1].f), lay.lev[1].pitch, s);
+    else if (e == hipSuccess)
         e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
     // full multigrid start (FP64 solves without a guess, option CCMG_OPT_FMG):
     // its last launch also gives the starting residual, as a guess's would
+    // (FP64 solves with the fused finest launch prolongate the FMG result
+    // inside their first pre-smoothing launch; the start's own residual is
+    // then not formed and rel_resid0 is NaN)
     const bool fmg = P->opt_fmg > 0 && !use_guess && !mixed;
-    if (e == hipSuccess && fmg) e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, 0);
+    const bool fmg_fused = fmg && fused_eligible(P);
+    if (e == hipSuccess && fmg && !fmg_fused)
+        e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, 0, nullptr, fmg_f1);
     const bool guess = use_guess || fmg;
     MixedState st = mixed_state(P, d_phi, pitch, !use_guess);
     if (e == hipSuccess && mixed) {
@@ -1787,11 +1815,11 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     }
     if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
 
-    const double rho0 = (guess || mixed) ? P->hrho[0] : 1.0;
+    const double rho0 = fmg_fused ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
     if (use_guess && std::isfinite(guess_reject) && !(rho0 <= guess_reject)) return R->status = kGuessRejected;
-    if (!std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
+    if (!fmg_fused && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
     int status = CCMG_NOT_CONVERGED;
     int cycles = 0;
     double rho = rho0;
@@ -1802,6 +1830,10 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const bool fused = !mixed && fused_eligible(P);
     const double keep = P->opt_fused_keep;
     FusedCtx fx{Buf<double>{d_phi, pitch}, false, !guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
+    if (fmg_fused) {
+        e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, -1, &fx.first_ec, fmg_f1);
+        if (e != hipSuccess) return R->status = CCMG_EHIP;
+    }
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;

@@ -139,6 +139,49 @@ __global__ __launch_bounds__(kRed) void k_fstats(const double *f, long pitch, in
     }
 }
 
+// The same statistics, and the four-cell restriction of f into `coarse`
+// (level 1, pitch pc) from the same loads: grid-stride over coarse rows, each
+// thread one coarse cell (two 16-byte loads per fine row pair), the mean
+// formed in the order ((f(2I,2J) + f(2I+1,2J)) + f(2I,2J+1)) + f(2I+1,2J+1).
+__global__ __launch_bounds__(kRed) void k_fstats_restrict(const double *f, long pitch, int n, double *out,
+                                                          double *coarse, long pc) {
+    __shared__ double red[4];
+    double s = 0.0, sa = 0.0, s2 = 0.0, bad = 0.0;
+    auto add = [&](double v) {
+        if (!isfinite(v)) {
+            bad += 1.0;
+            return;
+        }
+        s += v;
+        sa += fabs(v);
+        s2 += v * v;
+    };
+    const int nc = n >> 1;
+    for (int J = blockIdx.x; J < nc; J += gridDim.x) {
+        const double *r0 = f + (long)(2 * J + 1) * pitch + 1;
+        const double *r1 = r0 + pitch;
+        double *c = coarse + (long)(J + 1) * pc + 1;
+        for (int I = threadIdx.x; I < nc; I += kRed) {
+            const double a = r0[2 * I], b = r0[2 * I + 1], d = r1[2 * I], e = r1[2 * I + 1];
+            add(a);
+            add(b);
+            add(d);
+            add(e);
+            c[I] = 0.25 * (((a + b) + d) + e);
+        }
+    }
+    s = block_sum256(s, red);
+    sa = block_sum256(sa, red);
+    s2 = block_sum256(s2, red);
+    bad = block_sum256(bad, red);
+    if (threadIdx.x == 0) {
+        out[4 * blockIdx.x + 0] = s;
+        out[4 * blockIdx.x + 1] = sa;
+        out[4 * blockIdx.x + 2] = s2;
+        out[4 * blockIdx.x + 3] = bad;
+    }
+}
+
 __global__ __launch_bounds__(kRed) void k_reduce4(const double *p, int count, double *out4) {
     __shared__ double red[4];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -166,6 +209,13 @@ __global__ __launch_bounds__(kRed) void k_reduce4(const double *p, int count, do
 hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_fstats, dim3(blocks), dim3(kRed), 0, s, f, pitch, n, partial);
+    hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kRed), 0, s, partial, blocks, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_fstats_restrict(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
+                                  double *coarse, long pc, hipStream_t s) {
+    hipLaunchKernelGGL(k_fstats_restrict, dim3(blocks), dim3(kRed), 0, s, f, pitch, n, partial, coarse, pc);
     hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kRed), 0, s, partial, blocks, out4);
     return hipGetLastError();
 }
