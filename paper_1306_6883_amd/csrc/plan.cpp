@@ -1802,7 +1802,18 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->hpin + CCMG_HISTORY, scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    Buf<double> fmg_l1{nullptr, 0};
+    if (fmg_fused) {
+        // the full multigrid pass (workspace only) is queued before the host
+        // waits for f's statistics: its many small launches are enqueued while
+        // the device still works, and it runs while the host checks them
+        if (e == hipSuccess) e = hipEventRecord(P->ev_sync[0], s);
+        if (e == hipSuccess)
+            e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, -1, &fmg_l1, fmg_f1);
+        if (e == hipSuccess) e = hipEventSynchronize(P->ev_sync[0]);
+    } else if (e == hipSuccess) {
+        e = hipStreamSynchronize(s);
+    }
     if (e != hipSuccess) return R->status = CCMG_EHIP;
     const double *hs = P->hpin + CCMG_HISTORY;
     if (hs[S_FBAD] > 0 || !std::isfinite(hs[S_F2])) return R->status = CCMG_ENONFINITE;
@@ -1830,10 +1841,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const bool fused = !mixed && fused_eligible(P);
     const double keep = P->opt_fused_keep;
     FusedCtx fx{Buf<double>{d_phi, pitch}, false, !guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
-    if (fmg_fused) {
-        e = enqueue_fmg(P, d_f, pitch, d_phi, pitch, P->opt_fmg, P->opt_fmg, -1, &fx.first_ec, fmg_f1);
-        if (e != hipSuccess) return R->status = CCMG_EHIP;
-    }
+    if (fmg_fused) fx.first_ec = fmg_l1;
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;

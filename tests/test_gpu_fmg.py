@@ -125,3 +125,22 @@ def test_solve_with_fmg_start(bc, n, fused):
         else:
             assert 0.0 < r1.rel_resid0 < 1.0
         assert abs(r1.history[1] - rho) <= 1e-6 * rho
+
+
+def test_solve_with_fmg_start_zero_and_nonfinite_rhs():
+    """The FMG pass is queued before f's statistics are checked; a zero f
+    still gives phi = 0 and OK, a non-finite f ENONFINITE, and the plan
+    solves normally afterwards."""
+    n = 256
+    plan = cc.Plan(cc.Problem(n=n, bc="D", rtol=1e-10))
+    cc.ccmg_plan_set_option(plan, cc.OPT_FMG, 1)
+    phi = dev_field(np.full((n + 2, n + 2), 3.0))
+    r = cc.ccmg_solve(plan, dev_field(np.zeros((n + 2, n + 2))), phi)
+    assert r.status == cc.OK and torch.count_nonzero(phi[:, :n + 2]).item() == 0
+    bad = np.zeros((n + 2, n + 2))
+    bad[5, 7] = np.inf
+    with pytest.raises(cc.CcmgError):
+        cc.ccmg_solve(plan, dev_field(bad), phi)
+    f = rhs(n, 2, False)
+    r = cc.ccmg_solve(plan, dev_field(oracle.embed(f)), phi)
+    assert r.status == cc.OK and r.rel_resid <= 1e-10
