@@ -1848,7 +1848,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     } else if (P->p.max_cycles > 0) {
         const double *shift = P->singular ? scal + S_PHIMEAN : nullptr;
         std::vector<double> rhos(P->p.max_cycles + 2, 0.0);
-        rhos[0] = rho0;
+        // (a start whose residual was not formed predicts like the zero start)
+        rhos[0] = std::isfinite(rho0) ? rho0 : 1.0;
         int checked = 0;  // cycles whose residual the host has read
         const int inner_max = mixed ? mixed_inner_max(P) : 1;
         std::vector<int> &inner = inner_used;
