@@ -154,7 +154,7 @@ int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch,
  *   CCMG_OPT_FUSED       0 or 1 (default 1): the fused finest launch of FP64
  *                        V(2,2) solves (0: one launch per half cycle, the
  *                        same iterates).
- *   CCMG_OPT_FUSED_KEEP  >= 0 (default 100): a fused launch also writes the
+ *   CCMG_OPT_FUSED_KEEP  >= 0 (default 1): a fused launch also writes the
  *                        iterate after its post-smoothing (the solve's result
  *                        if that cycle meets the tolerance) while the residual
  *                        extrapolated from the last two cycles is within this

@@ -187,7 +187,7 @@ struct ccmg_plan {
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     // options (ccmg_plan_set_option)
     bool opt_fused = true;       // fused finest launch of FP64 V(2,2) solves
-    double opt_fused_keep = 100.0;  // keep a cycle's own iterate while the extrapolated residual is
+    double opt_fused_keep = 1.0;    // keep a cycle's own iterate while the extrapolated residual is
                                     // within this factor of the tolerance
     int opt_mixed_inner = 3;     // most FP32 cycles per refinement step
     int opt_fmg = 0;             // FMG start of FP64 solves without a guess: V-cycles per level (0: off)
@@ -895,7 +895,7 @@ void plan_init_host(ccmg_plan *P, const ccmg_problem &p) {
     P->timer.on = false;
     P->timer.used = 0;
     P->opt_fused = true;
-    P->opt_fused_keep = 100.0;
+    P->opt_fused_keep = 1.0;
     P->opt_mixed_inner = 3;
 }
 

@@ -157,7 +157,7 @@ def test_kernel_stats_count_only_launches_that_ran(c):
 def test_plan_options_round_trip_and_reject_bad_values():
     plan = cc.Plan(cc.Problem(n=64, bc="D"))
     assert cc.ccmg_plan_get_option(plan, cc.OPT_FUSED) == 1.0
-    assert cc.ccmg_plan_get_option(plan, cc.OPT_FUSED_KEEP) == 100.0
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_FUSED_KEEP) == 1.0
     assert cc.ccmg_plan_get_option(plan, cc.OPT_MIXED_INNER) == 3.0
     cc.ccmg_plan_set_option(plan, cc.OPT_MIXED_INNER, 5)
     assert cc.ccmg_plan_get_option(plan, cc.OPT_MIXED_INNER) == 5.0
