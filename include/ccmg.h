@@ -158,7 +158,8 @@ int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch,
  *                        iterate after its post-smoothing (the solve's result
  *                        if that cycle meets the tolerance) while the residual
  *                        extrapolated from the last two cycles is within this
- *                        factor of the tolerance; 0 never (the solve then
+ *                        factor of the tolerance (at least 100 until three
+ *                        cycles' residuals are known); 0 never (the solve then
  *                        returns the next cycle's pre-smoothed iterate, checked
  *                        by its own residual).
  *   CCMG_OPT_MIXED_INNER 1..8 (default 3): most FP32 V-cycles per refinement

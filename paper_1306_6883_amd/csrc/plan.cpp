@@ -1915,7 +1915,11 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 // while k may be the last
                 const double pred = predict(k);
                 const bool end_fused = k < P->p.max_cycles && !(pred <= 0.5 * P->p.rtol && checked >= 2);
-                const bool with_mid = !std::isfinite(pred) || pred <= keep * P->p.rtol;
+                // the extrapolation is trusted once three residuals are known;
+                // before that (short solves from a good guess contract faster
+                // than their first cycles show) the window is at least 100x
+                const double kf = (keep == 0.0 || checked >= 3) ? keep : std::max(keep, 100.0);
+                const bool with_mid = !std::isfinite(pred) || pred <= kf * P->p.rtol;
                 x = enqueue_fused_cycle(P, fx, d_f, pitch, Buf<double>{d_phi, pitch}, k, end_fused, with_mid);
                 fafter[k] = fx;
             } else {
