@@ -173,9 +173,23 @@ int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch,
  *                        prolongation runs inside the first pre-smoothing and
  *                        the start's residual is not formed: rel_resid0 and
  *                        history[0] are NaN.
+ *   CCMG_OPT_VISIT       0, 1 or 2 (default 1): in V(2,2) cycles a level below
+ *                        the finest and above the one-workgroup tail, whose
+ *                        correction starts from zero, may run as a visit:
+ *                        its restricting launch on the way down (two
+ *                        red-black iterations from zero, residual,
+ *                        restriction; Sec. 3.3) stores no iterate, and one
+ *                        launch on the way up recomputes those two
+ *                        iterations, adds the prolongated correction and
+ *                        runs the two post-smoothing iterations.  Each cell
+ *                        of the level is written and read once less; the
+ *                        iterates are bitwise those of the two-launch form.
+ *                        0: never; 1: on the levels where ccmg_plan_autotune
+ *                        found the pair faster (none on an untuned plan);
+ *                        2: on every level where it applies.
  * ccmg_plan_set_option returns CCMG_EINVAL for an unknown option or a value
  * outside its range; ccmg_plan_get_option writes the current value. */
-enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3, CCMG_OPT_FMG = 4 };
+enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3, CCMG_OPT_FMG = 4, CCMG_OPT_VISIT = 5 };
 int ccmg_plan_set_option(ccmg_plan *plan, int option, double value);
 int ccmg_plan_get_option(ccmg_plan *plan, int option, double *value);
 
@@ -416,10 +430,11 @@ int ccmg_solve_learned(ccmg_plan *plan, ccmg_net *net, const double *d_f, double
 /* ---- launch-shape autotuning.
  * Times every candidate tile shape (rows per wavefront band x wavefronts per
  * workgroup, or the 2-D tile kernel below the finest level) of the two
- * launches of each level, and of the fused finest launch, on the given data
- * and keeps the fastest for this plan.  d_f and d_phi are only read (finest level,
- * same layout as ccmg_solve); blocks until done.  Optional: untuned plans use
- * a fixed size-based choice. */
+ * launches of each level, of the same level run as a visit (see
+ * CCMG_OPT_VISIT; the visit is kept where its pair is faster), and of the
+ * fused finest launch, on the given data and keeps the fastest for this plan.
+ * d_f and d_phi are only read (finest level, same layout as ccmg_solve);
+ * blocks until done.  Optional: untuned plans use a fixed size-based choice. */
 int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch);
 /* Set one launch shape by hand: kind 0 = the nu1 (restricting) launch of
  * `level`, 1 = the nu2 (prolongating) launch; ty even, >= 8 unless it covers
@@ -427,8 +442,17 @@ int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdif
  * of the row march (levels below the finest with at least 64 cells per side
  * that are not in the one-workgroup tail).  kind 2 = the fused finest launch
  * of FP64 solves, 3 = its FP32 form in mixed-precision steps (level 0 only,
- * ty even and >= 8, no tile kernel).  Results do not depend on the shape. */
+ * ty even and >= 8, no tile kernel).  Levels below the finest that are not
+ * in the tail, run as a visit (CCMG_OPT_VISIT): kind 4 = the restricting
+ * launch without the stored iterate (as kind 0), kind 5 = the visit launch
+ * (row march only, ty even and >= 16 unless it covers the level; ty = 0 sets
+ * the level to run its two launches instead, and with CCMG_OPT_VISIT = 1
+ * any other ty sets it to run as a visit).  Results do not depend on the
+ * shape. */
 int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
+/* One launch shape, kinds as for ccmg_plan_set_shape (kind 5 gives ty = 0,
+ * wpb = 1 for a level that does not run as a visit under CCMG_OPT_VISIT = 1). */
+int ccmg_plan_shape(ccmg_plan *plan, int level, int kind, int *ty, int *wpb);
 /* The fused finest launch's shape: kind 2 (FP64) or 3 (FP32), as for
  * ccmg_plan_set_shape. */
 int ccmg_plan_fused_shape(ccmg_plan *plan, int kind, int *ty, int *wpb);

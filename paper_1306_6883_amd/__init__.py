@@ -25,7 +25,7 @@ BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC = 0, 1, 2
 FP64, MIXED = 0, 1
 OK, NOT_CONVERGED, EINVAL, ESIZE, EBC, EINCOMPAT, ENONFINITE, EHIP, EWORKSPACE = 0, 1, -1, -2, -3, -4, -5, -6, -7
 HISTORY = 128
-OPT_FUSED, OPT_FUSED_KEEP, OPT_MIXED_INNER, OPT_FMG = 1, 2, 3, 4
+OPT_FUSED, OPT_FUSED_KEEP, OPT_MIXED_INNER, OPT_FMG, OPT_VISIT = 1, 2, 3, 4, 5
 BATCH_OPT_EAGER = 1
 _BC = {"D": BC_DIRICHLET, "N": BC_NEUMANN, "P": BC_PERIODIC,
        BC_DIRICHLET: BC_DIRICHLET, BC_NEUMANN: BC_NEUMANN, BC_PERIODIC: BC_PERIODIC}
@@ -114,6 +114,7 @@ def lib():
         L.ccmg_cn_step.argtypes = [vp, dp, dp, pd, ctypes.POINTER(ccmg_result)]
         L.ccmg_plan_fused_shape.argtypes = [vp, i, ip, ip]
         L.ccmg_plan_set_shape.argtypes = [vp, i, i, i, i]
+        L.ccmg_plan_shape.argtypes = [vp, i, i, ip, ip]
         L.ccmg_plan_set_bottom.argtypes = [vp, i]
         L.ccmg_plan_kernel_stats.argtypes = [vp, ctypes.POINTER(ccmg_kernel_stat), i, ctypes.POINTER(i)]
         fp = ctypes.POINTER(ctypes.c_float)
@@ -471,6 +472,14 @@ def ccmg_plan_fused_shape(plan: Plan, kind: int = 2) -> tuple:
     ty, wpb = ctypes.c_int(), ctypes.c_int()
     _check(lib().ccmg_plan_fused_shape(plan.handle, kind, ctypes.byref(ty), ctypes.byref(wpb)),
            "ccmg_plan_fused_shape")
+    return ty.value, wpb.value
+
+
+def ccmg_plan_shape(plan: Plan, level: int, kind: int) -> tuple:
+    """(ty, wpb) of one launch, kinds as for ccmg_plan_set_shape (kind 5:
+    ty = 0 for a level that does not run as a visit)."""
+    ty, wpb = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ccmg_plan_shape(plan.handle, level, kind, ctypes.byref(ty), ctypes.byref(wpb)), "ccmg_plan_shape")
     return ty.value, wpb.value
 
 

@@ -19,10 +19,15 @@ enum Post {
     POST_IR = 4,        // (float launches) relaxed e -> phi64_out = phi64_in + e, FP64 residual
                         // of phi64_out -> r32 (+ sum r^2, sum phi64, sum r32 per tile)
     POST_R32 = 5,       // (double launches) residual -> r32 (+ the same three sums)
-    POST_FUSED = 6      // (finest level, NU = 4) the post-smoothing of one cycle and the
+    POST_FUSED = 6,     // (finest level, NU = 4) the post-smoothing of one cycle and the
                         // pre-smoothing of the next in one launch: after the first two iterations
                         // the residual norm (sum r^2, sum phi per tile -> partial_norm, if set) and the
                         // iterate (-> phi_mid, if set); after all four, RESTRICT as above
+    POST_VISIT = 7      // (levels below the finest, NU = 4, from zero, with prolongation) a
+                        // level's whole visit in one launch: the two pre-smoothing iterations
+                        // from zero (recomputed: the restricting launch of the way down then
+                        // stores no iterate), the prolongation of the coarse correction, the
+                        // two post-smoothing iterations; stores the result
 };
 
 // Arguments of one row-march launch over one grid level (see march.hip).
@@ -115,6 +120,9 @@ hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolo
 // The fused finest-level launch (POST_FUSED; march_f64_fused.hip).
 hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 hipError_t dispatch_fused(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
+// A coarse level's whole visit (POST_VISIT; march_visit.hip).
+hipError_t dispatch_visit(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
+hipError_t dispatch_visit(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
 // One march variant family with NU fused iterations; defined in march_impl.h and
 // instantiated per (T, NU) in the march_*.hip files.
 template <typename T, int NU>

@@ -14,6 +14,11 @@ hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolo
             return dispatch_fused(a, shape, s, nt);
         return hipErrorInvalidValue;
     }
+    if (post == POST_VISIT) {
+        if (nu == 4 && !load_phi && prolong && shape.ty >= 2 && !(shape.ty & 1) && shape.wpb >= 1 && shape.wpb <= 4)
+            return dispatch_visit(a, shape, s, nt);
+        return hipErrorInvalidValue;
+    }
     if (shape.ty == 0) return launch_tile<T>(a, nu, load_phi, prolong, post, s, nt);
     if (shape.ty < 2 || (shape.ty & 1) || shape.wpb < 1 || shape.wpb > 4) return hipErrorInvalidValue;
     switch (nu) {

@@ -35,6 +35,13 @@
 
 #include "internal.h"
 
+// Products are fused into additions only within one expression, as written
+// (a * b + c): never across statements.  A value kept in a register from an
+// earlier stage then takes part in later sums exactly as it would after a
+// round trip through memory, so the fused, visit and separate-launch forms
+// of a cycle give the same bits for any operator.
+#pragma clang fp contract(on)
+
 namespace ccmg {
 
 // ---- cross-lane moves (DPP wavefront shifts) --------------------------------
@@ -102,21 +109,28 @@ __device__ __forceinline__ void static_for(F &&f) {
 // ---- compile-time shape of a march variant ----------------------------------
 template <int NU, bool PROLONG, int POST>
 struct Cfg {
-    static constexpr int LAGR = POST ? 2 * NU + 1 : 0;  // residual stage
-    static constexpr int LAST = POST ? LAGR : 2 * NU;   // last stage
+    // VISIT: pre-smoothing stages 1 .. NU, the prolongation, post-smoothing
+    // stages NU + 1 .. 2 NU; no residual
+    static constexpr bool VISIT = POST == POST_VISIT;
+    static constexpr bool RES = POST != POST_NONE && !VISIT;  // a residual stage follows the relaxation
+    static constexpr int LAGR = RES ? 2 * NU + 1 : 0;  // residual stage
+    static constexpr int LAST = RES ? LAGR : 2 * NU;   // last stage
     // halo columns: one per stage, two (one lane) for the prolongation slope
-    static constexpr int HX = march_halo_x(NU, PROLONG, POST != 0);
+    // (VISIT: the slope's two columns lie within the pre-smoothing's four, so
+    // the halo has a column to spare)
+    static constexpr int HX = march_halo_x(NU, PROLONG, RES);
     static constexpr int HY = (LAST + 1) & ~1;  // halo rows (even: rows start on red parity)
     static constexpr int W = LAST >= 7 ? 14 : 10;  // register window (rows), even
     static constexpr int D = W - LAST - 2;      // prefetch distance (rows)
     static constexpr int WC = W / 2;            // coarse-row window
     static constexpr int DC = WC - 3;           // coarse prefetch distance
-    static constexpr int OUTW = march_outw(NU, PROLONG, POST != 0);  // output columns per tile
+    static constexpr int OUTW = march_outw(NU, PROLONG, RES);  // output columns per tile
     // Rows are stored as 16-byte aligned pairs (cells x0 - 1, x0 of lane x0),
     // which needs the column on either side of the output to be correct too:
     // true when the halo has a column to spare beyond the last stage.
-    static constexpr bool PAIRST = HX >= 2 * NU + (PROLONG ? 2 : 0) + 1;
+    static constexpr bool PAIRST = HX >= 2 * NU + ((PROLONG && !VISIT) ? 2 : 0) + 1;
     static_assert(D >= 1 && DC >= 0, "window too small");
+    static_assert(!VISIT || (NU == 4 && PROLONG), "a visit runs 2 + 2 iterations around the prolongation");
 };
 
 // Per-wave description of the tile, computed once by the kernel entry.
@@ -237,16 +251,23 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     static_assert(!FUSED || NU == 4, "the fused launch runs 2 + 2 iterations");
     double accN0 = 0.0, accN1 = 0.0;
     T SA[2] = {T(0), T(0)}, SB[2] = {T(0), T(0)};
+    // VISIT: the pre-smoothed row below the one being pre-smoothed
+    T SV0 = T(0), SV1 = T(0);
 
     static_for<0, D>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         load_row(ys + k, P0[k], P1[k], F0[k], F1[k]);
         if constexpr (IR) load_row64(ys + k, Q0[k], Q1[k], G0[k], G1[k]);
     });
+    // Coarse rows sit in a ring: coarse row R in slot (R - ys/2 + 1) mod WC.
+    // The prolongation of fine row y reads coarse rows y/2 - 1 .. y/2 + 1; it
+    // runs on row t at step t, or (VISIT) on row t - NU after the
+    // pre-smoothing, so there the ring starts two coarse rows lower.
+    constexpr int CLAG = C::VISIT ? NU / 2 : 0;
     if constexpr (PROLONG) {
         static_for<0, DC + 2>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            load_coarse((ys >> 1) - 1 + q, Cw[q]);
+            load_coarse((ys >> 1) - 1 - CLAG + q, Cw[(q - CLAG + WC) % WC]);
         });
     }
 
@@ -268,7 +289,8 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 if constexpr (IR) load_row64(t + D, Q0[kd], Q1[kd], G0[kd], G1[kd]);
             }
             if constexpr (PROLONG) {
-                if constexpr ((k & 1) == 0) load_coarse((t >> 1) + 1 + DC, Cw[((k >> 1) + 2 + DC) % WC]);
+                if constexpr ((k & 1) == 0)
+                    load_coarse((t >> 1) + 1 - CLAG + DC, Cw[((k >> 1) + 2 - CLAG + DC) % WC]);
             }
             // 2. finish the load of row t: mean shifts, prolongation (done for
             // every step: past the band it only touches halo slots)
@@ -294,11 +316,14 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 P0[k] = T(0);
                 P1[k] = T(0);
             }
-            if constexpr (PROLONG) {
-                const int J = t >> 1;
-                T cm = Cw[((k >> 1) + 0) % WC];
-                const T c0 = Cw[((k >> 1) + 1) % WC];
-                T cp = Cw[((k >> 1) + 2) % WC];
+            // prolongation of the coarse correction into row t - CLAG * 2
+            // (slot kq): e + slopes, the cell's quarter offsets
+            auto prolong = [&]() {
+                constexpr int kq = (k - 2 * CLAG + 2 * W) % W;
+                const int J = (t - 2 * CLAG) >> 1;
+                T cm = Cw[((k >> 1) - CLAG + 0 + WC) % WC];
+                const T c0 = Cw[((k >> 1) - CLAG + 1 + WC) % WC];
+                T cp = Cw[((k >> 1) - CLAG + 2 + WC) % WC];
                 if constexpr (YBR) {
                     if (J - 1 < 0) cm = syl * cm;    // coarse ghost row below
                     if (J + 1 >= nc) cp = syh * cp;  // coarse ghost row above
@@ -310,10 +335,11 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 }
                 const T mx = T(0.5) * (ee - ew);
                 const T my = T(0.5) * (cp - cm);
-                const T dy = (k & 1) ? T(0.25) : T(-0.25);
-                P0[k] = P0[k] + ((c0 + T(-0.25) * mx) + dy * my);
-                P1[k] = P1[k] + ((c0 + T(0.25) * mx) + dy * my);
-            }
+                const T dy = (k & 1) ? T(0.25) : T(-0.25);  // row t - 2 CLAG has t's parity
+                P0[kq] = P0[kq] + ((c0 + T(-0.25) * mx) + dy * my);
+                P1[kq] = P1[kq] + ((c0 + T(0.25) * mx) + dy * my);
+            };
+            if constexpr (PROLONG && !C::VISIT) prolong();
             // 3. relaxation stages: stage s works on row t - s; odd s = red, even s = black.
             // Unconditional: a stage on a row outside [ys, ye) writes a slot that
             // either is reloaded before it is read again (rows below ys) or only
@@ -334,6 +360,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.wedge) w = sxl * self;
                     }
                     T nn = P0[kp], ss = P0[km];
+                    if constexpr (C::VISIT && s == NU) ss = SV0;  // row below, before its prolongation
                     if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
@@ -347,6 +374,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e = sxh * self;
                     }
                     T nn = P1[kp], ss = P1[km];
+                    if constexpr (C::VISIT && s == NU) ss = SV1;  // row below, before its prolongation
                     if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
@@ -399,6 +427,16 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     SB[sv] = p1;
                 }
                 static_for<5, 2 * NU + 1>(stage);
+            } else if constexpr (C::VISIT) {
+                // stages 1 .. NU finish the pre-smoothing of row t - NU; its
+                // values are kept (the last pre-smoothing stage of the next
+                // row reads them) before the prolongation adds to them
+                static_for<1, NU + 1>(stage);
+                constexpr int kq = (k - NU + 2 * W) % W;
+                SV0 = P0[kq];
+                SV1 = P1[kq];
+                prolong();
+                static_for<NU + 1, 2 * NU + 1>(stage);
             } else {
                 static_for<1, 2 * NU + 1>(stage);
             }
@@ -452,7 +490,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         acc2 += (double)q0 + (double)q1;
                     }
                 }
-            } else if constexpr (POST != POST_NONE) {
+            } else if constexpr (C::RES) {
                 const int y = t - C::LAGR;
                 if (inrow(y)) {
                     constexpr int kk = (k - C::LAGR + 2 * W) % W;

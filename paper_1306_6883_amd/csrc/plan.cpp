@@ -163,6 +163,16 @@ MarchShape shape_for(int n) {
     return s;
 }
 
+// Default shape of a visit launch: its bands carry 8 halo rows on either
+// side, so they are taller.
+MarchShape visit_shape_for(int n) {
+    MarchShape s;
+    s.wpb = 1;
+    const int ty = n >= 4096 ? 128 : (n >= 512 ? 64 : 32);
+    s.ty = ty < n ? ty : n;
+    return s;
+}
+
 }  // namespace
 
 // Events bracketing finest-level launches while profiling is on.
@@ -183,6 +193,11 @@ struct ccmg_plan {
     ccmg_problem p;
     KernelTimer timer;
     MarchShape shp_pre[kMaxLevels], shp_post[kMaxLevels];  // launch shape per level (autotuned)
+    // a level run as a visit: its restricting launch without the stored
+    // iterate, and the visit launch (recomputed pre-smoothing, prolongation,
+    // post-smoothing); visit[l]: the autotuner found the pair faster
+    MarchShape shp_pre_v[kMaxLevels], shp_visit[kMaxLevels];
+    bool visit[kMaxLevels] = {};
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     // options (ccmg_plan_set_option)
@@ -191,6 +206,7 @@ struct ccmg_plan {
                                     // within this factor of the tolerance
     int opt_mixed_inner = 3;     // most FP32 cycles per refinement step
     int opt_fmg = 0;             // FMG start of FP64 solves without a guess: V-cycles per level (0: off)
+    int opt_visit = 1;           // coarse levels as visits: 0 never, 1 where autotuned, 2 wherever they apply
     int n_bottom = 2;  // 4 or 8: exact solve on that level (ccmg_plan_set_bottom)
     int tcycle = 0;    // cycle being enqueued by the solve loop (tags timed launches)
     double *hrho = nullptr;   // host-mapped: relative residual of each cycle
@@ -268,6 +284,18 @@ bool fused_eligible(const ccmg_plan *P) {
 int mixed_inner_max(const ccmg_plan *P) {
     if (P->p.prec != CCMG_MIXED || P->lay.lt < 1 || P->p.nu1 != 2 || P->p.nu2 != 2) return 1;
     return P->opt_mixed_inner;
+}
+// Level l (below the finest, above the one-workgroup tail) may run as a visit
+// in V(2,2) cycles: where its correction starts from zero, the restricting
+// launch of the way down stores no iterate and one launch on the way up
+// recomputes the two pre-smoothing iterations, adds the prolongated
+// correction and runs the two post-smoothing iterations (the same arithmetic
+// per cell: iterates are bitwise those of the two-launch form, and each cell
+// of the level is written and read once less).
+bool visit_level(const ccmg_plan *P, int l) {
+    if (l < 1 || l >= P->lay.lt || l >= kMaxLevels || P->p.nu1 != 2 || P->p.nu2 != 2 || P->opt_visit == 0)
+        return false;
+    return P->opt_visit == 2 || P->visit[l];
 }
 
 }  // namespace
@@ -379,7 +407,10 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     hipError_t e;
     Buf<T> cur[kMaxLevels] = {}, other[kMaxLevels] = {};
     int fpart_count[kMaxLevels] = {};
+    bool visited[kMaxLevels] = {};
     const bool f64 = sizeof(T) == sizeof(double);
+    // visits (tuned for the precision the plan relaxes its coarse levels in)
+    const bool visits_ok = f64 == (P->p.prec == CCMG_FP64);
     *norm_tiles = 0;
 
     auto fptr = [&](int l) -> Buf<T> {
@@ -432,9 +463,11 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     if (io.coarse_only) fpart_count[1] = io.f1_count;
     for (int l = top; l < lay.lt; ++l) {
         setup_bufs(l);
-        const MarchShape sh = P->shp_pre[l];
         const NuChain chain = split_nu(P->p.nu1);
         bool zero = io.coarse_only || l > top || io.zero;
+        const bool vis = visits_ok && zero && visit_level(P, l);
+        visited[l] = vis;
+        const MarchShape sh = vis ? P->shp_pre_v[l] : P->shp_pre[l];
         for (size_t i = 0; i < chain.size(); ++i) {
             const bool last = i + 1 == chain.size();
             MarchArgs<T> a{};
@@ -445,7 +478,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
             fmean(l, a);
             a.phi_in = cur[l].p;
             a.pin = cur[l].pitch;
-            a.phi_out = other[l].p;
+            a.phi_out = vis ? nullptr : other[l].p;  // a visit recomputes this iterate
             a.pout = other[l].pitch;
             a.phi_shift = (l == 0 && i == 0 && !zero) ? io.phi_shift : nullptr;
             a.skip = io.skip;
@@ -464,7 +497,7 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
             P->tstop(ti);
             if (e != hipSuccess) return e;
             if (last) fpart_count[l + 1] = nt;
-            std::swap(cur[l], other[l]);
+            if (!vis) std::swap(cur[l], other[l]);
             zero = false;
         }
     }
@@ -492,6 +525,24 @@ hipError_t enqueue_cycle(ccmg_plan *P, const CycleIO<T> &io, int *norm_tiles) {
     }
     // up
     for (int l = lay.lt - 1; l >= top; --l) {
+        if (visited[l]) {
+            MarchArgs<T> a{};
+            level_consts(P, l, a);
+            const Buf<T> fb = fptr(l);
+            a.f = fb.p;
+            a.pf = fb.pitch;
+            fmean(l, a);
+            a.phi_out = other[l].p;
+            a.pout = other[l].pitch;
+            a.skip = io.skip;
+            a.ec = cur[l + 1].p;
+            a.pc = cur[l + 1].pitch;
+            int nt = 0;
+            e = launch_march<T>(a, 4, false, true, POST_VISIT, P->shp_visit[l], s, &nt);
+            if (e != hipSuccess) return e;
+            std::swap(cur[l], other[l]);
+            continue;
+        }
         const MarchShape sh = P->shp_post[l];
         const NuChain chain = split_nu(P->p.nu2);
         for (size_t i = 0; i < chain.size(); ++i) {
@@ -887,7 +938,11 @@ void plan_init_host(ccmg_plan *P, const ccmg_problem &p) {
     build_layout(p, P->lay);
     P->singular = p.alpha == 0.0 && p.bc[0] != CCMG_BC_DIRICHLET && p.bc[1] != CCMG_BC_DIRICHLET &&
                   p.bc[2] != CCMG_BC_DIRICHLET && p.bc[3] != CCMG_BC_DIRICHLET;
-    for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) P->shp_pre[l] = P->shp_post[l] = shape_for(P->lay.lev[l].n);
+    for (int l = 0; l < P->lay.L && l < kMaxLevels; ++l) {
+        P->shp_pre[l] = P->shp_post[l] = P->shp_pre_v[l] = shape_for(P->lay.lev[l].n);
+        P->shp_visit[l] = visit_shape_for(P->lay.lev[l].n);
+        P->visit[l] = false;
+    }
     P->shp_fused = shape_for(P->lay.lev[0].n);
     P->shp_fused32 = shape_for(P->lay.lev[0].n);
     P->n_bottom = 2;
@@ -897,6 +952,7 @@ void plan_init_host(ccmg_plan *P, const ccmg_problem &p) {
     P->opt_fused = true;
     P->opt_fused_keep = 1.0;
     P->opt_mixed_inner = 3;
+    P->opt_visit = 1;
 }
 
 // pitch >= n + 2, and the array holds fewer than 2^31 elements (the kernels
@@ -1071,7 +1127,12 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
     const int reps = 4;
     for (int l = 0; l < lay.lt && err == hipSuccess; ++l) {
         const int n = lay.lev[l].n;
-        for (int kind = 0; kind < 2 && err == hipSuccess; ++kind) {
+        // kinds 0 / 1: the level's restricting and prolongating launches;
+        // 2 / 3: the same level as a visit (restricting launch without the
+        // stored iterate, visit launch), on levels where a visit applies
+        const bool visit_ok = l >= 1 && P->p.nu1 == 2 && P->p.nu2 == 2;
+        float kbest[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int kind = 0; kind < (visit_ok ? 4 : 2) && err == hipSuccess; ++kind) {
             MarchArgs<T> a{};
             level_consts(P, l, a);
             if (l == 0 && f64) {
@@ -1090,7 +1151,8 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
             a.pin = ppa;
             a.phi_out = P->at<T>(lay.lev[l].b);
             a.pout = lay.lev[l].pitch;
-            if (kind == 0) {  // the restricting launch of the nu1 half
+            if (kind == 0 || kind == 2) {  // the restricting launch of the nu1 half
+                if (kind == 2) a.phi_out = nullptr;
                 nu = split_nu(P->p.nu1).back();
                 load_phi = l == 0 && f64;
                 prolong = false;
@@ -1098,6 +1160,14 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
                 a.aux = P->at<T>(lay.lev[l + 1].f);
                 a.paux = lay.lev[l + 1].pitch;
                 a.partial = P->at<double>(lay.lev[l + 1].fpart);
+            } else if (kind == 3) {  // the visit launch
+                nu = 4;
+                load_phi = false;
+                prolong = true;
+                post = POST_VISIT;
+                a.phi_in = nullptr;
+                a.ec = P->at<T>(lay.lev[l + 1].a);
+                a.pc = lay.lev[l + 1].pitch;
             } else {  // the prolongating launch of the nu2 half
                 nu = split_nu(P->p.nu2).front();
                 load_phi = true;
@@ -1124,22 +1194,25 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
                 }
             }
             float best = 1e30f;
-            MarchShape bs = kind == 0 ? P->shp_pre[l] : P->shp_post[l];
+            MarchShape *const slot[4] = {&P->shp_pre[l], &P->shp_post[l], &P->shp_pre_v[l], &P->shp_visit[l]};
+            MarchShape bs = *slot[kind];
             // candidates: row-march shapes (powers of two, and bands that
             // balance the waves over the SIMDs), and (levels below the finest)
-            // the 2-D LDS tile kernel, written as ty = 0
-            const bool tile_ok = l > 0 && n >= kTileMinN;
+            // the 2-D LDS tile kernel, written as ty = 0 (not for the visit
+            // launch, whose bands need 8 halo rows a side: none below 16 rows)
+            const bool tile_ok = l > 0 && n >= kTileMinN && kind != 3;
             std::vector<MarchShape> cands;
             for (int ty : tys) {
                 if (ty == 0) {
                     if (tile_ok) cands.push_back(MarchShape{0, 1});
                     continue;
                 }
-                if (ty > n) continue;
+                if (ty > n || (kind == 3 && ty < 16 && ty < n)) continue;
                 for (int wpb : wpbs) cands.push_back(MarchShape{ty < n ? ty : n, wpb});
             }
-            for (int ty : balanced_tys(n, march_outw(nu, prolong, post != POST_NONE), P->simds, 4, xwalls))
-                cands.push_back(MarchShape{ty, 1});
+            const bool res = post != POST_NONE && post != POST_VISIT;
+            for (int ty : balanced_tys(n, march_outw(nu, prolong, res), P->simds, 4, xwalls))
+                if (kind != 3 || ty >= 16) cands.push_back(MarchShape{ty, 1});
             for (const MarchShape &sh : cands) {
                 {
                     int nt;
@@ -1159,9 +1232,11 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
                 }
                 if (err != hipSuccess) break;
             }
-            if (kind == 0) P->shp_pre[l] = bs;
-            else P->shp_post[l] = bs;
+            *slot[kind] = bs;
+            kbest[kind] = best;
         }
+        // the visit pair replaces the two launches where it is faster
+        if (err == hipSuccess && l < kMaxLevels) P->visit[l] = visit_ok && kbest[2] + kbest[3] < kbest[0] + kbest[1];
     }
     // the fused finest launch (FP64 plans that use it; MIXED plans with
     // several inner cycles per step, in FP32 without norm or kept iterate)
@@ -1239,8 +1314,21 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
 }
 
 int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
-    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 3) return CCMG_EINVAL;
-    if (kind >= 2) {  // the fused finest launch (FP64 / FP32)
+    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 5) return CCMG_EINVAL;
+    if (kind == 5) {  // the visit launch; ty = 0: the level runs its two launches instead
+        if (level == 0 || level >= P->lay.lt) return CCMG_EINVAL;
+        const int n = P->lay.lev[level].n;
+        if (ty == 0) {
+            P->visit[level] = false;
+            return CCMG_OK;
+        }
+        if (ty < 2 || (ty & 1) || (ty < 16 && ty < n) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
+        P->shp_visit[level] = MarchShape{ty < n ? ty : n, wpb};
+        P->visit[level] = true;
+        return CCMG_OK;
+    }
+    if (kind == 4 && (level == 0 || level >= P->lay.lt)) return CCMG_EINVAL;
+    if (kind == 2 || kind == 3) {  // the fused finest launch (FP64 / FP32)
         const int n = P->lay.lev[0].n;
         if (level != 0 || ty < 2 || (ty & 1) || (ty < kMinTy && ty < n) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
         const MarchShape sh{ty < n ? ty : n, wpb};
@@ -1250,8 +1338,7 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     }
     if (ty == 0) {  // the 2-D LDS tile kernel: levels below the finest that are not in the tail
         if (level == 0 || level >= P->lay.lt || P->lay.lev[level].n < kTileMinN) return CCMG_EINVAL;
-        if (kind == 0) P->shp_pre[level] = MarchShape{0, 1};
-        else P->shp_post[level] = MarchShape{0, 1};
+        (kind == 0 ? P->shp_pre : kind == 1 ? P->shp_post : P->shp_pre_v)[level] = MarchShape{0, 1};
         return CCMG_OK;
     }
     if (ty < 2 || (ty & 1) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
@@ -1259,8 +1346,24 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
     const int n = P->lay.lev[level].n;
     if (ty < kMinTy && ty < n) return CCMG_EINVAL;
     MarchShape sh{ty < n ? ty : n, wpb};
-    if (kind == 0) P->shp_pre[level] = sh;
-    else P->shp_post[level] = sh;
+    (kind == 0 ? P->shp_pre : kind == 1 ? P->shp_post : P->shp_pre_v)[level] = sh;
+    return CCMG_OK;
+}
+
+int ccmg_plan_shape(ccmg_plan *P, int level, int kind, int *ty, int *wpb) {
+    if (!P || !ty || !wpb || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 5)
+        return CCMG_EINVAL;
+    if ((kind == 2 || kind == 3) && level != 0) return CCMG_EINVAL;
+    if ((kind == 4 || kind == 5) && (level == 0 || level >= P->lay.lt)) return CCMG_EINVAL;
+    const MarchShape sh = kind == 0   ? P->shp_pre[level]
+                          : kind == 1 ? P->shp_post[level]
+                          : kind == 2 ? P->shp_fused
+                          : kind == 3 ? P->shp_fused32
+                          : kind == 4 ? P->shp_pre_v[level]
+                                      : P->shp_visit[level];
+    const bool none = kind == 5 && !P->visit[level];  // (0, 1): the level runs its two launches
+    *ty = none ? 0 : sh.ty;
+    *wpb = none ? 1 : sh.wpb;
     return CCMG_OK;
 }
 
@@ -1283,6 +1386,10 @@ int ccmg_plan_set_option(ccmg_plan *P, int option, double value) {
             if (value != std::floor(value) || value < 0.0 || value > 4.0) return CCMG_EINVAL;
             P->opt_fmg = (int)value;
             return CCMG_OK;
+        case CCMG_OPT_VISIT:
+            if (value != 0.0 && value != 1.0 && value != 2.0) return CCMG_EINVAL;
+            P->opt_visit = (int)value;
+            return CCMG_OK;
         default: return CCMG_EINVAL;
     }
 }
@@ -1294,6 +1401,7 @@ int ccmg_plan_get_option(ccmg_plan *P, int option, double *value) {
         case CCMG_OPT_FUSED_KEEP: *value = P->opt_fused_keep; return CCMG_OK;
         case CCMG_OPT_MIXED_INNER: *value = (double)P->opt_mixed_inner; return CCMG_OK;
         case CCMG_OPT_FMG: *value = (double)P->opt_fmg; return CCMG_OK;
+        case CCMG_OPT_VISIT: *value = (double)P->opt_visit; return CCMG_OK;
         default: return CCMG_EINVAL;
     }
 }

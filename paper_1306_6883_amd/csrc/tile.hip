@@ -12,6 +12,10 @@
 // the same order as in the row march, so both give the same bits.
 #include "internal.h"
 
+// Products fused into additions only within one expression, as in the row
+// march: both kernels give the same bits for any operator.
+#pragma clang fp contract(on)
+
 namespace ccmg {
 
 namespace {
@@ -187,8 +191,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const MarchArgs<T> a) {
         __syncthreads();
     }
 
-    // 3. the block's cells out
-    for (int k = tid; k < TS * TS; k += kTileThreads) {
+    // 3. the block's cells out (unless the iterate is not wanted: a level run
+    // as a visit recomputes it on the way up)
+    for (int k = tid; a.phi_out && k < TS * TS; k += kTileThreads) {
         const int j = k / TS, i = k - j * TS;
         const int gx = X0 + i, gy = Y0 + j;
         a.phi_out[(long)(gy + 1) * a.pout + 1 + gx] = u[H + j][H + i];

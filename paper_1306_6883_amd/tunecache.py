@@ -20,7 +20,8 @@ import tempfile
 
 import torch
 
-from . import (LIB_PATH, Plan, ccmg_plan_autotune, ccmg_plan_fused_shape, ccmg_plan_set_shape, ccmg_plan_shapes)
+from . import (LIB_PATH, Plan, ccmg_plan_autotune, ccmg_plan_fused_shape, ccmg_plan_set_shape, ccmg_plan_shape,
+               ccmg_plan_shapes)
 
 _lib_digest = None
 
@@ -74,11 +75,20 @@ def _store(path: str, data: dict) -> None:
     os.replace(tmp, path)
 
 
+def _row_march_levels(plan: Plan) -> int:
+    """Levels above the one-workgroup tail (those of more than 32 x 32 cells)."""
+    return max(0, plan.n.bit_length() - 1 - 5)
+
+
 def shapes_of(plan: Plan) -> dict:
     """The plan's launch shapes: per level (pre ty, pre wpb, post ty, post
-    wpb) and the fused finest launch in FP64 and FP32."""
+    wpb), the fused finest launch in FP64 and FP32, and per level below the
+    finest its visit shapes (restricting ty, wpb, visit ty, wpb; visit ty 0:
+    the level runs its two launches)."""
     return {"levels": [list(s) for s in ccmg_plan_shapes(plan)],
-            "fused64": list(ccmg_plan_fused_shape(plan, 2)), "fused32": list(ccmg_plan_fused_shape(plan, 3))}
+            "fused64": list(ccmg_plan_fused_shape(plan, 2)), "fused32": list(ccmg_plan_fused_shape(plan, 3)),
+            "visits": [[*ccmg_plan_shape(plan, lv, 4), *ccmg_plan_shape(plan, lv, 5)]
+                       for lv in range(1, _row_march_levels(plan))]}
 
 
 def apply_shapes(plan: Plan, shapes: dict) -> None:
@@ -87,6 +97,9 @@ def apply_shapes(plan: Plan, shapes: dict) -> None:
         ccmg_plan_set_shape(plan, level, 1, tq, wq)
     ccmg_plan_set_shape(plan, 0, 2, *shapes["fused64"])
     ccmg_plan_set_shape(plan, 0, 3, *shapes["fused32"])
+    for level, (tp, wp, tv, wv) in enumerate(shapes.get("visits", []), start=1):
+        ccmg_plan_set_shape(plan, level, 4, tp, wp)
+        ccmg_plan_set_shape(plan, level, 5, tv, wv)
 
 
 def tuned(plan: Plan, f: torch.Tensor, phi: torch.Tensor, path: str) -> tuple:

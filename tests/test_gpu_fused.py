@@ -101,7 +101,13 @@ def test_fused_solve_with_guess_and_helmholtz(bc):
         r1, p1, _ = solve(n, bc, fv, guess, **kw)
         assert r0.status == r1.status == cc.OK and r0.cycles == r1.cycles
         a, b = valid(p0), valid(p1)
-        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+        if exact.is_singular(kw.get("alpha", 0.0), bc):
+            # the unfused cycles shift phi by its mean between cycles: rounding only
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+        else:
+            # products fuse into sums only within an expression, so values kept
+            # in registers across stages round as after a store: the same bits
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("bc", ["DDDD", "PPPP", "DNPP"])

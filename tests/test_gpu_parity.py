@@ -101,15 +101,12 @@ def test_restrict_residual_matches_oracle(bc, n):
     assert np.max(np.abs(got - oracle.interior(want))) < 1e-12 * np.max(np.abs(oracle.interior(f)))
 
 
-@pytest.mark.parametrize("n", [2, 4, 64, 512, 2048])
-@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("n,level", [(4, 0), (8, 1), (64, 0), (64, 1), (512, 0), (512, 1), (2048, 0), (2048, 1)])
 def test_restrict_matches_oracle(n, level):
     """The standalone four-cell average (Sec. 3.3) equals the oracle's
     restriction bit for bit (same additions in the same order), on the finest
-    level and the one below it; the coarse ghosts and the fine array are left
-    alone."""
-    if n >> level < 4:
-        pytest.skip("no coarser level: the hierarchy ends at 2 x 2")
+    level and the one below it, down to the 2 x 2 level that ends the
+    hierarchy; the coarse ghosts and the fine array are left alone."""
     plan = plan_for(n, "DDDD")
     nl = n >> level
     fine = rand(nl, 30 + nl)

@@ -1,0 +1,160 @@
+"""Coarse levels run as visits (CCMG_OPT_VISIT): the restricting launch of the
+way down stores no iterate, and one launch on the way up recomputes the two
+pre-smoothing iterations from zero, adds the prolongated correction and runs
+the two post-smoothing iterations.  Every cell sees the same arithmetic in the
+same order, so iterates are bitwise those of the two-launch form (for any
+launch shapes), and V-cycles match the oracle's (Sec. 3.3) to rounding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_1306_6883_amd")
+
+BCS = ["PPPP", "DDDD", "NNNN", "DNPP", "PPND", "DDNN"]
+
+
+def dev_field(a):
+    n = a.shape[0] - 2
+    t = torch.zeros((n + 2, n + 2 + 5), dtype=torch.float64, device="cuda")
+    t[:, :n + 2] = torch.from_numpy(a).cuda()
+    return t
+
+
+def host(t):
+    n = t.shape[0] - 2
+    return t[:, :n + 2].cpu().numpy()
+
+
+def rhs(n, seed, singular):
+    f = W.fourier_modes(n, seed=seed, count=16, kmax=8) + np.random.default_rng(seed).standard_normal((n, n)) * 0.1
+    return f - f.mean() if singular else f + 0.2
+
+
+def solve(n, bc, f, visit, prec=None, fused=1, alpha=0.0, beta=-1.0, shapes=None, fmg=0):
+    kw = {} if prec is None else {"prec": prec}
+    plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc), alpha=alpha, beta=beta, rtol=1e-10, **kw))
+    cc.ccmg_plan_set_option(plan, cc.OPT_VISIT, visit)
+    if prec is None:
+        cc.ccmg_plan_set_option(plan, cc.OPT_FUSED, fused)
+        cc.ccmg_plan_set_option(plan, cc.OPT_FMG, fmg)
+    if shapes:
+        shapes(plan)
+    phi = dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, dev_field(oracle.embed(f)), phi)
+    torch.cuda.synchronize()
+    return host(phi), r
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [64, 128, 512, 2048])
+@pytest.mark.parametrize("form", ["fused", "unfused", "mixed", "fmg"])
+def test_visit_bitwise_equal_to_two_launches(bc, n, form):
+    """Whole solves (FP64 with and without the fused finest launch, from
+    zero and from the full multigrid start; MIXED, whose coarse levels relax
+    in FP32): the same result, history and cycle count to the bit."""
+    singular = "D" not in bc
+    f = rhs(n, 3, singular)
+    kw = {"mixed": {"prec": cc.MIXED}, "unfused": {"fused": 0}, "fmg": {"fmg": 1}}.get(form, {})
+    a, ra = solve(n, bc, f, 0, **kw)
+    b, rb = solve(n, bc, f, 2, **kw)
+    assert ra.status == rb.status == cc.OK and ra.cycles == rb.cycles
+    assert np.array_equal(np.array(ra.history[:ra.cycles + 1]), np.array(rb.history[:rb.cycles + 1]), equal_nan=True)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("c", [0.1, 1.0, 10.0])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_visit_helmholtz_bitwise(c, fused):
+    """Helmholtz (the diagonal 1/(alpha + 4 beta/h^2) is no power of two, so
+    any change in how products fuse into sums would show)."""
+    n = 1024
+    beta = c / (2.0 * n * n)
+    f = rhs(n, 5, False)
+    a, ra = solve(n, "DNPP", f, 0, alpha=1.0, beta=beta, fused=fused)
+    b, rb = solve(n, "DNPP", f, 2, alpha=1.0, beta=beta, fused=fused)
+    assert ra.status == rb.status == cc.OK and ra.cycles == rb.cycles
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("n", [64, 256, 512])
+def test_visit_vcycle_iterates_match_oracle(bc, n):
+    """Three V-cycles with every level below the finest run as a visit,
+    against the oracle's V-cycle after each cycle."""
+    plan = cc.Plan(cc.Problem(n=n, bc=tuple(bc)))
+    cc.ccmg_plan_set_option(plan, cc.OPT_VISIT, 2)
+    p = oracle.Problem(n=n, h=1.0 / n, bc=tuple(bc))
+    f = oracle.embed(np.random.default_rng(12).standard_normal((n, n)))
+    if p.singular:
+        f = oracle.embed(oracle.interior(f) - oracle.interior(f).mean())
+    phi = oracle.embed(np.random.default_rng(13).standard_normal((n, n)))
+    d_f, d_phi = dev_field(f), dev_field(phi)
+    ref = phi.copy()
+    for k in range(3):
+        cc.ccmg_vcycle(plan, d_f, d_phi)
+        oracle.vcycle(p, ref, f)
+        got, want = oracle.interior(host(d_phi)), oracle.interior(ref)
+        err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+        assert err < 1e-11, (k, err)
+
+
+@pytest.mark.parametrize("bc", ["DDDD", "PPPP", "NDDN"])
+def test_visit_shape_invariance(bc):
+    """Visit launches in bands of any height (bands that do not divide the
+    level, the halved bands of the x-edge strips, one wave or four per
+    workgroup; the restricting launch as row march or 2-D tiles) and after
+    autotuning: the same bits as the two-launch form (singular problems to
+    rounding: their coarse right-hand sides' means are sums grouped by the
+    restricting launch's tiles)."""
+    n = 1024
+    singular = "D" not in bc
+    f = rhs(n, 7, singular)
+    ref, r0 = solve(n, bc, f, 0)
+
+    def fixed(ty4, w4, ty5, w5):
+        def apply(plan):
+            for level in range(1, 5):  # 512^2 .. 64^2
+                cc.ccmg_plan_set_shape(plan, level, 4, ty4, w4)
+                cc.ccmg_plan_set_shape(plan, level, 5, ty5, w5)
+            assert cc.ccmg_plan_shape(plan, 1, 5)[0] == min(ty5, 512)
+        return apply
+
+    def tuned(plan):
+        src = dev_field(oracle.embed(f))
+        cc.ccmg_plan_autotune(plan, src, dev_field(oracle.field_zeros(n)))
+
+    for shapes in (fixed(16, 1, 16, 1), fixed(48, 4, 80, 2), fixed(0, 1, 130, 1), fixed(256, 2, 512, 4), tuned):
+        got, r = solve(n, bc, f, 2 if shapes is not tuned else 1, shapes=shapes)
+        assert r.status == cc.OK and r.cycles == r0.cycles
+        if singular:
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        else:
+            assert np.array_equal(got, ref)
+
+
+def test_visit_options_and_shapes_rejected():
+    plan = cc.Plan(cc.Problem(n=512, bc="D"))
+    assert cc.ccmg_plan_get_option(plan, cc.OPT_VISIT) == 1.0
+    for v in (-1, 0.5, 3):
+        with pytest.raises(cc.CcmgError):
+            cc.ccmg_plan_set_option(plan, cc.OPT_VISIT, v)
+    # an untuned plan runs no visits under the default option
+    assert all(cc.ccmg_plan_shape(plan, level, 5)[0] == 0 for level in range(1, 4))
+    # levels 1 .. 3 (256^2 .. 64^2) only; visit bands even, >= 16 unless they cover the level
+    for level, kind, ty, wpb in ((0, 4, 64, 1), (0, 5, 64, 1), (4, 5, 32, 1), (4, 4, 32, 1), (1, 5, 10, 1),
+                                 (1, 5, 33, 1), (1, 5, 64, 5), (1, 4, 7, 1), (1, 6, 64, 1)):
+        with pytest.raises(cc.CcmgError):
+            cc.ccmg_plan_set_shape(plan, level, kind, ty, wpb)
+    with pytest.raises(cc.CcmgError):
+        cc.ccmg_plan_shape(plan, 0, 5)
+    cc.ccmg_plan_set_shape(plan, 2, 5, 128, 1)  # 128 rows cover the 128^2 level
+    assert cc.ccmg_plan_shape(plan, 2, 5) == (128, 1)
+    cc.ccmg_plan_set_shape(plan, 2, 5, 0, 1)
+    assert cc.ccmg_plan_shape(plan, 2, 5)[0] == 0
+    cc.ccmg_plan_set_shape(plan, 3, 4, 0, 1)  # 2-D tiles for the restricting launch of 64^2
+    assert cc.ccmg_plan_shape(plan, 3, 4) == (0, 1)
