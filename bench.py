@@ -75,6 +75,8 @@ def measure(cc, torch, n, bc, fv, steps, warmup, fused_shape=None):
         cc.ccmg_plan_set_shape(plan, 0, 2, fused_shape[0], fused_shape[1])
     shapes = cc.ccmg_plan_shapes(plan)
     fused_shape = cc.ccmg_plan_fused_shape(plan, 2)
+    # levels 1 .. (those above the 32^2 tail) run as visits where ty > 0
+    visits = [cc.ccmg_plan_shape(plan, lv, 5) for lv in range(1, n.bit_length() - 1 - 5)]
     for _ in range(warmup):
         r = cc.ccmg_solve(plan, f, phi)
         assert r.status == cc.OK, r
@@ -87,7 +89,7 @@ def measure(cc, torch, n, bc, fv, steps, warmup, fused_shape=None):
     out = dict(n=n, bc=bc, seconds=dt, solves=steps, cycles=cycles,
                cycles_per_solve=cycles / steps, ms_per_solve=1e3 * dt / steps,
                pts_cycles_per_s=n * n * cycles / dt, rel_resid=res[-1].rel_resid,
-               history=res[-1].history, kernels=stats, shapes=shapes, fused_shape=fused_shape)
+               history=res[-1].history, kernels=stats, shapes=shapes, fused_shape=fused_shape, visits=visits)
     del plan, f, phi
     torch.cuda.empty_cache()
     return out
@@ -602,6 +604,8 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=256, help="held-out seeds the learned leg evaluates on")
     ap.add_argument("--next-rows-only", action="store_true",
                     help="only the Crank-Nicolson, side-data and projection legs (one JSON line of their own)")
+    ap.add_argument("--fmg-only", action="store_true",
+                    help="only the full multigrid start leg (one JSON line of its own; profiling aid)")
     ap.add_argument("--fused-shape", type=str, default=None,
                     help="TY,WPB: rows per band and waves per workgroup of the headline's fused launch, "
                          "instead of the autotuner's choice (for counter runs)")
@@ -632,6 +636,9 @@ def main():
     if args.learned_only:
         print(json.dumps({"learned": learned_vs_plain(cc, torch, W, args.learned_solves, args.learned_steps,
                                                       args.learned_eval)}), flush=True)
+        return
+    if args.fmg_only:
+        print(json.dumps({"fmg_start": fmg_start(cc, torch, W, 10)}), flush=True)
         return
     if args.next_rows_only:
         print(json.dumps({"cn_diffusion": cn_diffusion(cc, torch, 10), "side_data": side_data_solves(cc, torch, W, 5),
@@ -668,7 +675,7 @@ def main():
         also["periodic_4096"] = dict(ms_per_solve=round(m4["ms_per_solve"], 4),
                                      cycles_per_solve=m4["cycles_per_solve"],
                                      value=m4["pts_cycles_per_s"], rel_resid=m4["rel_resid"],
-                                     roofline=rl4, fused_shape=m4["fused_shape"])
+                                     roofline=rl4, fused_shape=m4["fused_shape"], visits=m4["visits"])
         log(f"{n4}^2: {m4['ms_per_solve']:.3f} ms/solve, {m4['pts_cycles_per_s'] / 1e9:.2f} G; "
             f"{rl4['kernel']} {rl4['achieved']} GB/s" +
             (f", counter bytes {rl4['traffic_gbs']} GB/s" if rl4["traffic_gbs"] else ""))
@@ -716,7 +723,9 @@ def main():
         "roofline_detail": {k: rl[k] for k in ("kernel", "avg_launch_ms", "bytes_per_launch", "traffic_gbs", "traffic_frac",
                                                         "all_kernels")},
         "launch_shapes": {"levels": "finest first; (rows per band, waves per workgroup) of the nu1 and nu2 launches",
-                          "value": m["shapes"], "fused": m["fused_shape"]},
+                          "value": m["shapes"], "fused": m["fused_shape"],
+                          "visits": "levels 1, 2, ...: shape of the visit launch, (0, 1) where the level runs "
+                                    "its two launches", "visit_value": m["visits"]},
         "cpu_baseline": cpu,
         "also": also,
     }
