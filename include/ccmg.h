@@ -130,7 +130,10 @@ int ccmg_plan_destroy(ccmg_plan *plan);
  * `out` may be NULL.  FP64 plans with nu1 = nu2 = 2 and more than 32 cells
  * per side run the finest level's post-smoothing of one cycle and
  * pre-smoothing of the next in one launch (the same iterates; see
- * CCMG_OPT_FUSED). */
+ * CCMG_OPT_FUSED); from a zero start they also take f's statistics (for the
+ * checks above and ||f||) in the first cycle's first launch and check them
+ * after that cycle.  On an error status (CCMG_EINCOMPAT, CCMG_ENONFINITE,
+ * ...) d_phi's contents are unspecified. */
 int ccmg_solve(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
                ccmg_result *out);
 

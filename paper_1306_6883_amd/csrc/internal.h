@@ -75,6 +75,10 @@ struct MarchArgs {
     T *phi_mid;
     int pmid;
     double *partial_norm;
+    // POST_RESTRICT: if set, per tile (4 * tile + q) the statistics of f over
+    // the tile's output cells: sum f, sum |f|, sum f^2 over finite values and
+    // the count of non-finite ones (f as loaded, before any mean shift)
+    double *fstat_part;
 };
 
 // One unit of work of a batched launch: tile `tile` of level descriptor `desc`.
@@ -211,6 +215,8 @@ hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, in
 hipError_t launch_fstats_restrict(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
                                   double *coarse, long pc, hipStream_t s);
 hipError_t launch_set(double *p, int count, double v, hipStream_t s);
+// out4[q] = sum over i < count of partial[4 i + q], in a fixed order (one workgroup).
+hipError_t launch_reduce4(const double *partial, int count, double *out4, hipStream_t s);
 hipError_t launch_set_int(int *p, int count, int v, hipStream_t s);
 // coarse = four-cell average of fine (valid cells; nc cells per side of the coarse level).
 hipError_t launch_restrict(const double *fine, long pf, double *coarse, long pc, int nc, hipStream_t s);

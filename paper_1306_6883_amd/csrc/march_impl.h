@@ -245,6 +245,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
 
     double acc0 = 0.0, acc1 = 0.0;
     T rprev0 = T(0), rprev1 = T(0);
+    // POST_RESTRICT with fstat_part: statistics of f over the output cells
+    const bool fst = POST == POST_RESTRICT && a.fstat_part != nullptr;
+    double fs = 0.0, fa = 0.0, f2 = 0.0, fbad = 0.0;
     // POST_FUSED: norm sums after the post-smoothing, and that state of the
     // previous row (the row below the one whose residual is taken)
     constexpr bool FUSED = POST == POST_FUSED;
@@ -519,6 +522,21 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
                     const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
                     const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
+                    if constexpr (POST == POST_RESTRICT) {
+                        if (fst && tl.outl) {
+                            auto add = [&](double v) {
+                                if (!isfinite(v)) {
+                                    fbad += 1.0;
+                                } else {
+                                    fs += v;
+                                    fa += fabs(v);
+                                    f2 += v * v;
+                                }
+                            };
+                            add((double)F0[kk]);
+                            add((double)F1[kk]);
+                        }
+                    }
                     if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
                         if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
                             const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
@@ -570,6 +588,15 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
+        if (fst) {
+            const double q0 = wave_sum(fs), q1 = wave_sum(fa), q2 = wave_sum(f2), q3 = wave_sum(fbad);
+            if (lane == 0) {
+                a.fstat_part[4 * tile + 0] = q0;
+                a.fstat_part[4 * tile + 1] = q1;
+                a.fstat_part[4 * tile + 2] = q2;
+                a.fstat_part[4 * tile + 3] = q3;
+            }
+        }
         if constexpr (FUSED) {
             const double s0 = wave_sum(accN0), s1 = wave_sum(accN1);
             if (lane == 0 && a.partial_norm) {

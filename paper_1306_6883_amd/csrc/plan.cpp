@@ -138,7 +138,9 @@ bool build_layout(const ccmg_problem &p, Layout &lay) {
     lay.normpart = take(sizeof(double) * 2 * lay.normpart_cap);
     lay.part3 = take(sizeof(double) * lay.normpart_cap);
     lay.part3b = take(sizeof(double) * lay.normpart_cap);
-    lay.fstats = take(sizeof(double) * 4 * kStatBlocks);
+    // f statistics: per workgroup of the statistics pass, or per tile of the
+    // first restricting launch of a solve (which takes them from its own loads)
+    lay.fstats = take(sizeof(double) * 4 * std::max(kStatBlocks, max_tiles(n)));
     lay.scal = take(sizeof(double) * kScal);
     lay.hist = take(sizeof(double) * CCMG_HISTORY);
     lay.flags = take(sizeof(int) * 16);
@@ -1689,6 +1691,10 @@ struct FusedCtx {
     Buf<double> next;    // the pre-smoothed iterate of the following cycle (fused end)
     Buf<double> first_ec{nullptr, 0};  // full multigrid start: the level-1 phi that the first
                                        // pre-smoothing prolongates into a zero field
+    // the first pre-smoothing also takes f's statistics (into the scalars,
+    // then copied to `stats_host`), the solve's separate pass being skipped
+    bool first_stats = false;
+    double *stats_host = nullptr;
 };
 
 // One V-cycle of the fused driver: [level-0 pre] + levels >= 1 + level-0 end
@@ -1732,9 +1738,16 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
             P->tstop(ti);
             cx.first_ec = Buf<double>{nullptr, 0};
         } else {
+            if (cx.first_stats) a.fstat_part = P->at<double>(lay.fstats);
             const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? 2.0 : 3.0) + 0.25));
             e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
             P->tstop(ti);
+            if (e == hipSuccess && cx.first_stats) {
+                e = launch_reduce4(P->at<double>(lay.fstats), nt, P->scal() + S_FSUM, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(cx.stats_host, P->scal(), sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
+                cx.first_stats = false;
+            }
         }
         if (e != hipSuccess) return e;
         cx.f1_count = nt;
@@ -1876,10 +1889,16 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (e == hipSuccess) e = launch_set(scal, kScal, 0.0, s);
     // full multigrid start: f's statistics and its restriction to level 1 from one read
     const bool fmg_f1 = P->opt_fmg > 0 && !use_guess && !mixed && lay.lt >= 1;
+    // FP64 solves from zero with the fused finest launch take f's statistics
+    // in the first pre-smoothing launch, from its own loads of f, and are
+    // checked once the first cycle has run: no separate pass, and the device
+    // does not wait for the host before the first cycle (on a bad f that
+    // cycle's results are dropped)
+    const bool stats_late = !use_guess && !mixed && P->opt_fmg == 0 && fused_eligible(P) && P->p.max_cycles > 0;
     if (e == hipSuccess && fmg_f1)
         e = launch_fstats_restrict(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM,
                                    P->at<double>(lay.lev[1].f), lay.lev[1].pitch, s);
-    else if (e == hipSuccess)
+    else if (e == hipSuccess && !stats_late)
         e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
     // full multigrid start (FP64 solves without a guess, option CCMG_OPT_FMG):
     // its last launch also gives the starting residual, as a guess's would
@@ -1908,10 +1927,12 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             e = launch_cycle_end(P->at<double>(lay.normpart), nt, n, P->singular ? 1 : 0, scal + S_F2,
                                  P->p.rtol, P->hist(), scal + S_PHIMEAN, P->done(), P->drho, s);
     }
-    if (e == hipSuccess)
+    if (e == hipSuccess && !stats_late)
         e = hipMemcpyAsync(P->hpin + CCMG_HISTORY, scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
     Buf<double> fmg_l1{nullptr, 0};
-    if (fmg_fused) {
+    if (stats_late) {
+        // checked after the first cycle (below)
+    } else if (fmg_fused) {
         // the full multigrid pass (workspace only) is queued before the host
         // waits for f's statistics: its many small launches are enqueued while
         // the device still works, and it runs while the host checks them
@@ -1924,15 +1945,25 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     }
     if (e != hipSuccess) return R->status = CCMG_EHIP;
     const double *hs = P->hpin + CCMG_HISTORY;
-    if (hs[S_FBAD] > 0 || !std::isfinite(hs[S_F2])) return R->status = CCMG_ENONFINITE;
-    if (hs[S_F2] == 0.0) {
-        // phi = 0 exactly (valid and ghost cells)
-        e = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        R->status = e == hipSuccess ? CCMG_OK : CCMG_EHIP;
-        return R->status;
+    // f's statistics: kGoOn, or the status to return (phi = 0 for a zero f),
+    // after the device work queued so far has finished
+    constexpr int kGoOn = 1 << 20;
+    auto check_f = [&]() -> int {
+        int st = kGoOn;
+        if (hs[S_FBAD] > 0 || !std::isfinite(hs[S_F2])) st = CCMG_ENONFINITE;
+        else if (hs[S_F2] == 0.0) st = CCMG_OK;
+        else if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) st = CCMG_EINCOMPAT;
+        if (st == kGoOn) return st;
+        hipError_t x = hipSuccess;
+        if (st == CCMG_OK)  // phi = 0 exactly (valid and ghost cells)
+            x = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
+        if (x == hipSuccess) x = hipStreamSynchronize(s);
+        return x == hipSuccess ? st : CCMG_EHIP;
+    };
+    if (!stats_late) {
+        const int st = check_f();
+        if (st != kGoOn) return R->status = st;
     }
-    if (P->singular && std::fabs(hs[S_FSUM]) > 1e-12 * hs[S_FABS]) return R->status = CCMG_EINCOMPAT;
 
     const double rho0 = fmg_fused ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
@@ -1950,6 +1981,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const double keep = P->opt_fused_keep;
     FusedCtx fx{Buf<double>{d_phi, pitch}, false, !guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
     if (fmg_fused) fx.first_ec = fmg_l1;
+    fx.first_stats = stats_late;
+    fx.stats_host = P->hpin + CCMG_HISTORY;
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;
@@ -2056,6 +2089,13 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             if (e != hipSuccess) break;
             e = hipEventSynchronize(P->ev_sync[k & 1]);
             if (e != hipSuccess) break;
+            if (stats_late && k == 1) {  // f's statistics came with the first cycle
+                const int st = check_f();
+                if (st != kGoOn) {
+                    std::memset(R, 0, sizeof(*R));
+                    return R->status = st;
+                }
+            }
             rho = P->hrho[k];  // written by the step's last kernel (host-mapped)
             R->history[k] = rho;
             rhos[k] = rho;

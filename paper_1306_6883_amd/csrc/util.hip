@@ -206,6 +206,11 @@ __global__ __launch_bounds__(kRed) void k_reduce4(const double *p, int count, do
     }
 }
 
+hipError_t launch_reduce4(const double *partial, int count, double *out4, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce4, dim3(1), dim3(kRed), 0, s, partial, count, out4);
+    return hipGetLastError();
+}
+
 hipError_t launch_fstats(const double *f, long pitch, int n, double *partial, int blocks, double *out4,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_fstats, dim3(blocks), dim3(kRed), 0, s, f, pitch, n, partial);

@@ -171,3 +171,38 @@ def test_plan_options_round_trip_and_reject_bad_values():
                      (cc.OPT_MIXED_INNER, 9), (99, 1), (cc.OPT_FUSED_KEEP, float("nan"))):
         with pytest.raises(cc.CcmgError):
             cc.ccmg_plan_set_option(plan, opt, bad)
+
+
+@pytest.mark.parametrize("max_cycles", [1, 2, 100])
+def test_statistics_from_the_first_cycle(max_cycles):
+    """FP64 solves from zero with the fused launch take f's statistics from
+    the first pre-smoothing launch's own loads and check them once the first
+    cycle has run: a zero f still gives phi = 0 and OK, a non-finite f
+    ENONFINITE, an incompatible singular f EINCOMPAT, and the plan then solves
+    as before (its ||f|| summed per tile instead of per workgroup: the
+    residual history agrees with the separate pass's to rounding)."""
+    n = 512
+    plan = cc.Plan(cc.Problem(n=n, bc="DDDD", rtol=1e-10, max_cycles=max_cycles))
+    phi = dev_field(np.full((n + 2, n + 2), 5.0))
+    r = cc.ccmg_solve(plan, dev_field(oracle.field_zeros(n)), phi)
+    assert r.status == cc.OK and r.cycles == 0 and torch.count_nonzero(phi[:, :n + 2]).item() == 0
+    for bad in (np.nan, np.inf, -np.inf):
+        fv = np.zeros((n, n))
+        fv[100, 7] = bad
+        with pytest.raises(cc.CcmgError) as e:
+            cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
+        assert e.value.status == cc.ENONFINITE
+    per = cc.Plan(cc.Problem(n=n, bc="PPPP", rtol=1e-10, max_cycles=max_cycles))
+    with pytest.raises(cc.CcmgError) as e:
+        cc.ccmg_solve(per, dev_field(oracle.embed(np.ones((n, n)))), phi)
+    assert e.value.status == cc.EINCOMPAT
+    fv = W.fourier_modes(n, seed=8, count=16, kmax=8) + 0.1
+    r1, p1, _ = solve(n, "DDDD", fv, options={})
+    r0, p0, _ = solve(n, "DDDD", fv, options={cc.OPT_FUSED: 0})
+    assert r1.status == r0.status == cc.OK and r1.cycles == r0.cycles
+    assert np.allclose(r1.history, r0.history, rtol=1e-13, atol=0)
+    assert np.array_equal(valid(p1), valid(p0))
+    d_phi = dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), d_phi)
+    assert r.status == (cc.OK if max_cycles == 100 else cc.NOT_CONVERGED) and r.cycles == min(max_cycles, r1.cycles)
+    assert abs(r.history[1] - r1.history[1]) <= 1e-12 * r1.history[1]
