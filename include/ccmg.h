@@ -473,6 +473,9 @@ int ccmg_plan_shapes(ccmg_plan *plan, int *ty_pre, int *wpb_pre, int *ty_post, i
  * its FP64 residual, rounded to FP32 for the next step); FP64 solves with
  * fused launches: "finest_fused" (prolongation + 2 relaxations + residual
  * norm [+ that iterate kept], then 2 relaxations + residual + restriction);
+ * "finest_fused_first" (the first such launch of a solve from zero: the
+ * first cycle's two pre-smoothing relaxations, not stored by its first
+ * launch, recomputed from f, then what "finest_fused" does);
  * MIXED steps with several inner cycles: "mixed_finest_fused" (the same in
  * FP32 between two inner cycles, without norm or kept iterate); the
  * Crank-Nicolson right-hand side "cn_rhs"; the projection's "divergence" and

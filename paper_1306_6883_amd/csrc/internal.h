@@ -23,11 +23,14 @@ enum Post {
                         // pre-smoothing of the next in one launch: after the first two iterations
                         // the residual norm (sum r^2, sum phi per tile -> partial_norm, if set) and the
                         // iterate (-> phi_mid, if set); after all four, RESTRICT as above
-    POST_VISIT = 7      // (levels below the finest, NU = 4, from zero, with prolongation) a
+    POST_VISIT = 7,     // (levels below the finest, NU = 4, from zero, with prolongation) a
                         // level's whole visit in one launch: the two pre-smoothing iterations
                         // from zero (recomputed: the restricting launch of the way down then
                         // stores no iterate), the prolongation of the coarse correction, the
                         // two post-smoothing iterations; stores the result
+    POST_FUSED0 = 8     // (finest level, NU = 6, from zero) the first fused launch of a solve
+                        // from zero: the first cycle's two pre-smoothing iterations recomputed
+                        // from zero as in POST_VISIT, then everything POST_FUSED does
 };
 
 // Arguments of one row-march launch over one grid level (see march.hip).
@@ -124,6 +127,8 @@ hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolo
 // The fused finest-level launch (POST_FUSED; march_f64_fused.hip).
 hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 hipError_t dispatch_fused(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
+// The first fused launch of a solve from zero (POST_FUSED0; march_f64_fused.hip).
+hipError_t dispatch_fused0(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 // A coarse level's whole visit (POST_VISIT; march_visit.hip).
 hipError_t dispatch_visit(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 hipError_t dispatch_visit(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);

@@ -109,28 +109,32 @@ __device__ __forceinline__ void static_for(F &&f) {
 // ---- compile-time shape of a march variant ----------------------------------
 template <int NU, bool PROLONG, int POST>
 struct Cfg {
-    // VISIT: pre-smoothing stages 1 .. NU, the prolongation, post-smoothing
-    // stages NU + 1 .. 2 NU; no residual
+    // VISIT: pre-smoothing stages 1 .. 4 from zero, the prolongation,
+    // post-smoothing stages 5 .. 8; no residual.  FUSED0: the same four
+    // stages and prolongation, then POST_FUSED's stages, norm and residual.
     static constexpr bool VISIT = POST == POST_VISIT;
+    static constexpr bool FUSED0 = POST == POST_FUSED0;
+    static constexpr int PRE0 = (VISIT || FUSED0) ? 4 : 0;  // stages before the prolongation
     static constexpr bool RES = POST != POST_NONE && !VISIT;  // a residual stage follows the relaxation
     static constexpr int LAGR = RES ? 2 * NU + 1 : 0;  // residual stage
     static constexpr int LAST = RES ? LAGR : 2 * NU;   // last stage
     // halo columns: one per stage, two (one lane) for the prolongation slope
     // (VISIT: the slope's two columns lie within the pre-smoothing's four, so
-    // the halo has a column to spare)
-    static constexpr int HX = march_halo_x(NU, PROLONG, RES);
+    // the halo has a column to spare; FUSED0 counts them there too)
+    static constexpr int HX = FUSED0 ? march_halo_x(NU, false, RES) : march_halo_x(NU, PROLONG, RES);
     static constexpr int HY = (LAST + 1) & ~1;  // halo rows (even: rows start on red parity)
-    static constexpr int W = LAST >= 7 ? 14 : 10;  // register window (rows), even
+    static constexpr int W = LAST >= 11 ? 18 : (LAST >= 7 ? 14 : 10);  // register window (rows), even
     static constexpr int D = W - LAST - 2;      // prefetch distance (rows)
     static constexpr int WC = W / 2;            // coarse-row window
     static constexpr int DC = WC - 3;           // coarse prefetch distance
-    static constexpr int OUTW = march_outw(NU, PROLONG, RES);  // output columns per tile
+    static constexpr int OUTW = 128 - 2 * HX;  // output columns per tile
     // Rows are stored as 16-byte aligned pairs (cells x0 - 1, x0 of lane x0),
     // which needs the column on either side of the output to be correct too:
     // true when the halo has a column to spare beyond the last stage.
-    static constexpr bool PAIRST = HX >= 2 * NU + ((PROLONG && !VISIT) ? 2 : 0) + 1;
+    static constexpr bool PAIRST = HX >= 2 * NU + ((PROLONG && !PRE0) ? 2 : 0) + 1;
     static_assert(D >= 1 && DC >= 0, "window too small");
     static_assert(!VISIT || (NU == 4 && PROLONG), "a visit runs 2 + 2 iterations around the prolongation");
+    static_assert(!FUSED0 || (NU == 6 && PROLONG), "FUSED0 runs 2 + 2 + 2 iterations");
 };
 
 // Per-wave description of the tile, computed once by the kernel entry.
@@ -248,10 +252,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     // POST_RESTRICT with fstat_part: statistics of f over the output cells
     const bool fst = POST == POST_RESTRICT && a.fstat_part != nullptr;
     double fs = 0.0, fa = 0.0, f2 = 0.0, fbad = 0.0;
-    // POST_FUSED: norm sums after the post-smoothing, and that state of the
-    // previous row (the row below the one whose residual is taken)
-    constexpr bool FUSED = POST == POST_FUSED;
-    static_assert(!FUSED || NU == 4, "the fused launch runs 2 + 2 iterations");
+    // POST_FUSED (and FUSED0): norm sums after the post-smoothing, and that
+    // state of the previous row (the row below the one whose residual is taken)
+    constexpr bool FUSED = POST == POST_FUSED || POST == POST_FUSED0;
+    static_assert(POST != POST_FUSED || NU == 4, "the fused launch runs 2 + 2 iterations");
     double accN0 = 0.0, accN1 = 0.0;
     T SA[2] = {T(0), T(0)}, SB[2] = {T(0), T(0)};
     // VISIT: the pre-smoothed row below the one being pre-smoothed
@@ -266,7 +270,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     // The prolongation of fine row y reads coarse rows y/2 - 1 .. y/2 + 1; it
     // runs on row t at step t, or (VISIT) on row t - NU after the
     // pre-smoothing, so there the ring starts two coarse rows lower.
-    constexpr int CLAG = C::VISIT ? NU / 2 : 0;
+    constexpr int CLAG = C::PRE0 / 2;
     if constexpr (PROLONG) {
         static_for<0, DC + 2>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -342,7 +346,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 P0[kq] = P0[kq] + ((c0 + T(-0.25) * mx) + dy * my);
                 P1[kq] = P1[kq] + ((c0 + T(0.25) * mx) + dy * my);
             };
-            if constexpr (PROLONG && !C::VISIT) prolong();
+            if constexpr (PROLONG && C::PRE0 == 0) prolong();
             // 3. relaxation stages: stage s works on row t - s; odd s = red, even s = black.
             // Unconditional: a stage on a row outside [ys, ye) writes a slot that
             // either is reloaded before it is read again (rows below ys) or only
@@ -363,7 +367,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.wedge) w = sxl * self;
                     }
                     T nn = P0[kp], ss = P0[km];
-                    if constexpr (C::VISIT && s == NU) ss = SV0;  // row below, before its prolongation
+                    if constexpr (C::PRE0 > 0 && s == C::PRE0) ss = SV0;  // row below, before its prolongation
                     if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
@@ -377,7 +381,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                         if (tl.eedge) e = sxh * self;
                     }
                     T nn = P1[kp], ss = P1[km];
-                    if constexpr (C::VISIT && s == NU) ss = SV1;  // row below, before its prolongation
+                    if constexpr (C::PRE0 > 0 && s == C::PRE0) ss = SV1;  // row below, before its prolongation
                     if constexpr (YBR) {
                         if (y == nm) nn = syh * self;
                         if (y == 0) ss = syl * self;
@@ -386,16 +390,28 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 }
             };
             if constexpr (FUSED) {
-                // stages 1-4 finish the post-smoothing of row t-4; before stage 5
-                // touches row t-5, take the residual norm of row t-5 (rows t-6
-                // .. t-4 all after stage 4; row t-6 from the copy saved one step
-                // ago) and store / save it
-                static_for<1, 5>(stage);
+                // FUSED0: stages 1-4 recompute the pre-smoothing of row t-4
+                // from zero, whose values are kept for the next step's stage 4
+                // (as in a visit) before the prolongation adds to them.  Then
+                // (B = 0 or 4) stages B+1 .. B+4 finish the post-smoothing of
+                // row t-B-4; before stage B+5 touches row t-B-5, take the
+                // residual norm of row t-B-5 (rows t-B-6 .. t-B-4 all after
+                // stage B+4; row t-B-6 from the copy saved one step ago) and
+                // store / save it
+                constexpr int B = C::PRE0;
+                if constexpr (B > 0) {
+                    static_for<1, B + 1>(stage);
+                    constexpr int kq = (k - B + 2 * W) % W;
+                    SV0 = P0[kq];
+                    SV1 = P1[kq];
+                    prolong();
+                }
+                static_for<B + 1, B + 5>(stage);
                 {
-                    const int y = t - 5;
-                    constexpr int kk = (k - 5 + 2 * W) % W;
-                    constexpr int kp = (k - 4 + 2 * W) % W;
-                    constexpr int sv = (k + 1) & 1;  // parity of row t-5 (t - k is even)
+                    const int y = t - B - 5;
+                    constexpr int kk = (k - B - 5 + 2 * W) % W;
+                    constexpr int kp = (k - B - 4 + 2 * W) % W;
+                    constexpr int sv = (k + B + 1) & 1;  // parity of row t-B-5 (t - k is even)
                     const T p0 = P0[kk], p1 = P1[kk];
                     T w0 = from_left(P1[kk]);
                     T e1 = from_right(P0[kk]);
@@ -429,7 +445,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     SA[sv] = p0;
                     SB[sv] = p1;
                 }
-                static_for<5, 2 * NU + 1>(stage);
+                static_for<B + 5, 2 * NU + 1>(stage);
             } else if constexpr (C::VISIT) {
                 // stages 1 .. NU finish the pre-smoothing of row t - NU; its
                 // values are kept (the last pre-smoothing stage of the next
@@ -537,7 +553,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             add((double)F1[kk]);
                         }
                     }
-                    if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
+                    if constexpr (POST == POST_RESTRICT || FUSED) {
                         if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
                             const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
                             if (tl.outl) {
@@ -585,7 +601,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             static_for<0, W>([&](auto kc) { step(kc, std::true_type{}, tb); });
     }
 
-    if constexpr (POST == POST_RESTRICT || POST == POST_FUSED) {
+    if constexpr (POST == POST_RESTRICT || FUSED) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
         if (fst) {

@@ -33,7 +33,7 @@ using namespace ccmg;
 namespace {
 
 constexpr int kMinTy = 8;       // smallest rows-per-tile the shape picker uses
-constexpr int kMinOutw = 104;   // narrowest output width of any march variant (the fused one)
+constexpr int kMinOutw = 100;   // narrowest output width of any march variant (the first fused one)
 constexpr int kStatBlocks = 2048;  // f statistics: workgroups (8 waves per SIMD)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -179,7 +179,7 @@ MarchShape visit_shape_for(int n) {
 
 // Events bracketing finest-level launches while profiling is on.
 struct KernelTimer {
-    static constexpr int kKinds = 9;
+    static constexpr int kKinds = 10;
     static constexpr int kPairs = 1024;
     bool on = false;
     std::vector<hipEvent_t> ev;          // 2 * kPairs
@@ -1568,7 +1568,7 @@ int ccmg_plan_kernel_stats(ccmg_plan *P, ccmg_kernel_stat *out, int max, int *co
     static const char *names[KernelTimer::kKinds] = {"finest_pre", "finest_post", "mixed_finest_pre",
                                                       "mixed_finest_post_ir", "finest_fused",
                                                       "mixed_finest_fused", "cn_rhs", "divergence",
-                                                      "subtract_gradient"};
+                                                      "subtract_gradient", "finest_fused_first"};
     *count = KernelTimer::kKinds;
     for (int k = 0; k < KernelTimer::kKinds && k < max; ++k) {
         std::memset(&out[k], 0, sizeof(out[k]));
@@ -1695,6 +1695,11 @@ struct FusedCtx {
     // then copied to `stats_host`), the solve's separate pass being skipped
     bool first_stats = false;
     double *stats_host = nullptr;
+    // a first pre-smoothing from zero may leave its iterate unstored, the
+    // first fused launch recomputing it (the solve allows at least 2 cycles);
+    // `recompute`: the next fused launch must
+    bool allow_recompute = false;
+    bool recompute = false;
 };
 
 // One V-cycle of the fused driver: [level-0 pre] + levels >= 1 + level-0 end
@@ -1739,7 +1744,10 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
             cx.first_ec = Buf<double>{nullptr, 0};
         } else {
             if (cx.first_stats) a.fstat_part = P->at<double>(lay.fstats);
-            const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? 2.0 : 3.0) + 0.25));
+            cx.recompute = cx.first_zero && cx.allow_recompute && end_fused;
+            if (cx.recompute) a.phi_out = nullptr;
+            const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? (cx.recompute ? 1.0 : 2.0) : 3.0) +
+                                                               0.25));
             e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
             P->tstop(ti);
             if (e == hipSuccess && cx.first_stats) {
@@ -1789,9 +1797,17 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
         a.paux = lay.lev[1].pitch;
         a.partial = P->at<double>(lay.lev[1].fpart);
         a.partial_norm = P->at<double>(lay.normpart);
-        const int ti = P->tstart(4, sizeof(double) * nn * (3.0 + 0.5 + (with_mid ? 1.0 : 0.0)));
-        e = launch_march<double>(a, 4, true, true, POST_FUSED, P->shp_fused, s, &nt);
-        P->tstop(ti);
+        if (cx.recompute) {  // the first cycle's pre-smoothing was not stored: recompute it from f
+            a.phi_in = nullptr;
+            const int ti = P->tstart(9, sizeof(double) * nn * (2.0 + 0.5 + (with_mid ? 1.0 : 0.0)));
+            e = launch_march<double>(a, 6, false, true, POST_FUSED0, P->shp_fused, s, &nt);
+            P->tstop(ti);
+            cx.recompute = false;
+        } else {
+            const int ti = P->tstart(4, sizeof(double) * nn * (3.0 + 0.5 + (with_mid ? 1.0 : 0.0)));
+            e = launch_march<double>(a, 4, true, true, POST_FUSED, P->shp_fused, s, &nt);
+            P->tstop(ti);
+        }
         if (e != hipSuccess) return e;
         cx.f1_count = nt;
         cx.pre_done = true;
@@ -1799,6 +1815,7 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
         cx.next = out;
         cx.cur = out;
     } else {
+        if (cx.recompute) return hipErrorInvalidValue;  // (not reached: recompute only before a fused end)
         a.phi_out = A.p;
         a.pout = A.pitch;
         a.partial = P->at<double>(lay.normpart);
@@ -1983,6 +2000,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (fmg_fused) fx.first_ec = fmg_l1;
     fx.first_stats = stats_late;
     fx.stats_host = P->hpin + CCMG_HISTORY;
+    fx.allow_recompute = P->p.max_cycles >= 2;
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;

@@ -156,8 +156,10 @@ def test_kernel_stats_count_only_launches_that_ran(c):
     stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
     cc.ccmg_plan_profile(plan, False)
     assert r.status == cc.OK
-    counted = sum(stats[k]["launches"] for k in ("finest_pre", "finest_post", "finest_fused"))
+    counted = sum(stats[k]["launches"] for k in ("finest_pre", "finest_post", "finest_fused", "finest_fused_first"))
     assert counted == r.cycles + 1, (counted, r.cycles)
+    # from zero, the first cycle's end recomputes its pre-smoothing (not stored)
+    assert stats["finest_fused_first"]["launches"] == (1 if r.cycles >= 2 else 0)
 
 
 def test_plan_options_round_trip_and_reject_bad_values():
