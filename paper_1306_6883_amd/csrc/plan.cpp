@@ -1240,6 +1240,43 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
         // the visit pair replaces the two launches where it is faster
         if (err == hipSuccess && l < kMaxLevels) P->visit[l] = visit_ok && kbest[2] + kbest[3] < kbest[0] + kbest[1];
     }
+    // Visits, level by level from the top: decided on the coarse part of whole
+    // cycles (levels 1 down, as the fused driver runs them), each form timed
+    // three times, the faster kept.  A launch timed alone misses how it
+    // shares the caches with its neighbours in the cycle, and the small
+    // levels' launches differ by a few microseconds.
+    if (err == hipSuccess && P->p.nu1 == 2 && P->p.nu2 == 2 && lay.lt >= 2) {
+        const int saved = P->opt_visit;
+        P->opt_visit = 1;
+        auto time_cycles = [&](float *best) -> hipError_t {
+            CycleIO<T> io;
+            io.coarse_only = true;
+            io.f1_count = 1;
+            Buf<T> l1{nullptr, 0};
+            io.l1_out = &l1;
+            int nt = 0;
+            hipError_t x = enqueue_cycle<T>(P, io, &nt);  // warm-up
+            if (x == hipSuccess) x = hipEventRecord(e0, s);
+            for (int r = 0; r < 4 && x == hipSuccess; ++r) x = enqueue_cycle<T>(P, io, &nt);
+            if (x == hipSuccess) x = hipEventRecord(e1, s);
+            if (x == hipSuccess) x = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+            if (x == hipSuccess && ms < *best) *best = ms;
+            return x;
+        };
+        for (int l = 1; l < lay.lt && l < kMaxLevels && err == hipSuccess; ++l) {
+            float on = 1e30f, off = 1e30f;
+            for (int round = 0; round < 3 && err == hipSuccess; ++round) {
+                P->visit[l] = false;
+                err = time_cycles(&off);
+                P->visit[l] = true;
+                if (err == hipSuccess) err = time_cycles(&on);
+            }
+            P->visit[l] = on < off;
+        }
+        P->opt_visit = saved;
+    }
     // the fused finest launch (FP64 plans that use it; MIXED plans with
     // several inner cycles per step, in FP32 without norm or kept iterate)
     const bool tune_fused = f64 ? fused_eligible(P) : mixed_inner_max(P) > 1;
