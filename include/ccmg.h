@@ -187,9 +187,13 @@ int ccmg_fmg(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdiff_t pitch,
  *                        runs the two post-smoothing iterations.  Each cell
  *                        of the level is written and read once less; the
  *                        iterates are bitwise those of the two-launch form.
- *                        0: never; 1: on the levels where ccmg_plan_autotune
- *                        found the pair faster (none on an untuned plan);
- *                        2: on every level where it applies.
+ *                        The same holds for the finest level of FP64 solves
+ *                        from zero with the fused launch (at least 2 cycles
+ *                        allowed): the first pre-smoothing stores no iterate
+ *                        and the first fused launch recomputes it from f.
+ *                        0: never; 1: where ccmg_plan_autotune found it
+ *                        faster (nowhere on an untuned plan); 2: wherever it
+ *                        applies.
  * ccmg_plan_set_option returns CCMG_EINVAL for an unknown option or a value
  * outside its range; ccmg_plan_get_option writes the current value. */
 enum { CCMG_OPT_FUSED = 1, CCMG_OPT_FUSED_KEEP = 2, CCMG_OPT_MIXED_INNER = 3, CCMG_OPT_FMG = 4, CCMG_OPT_VISIT = 5 };
@@ -450,11 +454,14 @@ int ccmg_plan_autotune(ccmg_plan *plan, const double *d_f, double *d_phi, ptrdif
  * launch without the stored iterate (as kind 0), kind 5 = the visit launch
  * (row march only, ty even and >= 16 unless it covers the level; ty = 0 sets
  * the level to run its two launches instead, and with CCMG_OPT_VISIT = 1
- * any other ty sets it to run as a visit).  Results do not depend on the
- * shape. */
+ * any other ty sets it to run as a visit).  kind 6 (level 0, FP64): the
+ * first fused launch of a solve from zero that recomputes the first
+ * pre-smoothing (ty as for kind 5; 0: the pre-smoothing is stored and the
+ * ordinary fused launch reads it).  Results do not depend on the shape. */
 int ccmg_plan_set_shape(ccmg_plan *plan, int level, int kind, int ty, int wpb);
-/* One launch shape, kinds as for ccmg_plan_set_shape (kind 5 gives ty = 0,
- * wpb = 1 for a level that does not run as a visit under CCMG_OPT_VISIT = 1). */
+/* One launch shape, kinds as for ccmg_plan_set_shape (kinds 5 and 6 give
+ * ty = 0, wpb = 1 where the recomputing form is not chosen for
+ * CCMG_OPT_VISIT = 1). */
 int ccmg_plan_shape(ccmg_plan *plan, int level, int kind, int *ty, int *wpb);
 /* The fused finest launch's shape: kind 2 (FP64) or 3 (FP32), as for
  * ccmg_plan_set_shape. */

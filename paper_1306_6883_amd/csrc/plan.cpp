@@ -201,6 +201,11 @@ struct ccmg_plan {
     MarchShape shp_pre_v[kMaxLevels], shp_visit[kMaxLevels];
     bool visit[kMaxLevels] = {};
     MarchShape shp_fused{64, 1};  // the fused finest launch (autotuned)
+    // the first fused launch of a solve from zero recomputing the first
+    // pre-smoothing (fused0: the autotuner found that pair faster than a
+    // stored pre-smoothing and the ordinary fused launch)
+    MarchShape shp_fused0{64, 1};
+    bool fused0 = false;
     MarchShape shp_fused32{64, 1};  // ... its FP32 form (inner cycles of a mixed step)
     // options (ccmg_plan_set_option)
     bool opt_fused = true;       // fused finest launch of FP64 V(2,2) solves
@@ -946,6 +951,8 @@ void plan_init_host(ccmg_plan *P, const ccmg_problem &p) {
         P->visit[l] = false;
     }
     P->shp_fused = shape_for(P->lay.lev[0].n);
+    P->shp_fused0 = shape_for(P->lay.lev[0].n);
+    P->fused0 = false;
     P->shp_fused32 = shape_for(P->lay.lev[0].n);
     P->n_bottom = 2;
     P->tcycle = 0;
@@ -1334,6 +1341,59 @@ hipError_t autotune_levels(ccmg_plan *P, const double *d_f, double *d_phi, ptrdi
         }
         if (f64) P->shp_fused = bs;
         else P->shp_fused32 = bs;
+        // FP64: the first cycle's end of a solve from zero, with the first
+        // pre-smoothing stored and the ordinary fused launch, against the
+        // pre-smoothing unstored and the fused launch that recomputes it
+        // (its bands carry 14 halo rows a side instead of 10)
+        if (f64 && err == hipSuccess) {
+            MarchArgs<T> pre{};
+            level_consts(P, 0, pre);
+            pre.f = a.f;
+            pre.pf = a.pf;
+            pre.phi_out = a.phi_out;
+            pre.pout = a.pout;
+            pre.aux = a.aux;
+            pre.paux = a.paux;
+            pre.partial = a.partial;
+            MarchArgs<T> af = a;  // (no kept iterate: the first cycle's end keeps none)
+            af.phi_mid = nullptr;
+            MarchArgs<T> z = af;
+            z.phi_in = nullptr;
+            auto pair = [&](bool recompute, MarchShape sh, float *ms) -> hipError_t {
+                MarchArgs<T> p0 = pre;
+                if (recompute) p0.phi_out = nullptr;
+                int nt;
+                hipError_t x = hipSuccess;
+                for (int r = 0; r <= reps && x == hipSuccess; ++r) {  // the first pair warms up
+                    if (r == 1) x = hipEventRecord(e0, s);
+                    if (x == hipSuccess) x = launch_march<T>(p0, 2, false, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
+                    if (x == hipSuccess)
+                        x = recompute ? launch_march<T>(z, 6, false, true, POST_FUSED0, sh, s, &nt)
+                                      : launch_march<T>(af, 4, true, true, POST_FUSED, sh, s, &nt);
+                }
+                if (x == hipSuccess) x = hipEventRecord(e1, s);
+                if (x == hipSuccess) x = hipEventSynchronize(e1);
+                if (x == hipSuccess) x = hipEventElapsedTime(ms, e0, e1);
+                return x;
+            };
+            float stored = 1e30f, best0 = 1e30f;
+            MarchShape bs0 = P->shp_fused0;
+            err = pair(false, P->shp_fused, &stored);
+            for (const MarchShape &sh : cands) {
+                if (err != hipSuccess) break;
+                if (sh.ty < 16 && sh.ty < n) continue;  // 14 halo rows a side
+                float ms = 1e30f;
+                err = pair(true, sh, &ms);
+                if (err == hipSuccess && ms < best0) {
+                    best0 = ms;
+                    bs0 = sh;
+                }
+            }
+            if (err == hipSuccess) {
+                P->shp_fused0 = bs0;
+                P->fused0 = best0 < stored;
+            }
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1353,7 +1413,19 @@ int ccmg_plan_autotune(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t
 }
 
 int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
-    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 5) return CCMG_EINVAL;
+    if (!P || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 6) return CCMG_EINVAL;
+    if (kind == 6) {  // the first fused launch recomputing the first pre-smoothing; ty = 0: not used
+        const int n = P->lay.lev[0].n;
+        if (level != 0) return CCMG_EINVAL;
+        if (ty == 0) {
+            P->fused0 = false;
+            return CCMG_OK;
+        }
+        if (ty < 2 || (ty & 1) || (ty < 16 && ty < n) || wpb < 1 || wpb > 4) return CCMG_EINVAL;
+        P->shp_fused0 = MarchShape{ty < n ? ty : n, wpb};
+        P->fused0 = true;
+        return CCMG_OK;
+    }
     if (kind == 5) {  // the visit launch; ty = 0: the level runs its two launches instead
         if (level == 0 || level >= P->lay.lt) return CCMG_EINVAL;
         const int n = P->lay.lev[level].n;
@@ -1390,9 +1462,14 @@ int ccmg_plan_set_shape(ccmg_plan *P, int level, int kind, int ty, int wpb) {
 }
 
 int ccmg_plan_shape(ccmg_plan *P, int level, int kind, int *ty, int *wpb) {
-    if (!P || !ty || !wpb || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 5)
+    if (!P || !ty || !wpb || level < 0 || level >= P->lay.L || level >= kMaxLevels || kind < 0 || kind > 6)
         return CCMG_EINVAL;
-    if ((kind == 2 || kind == 3) && level != 0) return CCMG_EINVAL;
+    if ((kind == 2 || kind == 3 || kind == 6) && level != 0) return CCMG_EINVAL;
+    if (kind == 6) {
+        *ty = P->fused0 ? P->shp_fused0.ty : 0;
+        *wpb = P->fused0 ? P->shp_fused0.wpb : 1;
+        return CCMG_OK;
+    }
     if ((kind == 4 || kind == 5) && (level == 0 || level >= P->lay.lt)) return CCMG_EINVAL;
     const MarchShape sh = kind == 0   ? P->shp_pre[level]
                           : kind == 1 ? P->shp_post[level]
@@ -1837,7 +1914,7 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
         if (cx.recompute) {  // the first cycle's pre-smoothing was not stored: recompute it from f
             a.phi_in = nullptr;
             const int ti = P->tstart(9, sizeof(double) * nn * (2.0 + 0.5 + (with_mid ? 1.0 : 0.0)));
-            e = launch_march<double>(a, 6, false, true, POST_FUSED0, P->shp_fused, s, &nt);
+            e = launch_march<double>(a, 6, false, true, POST_FUSED0, P->shp_fused0, s, &nt);
             P->tstop(ti);
             cx.recompute = false;
         } else {
@@ -2037,7 +2114,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (fmg_fused) fx.first_ec = fmg_l1;
     fx.first_stats = stats_late;
     fx.stats_host = P->hpin + CCMG_HISTORY;
-    fx.allow_recompute = P->p.max_cycles >= 2;
+    fx.allow_recompute = P->p.max_cycles >= 2 && (P->opt_visit == 2 || (P->opt_visit == 1 && P->fused0));
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
     if (rho0 <= P->p.rtol) {
         status = CCMG_OK;

@@ -82,13 +82,15 @@ def _row_march_levels(plan: Plan) -> int:
 
 def shapes_of(plan: Plan) -> dict:
     """The plan's launch shapes: per level (pre ty, pre wpb, post ty, post
-    wpb), the fused finest launch in FP64 and FP32, and per level below the
+    wpb), the fused finest launch in FP64 and FP32, per level below the
     finest its visit shapes (restricting ty, wpb, visit ty, wpb; visit ty 0:
-    the level runs its two launches)."""
+    the level runs its two launches), and the first fused launch that
+    recomputes the first pre-smoothing (ty 0: not used)."""
     return {"levels": [list(s) for s in ccmg_plan_shapes(plan)],
             "fused64": list(ccmg_plan_fused_shape(plan, 2)), "fused32": list(ccmg_plan_fused_shape(plan, 3)),
             "visits": [[*ccmg_plan_shape(plan, lv, 4), *ccmg_plan_shape(plan, lv, 5)]
-                       for lv in range(1, _row_march_levels(plan))]}
+                       for lv in range(1, _row_march_levels(plan))],
+            "fused0": list(ccmg_plan_shape(plan, 0, 6))}
 
 
 def apply_shapes(plan: Plan, shapes: dict) -> None:
@@ -100,6 +102,8 @@ def apply_shapes(plan: Plan, shapes: dict) -> None:
     for level, (tp, wp, tv, wv) in enumerate(shapes.get("visits", []), start=1):
         ccmg_plan_set_shape(plan, level, 4, tp, wp)
         ccmg_plan_set_shape(plan, level, 5, tv, wv)
+    if "fused0" in shapes:
+        ccmg_plan_set_shape(plan, 0, 6, *shapes["fused0"])
 
 
 def tuned(plan: Plan, f: torch.Tensor, phi: torch.Tensor, path: str) -> tuple:

@@ -39,12 +39,15 @@ def solve(n, bc, fv, guess=None, options=None, **kw):
 
 @pytest.mark.parametrize("bc", ["DDDD", "NNDD", "DNPP", "PPDD", "PPPP", "NNNN"])
 @pytest.mark.parametrize("n", [64, 512])
-def test_fused_solve_matches_unfused(bc, n):
+@pytest.mark.parametrize("visit", [1, 2])
+def test_fused_solve_matches_unfused(bc, n, visit):
+    """visit = 2: also the first fused launch that recomputes the first
+    pre-smoothing, and every coarse level as a visit (both forms)."""
     fv = W.fourier_modes(n, seed=4, count=16, kmax=8)
     if not exact.is_singular(0.0, bc):
         fv = fv + 0.3  # a mean, where the problem allows one
-    r0, p0, _ = solve(n, bc, fv, options={cc.OPT_FUSED: 0})
-    r1, p1, plan = solve(n, bc, fv)
+    r0, p0, _ = solve(n, bc, fv, options={cc.OPT_FUSED: 0, cc.OPT_VISIT: visit})
+    r1, p1, plan = solve(n, bc, fv, options={cc.OPT_VISIT: visit})
     assert r0.status == r1.status == cc.OK
     assert r0.cycles == r1.cycles
     a, b = valid(p0), valid(p1)
@@ -61,7 +64,8 @@ def test_fused_solve_matches_unfused(bc, n):
     cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
     stats = {k["name"]: k for k in cc.ccmg_plan_kernel_stats(plan)}
     cc.ccmg_plan_profile(plan, False)
-    assert stats["finest_fused"]["launches"] >= r1.cycles - 2
+    assert stats["finest_fused"]["launches"] + stats["finest_fused_first"]["launches"] >= r1.cycles - 1
+    assert stats["finest_fused_first"]["launches"] == (1 if visit == 2 else 0)
     assert 1 <= stats["finest_pre"]["launches"] <= 2
 
 
@@ -149,7 +153,7 @@ def test_kernel_stats_count_only_launches_that_ran(c):
     first pre-smoothing."""
     n = 1024
     fv = W.gaussian_random_field(n, seed=4)
-    r, _, plan = solve(n, "PPPP", fv, alpha=1.0, beta=c / (2.0 * n * n))
+    r, _, plan = solve(n, "PPPP", fv, options={cc.OPT_VISIT: 2}, alpha=1.0, beta=c / (2.0 * n * n))
     cc.ccmg_plan_profile(plan, True)
     phi = dev_field(oracle.field_zeros(n))
     r = cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), phi)
@@ -158,7 +162,8 @@ def test_kernel_stats_count_only_launches_that_ran(c):
     assert r.status == cc.OK
     counted = sum(stats[k]["launches"] for k in ("finest_pre", "finest_post", "finest_fused", "finest_fused_first"))
     assert counted == r.cycles + 1, (counted, r.cycles)
-    # from zero, the first cycle's end recomputes its pre-smoothing (not stored)
+    # from zero (recomputing forms on), the first cycle's end recomputes its
+    # pre-smoothing (not stored)
     assert stats["finest_fused_first"]["launches"] == (1 if r.cycles >= 2 else 0)
 
 

@@ -56,15 +56,27 @@ def solve(n, bc, f, visit, prec=None, fused=1, alpha=0.0, beta=-1.0, shapes=None
 def test_visit_bitwise_equal_to_two_launches(bc, n, form):
     """Whole solves (FP64 with and without the fused finest launch, from
     zero and from the full multigrid start; MIXED, whose coarse levels relax
-    in FP32): the same result, history and cycle count to the bit."""
+    in FP32): the same result, history and cycle count to the bit.  With the
+    fused launch from zero, option 2 also recomputes the first cycle's
+    pre-smoothing in the first fused launch, whose tiles are narrower (14
+    halo columns): its per-tile norm sums group differently, so there the
+    history agrees to rounding, and singular problems (their mean taken from
+    those sums) too."""
     singular = "D" not in bc
     f = rhs(n, 3, singular)
     kw = {"mixed": {"prec": cc.MIXED}, "unfused": {"fused": 0}, "fmg": {"fmg": 1}}.get(form, {})
     a, ra = solve(n, bc, f, 0, **kw)
     b, rb = solve(n, bc, f, 2, **kw)
     assert ra.status == rb.status == cc.OK and ra.cycles == rb.cycles
-    assert np.array_equal(np.array(ra.history[:ra.cycles + 1]), np.array(rb.history[:rb.cycles + 1]), equal_nan=True)
-    assert np.array_equal(a, b)
+    ha, hb = np.array(ra.history[:ra.cycles + 1]), np.array(rb.history[:rb.cycles + 1])
+    if form == "fused":  # (singular: residuals near the FP64 floor follow the mean's rounding)
+        assert np.allclose(ha, hb, rtol=1e-3 if singular else 1e-12, atol=0)
+    else:
+        assert np.array_equal(ha, hb, equal_nan=True)
+    if form == "fused" and singular:
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+    else:
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("c", [0.1, 1.0, 10.0])
@@ -137,6 +149,29 @@ def test_visit_shape_invariance(bc):
             assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("n", [512, 4096])
+def test_first_fused_launch_recomputing_from_zero(n):
+    """The first fused launch of a solve from zero with the first
+    pre-smoothing recomputed (shape kind 6, any band height; bands of 14 halo
+    rows a side) gives the bits of the stored form, and the autotuner's choice
+    too."""
+    f = rhs(n, 9, False)
+    ref, r0 = solve(n, "DDNN", f, 0)
+
+    def fixed(ty, wpb):
+        def apply(plan):
+            cc.ccmg_plan_set_shape(plan, 0, 6, ty, wpb)
+        return apply
+
+    def tuned(plan):
+        cc.ccmg_plan_autotune(plan, dev_field(oracle.embed(f)), dev_field(oracle.field_zeros(n)))
+
+    for shapes in (fixed(16, 1), fixed(94, 2), fixed(512, 4), tuned):
+        got, r = solve(n, "DDNN", f, 1, shapes=shapes)
+        assert r.status == cc.OK and r.cycles == r0.cycles
+        assert np.array_equal(got, ref)
+
+
 def test_visit_options_and_shapes_rejected():
     plan = cc.Plan(cc.Problem(n=512, bc="D"))
     assert cc.ccmg_plan_get_option(plan, cc.OPT_VISIT) == 1.0
@@ -158,3 +193,12 @@ def test_visit_options_and_shapes_rejected():
     assert cc.ccmg_plan_shape(plan, 2, 5)[0] == 0
     cc.ccmg_plan_set_shape(plan, 3, 4, 0, 1)  # 2-D tiles for the restricting launch of 64^2
     assert cc.ccmg_plan_shape(plan, 3, 4) == (0, 1)
+    # kind 6: the first fused launch recomputing the first pre-smoothing (level 0)
+    assert cc.ccmg_plan_shape(plan, 0, 6) == (0, 1)
+    for level, ty, wpb in ((1, 64, 1), (0, 10, 1), (0, 65, 1), (0, 64, 0)):
+        with pytest.raises(cc.CcmgError):
+            cc.ccmg_plan_set_shape(plan, level, 6, ty, wpb)
+    cc.ccmg_plan_set_shape(plan, 0, 6, 128, 2)
+    assert cc.ccmg_plan_shape(plan, 0, 6) == (128, 2)
+    cc.ccmg_plan_set_shape(plan, 0, 6, 0, 1)
+    assert cc.ccmg_plan_shape(plan, 0, 6) == (0, 1)
