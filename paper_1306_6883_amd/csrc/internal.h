@@ -82,6 +82,10 @@ struct MarchArgs {
     // the tile's output cells: sum f, sum |f|, sum f^2 over finite values and
     // the count of non-finite ones (f as loaded, before any mean shift)
     double *fstat_part;
+    // POST_RESTRICT with LOADPHI: if set, per tile (2 * tile + q) the sums
+    // (r^2, phi) of the residual of the loaded iterate, before any relaxation
+    // (the residual norm of a solve's starting guess); no mean shift may apply
+    double *in_norm_part;
 };
 
 // One unit of work of a batched launch: tile `tile` of level descriptor `desc`.

@@ -252,6 +252,13 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     // POST_RESTRICT with fstat_part: statistics of f over the output cells
     const bool fst = POST == POST_RESTRICT && a.fstat_part != nullptr;
     double fs = 0.0, fa = 0.0, f2 = 0.0, fbad = 0.0;
+    // POST_RESTRICT from a loaded iterate with in_norm_part: the residual
+    // norm sums of the iterate as loaded, and the loaded values of the row
+    // below the one whose residual is taken (stage 1 has already changed
+    // that row in its window slot)
+    const bool innorm = POST == POST_RESTRICT && LOADPHI && a.in_norm_part != nullptr;
+    double accI0 = 0.0, accI1 = 0.0;
+    T SI0 = T(0), SI1 = T(0);
     // POST_FUSED (and FUSED0): norm sums after the post-smoothing, and that
     // state of the previous row (the row below the one whose residual is taken)
     constexpr bool FUSED = POST == POST_FUSED || POST == POST_FUSED0;
@@ -347,6 +354,43 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 P1[kq] = P1[kq] + ((c0 + T(0.25) * mx) + dy * my);
             };
             if constexpr (PROLONG && C::PRE0 == 0) prolong();
+            // 2b. residual of row t-1 as loaded (rows t and t-1 still are;
+            // row t-2 from the copy kept one step ago)
+            if constexpr (POST == POST_RESTRICT && LOADPHI) {
+                if (innorm) {
+                    const int y = t - 1;
+                    constexpr int kk = (k - 1 + W) % W;
+                    const T p0 = P0[kk], p1 = P1[kk];
+                    T w0 = from_left(P1[kk]);
+                    T e1 = from_right(P0[kk]);
+                    if constexpr (XB) {
+                        if (tl.wedge) w0 = sxl * p0;
+                        if (tl.eedge) e1 = sxh * p1;
+                    }
+                    T n0 = P0[k], n1 = P1[k], s0 = SI0, s1 = SI1;
+                    if constexpr (YBR) {
+                        if (y == nm) {
+                            n0 = syh * p0;
+                            n1 = syh * p1;
+                        }
+                        if (y == 0) {
+                            s0 = syl * p0;
+                            s1 = syl * p1;
+                        }
+                    }
+                    if (inrow(y) && tl.outl) {
+                        const T ih2 = a.ih2;
+                        const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                        const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                        const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
+                        const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
+                        accI0 += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+                        accI1 += (double)p0 + (double)p1;
+                    }
+                    SI0 = p0;
+                    SI1 = p1;
+                }
+            }
             // 3. relaxation stages: stage s works on row t - s; odd s = red, even s = black.
             // Unconditional: a stage on a row outside [ys, ye) writes a slot that
             // either is reloaded before it is read again (rows below ys) or only
@@ -604,6 +648,13 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     if constexpr (POST == POST_RESTRICT || FUSED) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
+        if (innorm) {
+            const double q0 = wave_sum(accI0), q1 = wave_sum(accI1);
+            if (lane == 0) {
+                a.in_norm_part[2 * tile] = q0;
+                a.in_norm_part[2 * tile + 1] = q1;
+            }
+        }
         if (fst) {
             const double q0 = wave_sum(fs), q1 = wave_sum(fa), q2 = wave_sum(f2), q3 = wave_sum(fbad);
             if (lane == 0) {

@@ -1809,6 +1809,9 @@ struct FusedCtx {
     // then copied to `stats_host`), the solve's separate pass being skipped
     bool first_stats = false;
     double *stats_host = nullptr;
+    // the first pre-smoothing (from a guess) also takes the guess's residual
+    // norm, filed as the history's entry 0 (the solve's separate pass skipped)
+    bool first_norm = false;
     // a first pre-smoothing from zero may leave its iterate unstored, the
     // first fused launch recomputing it (the solve allows at least 2 cycles);
     // `recompute`: the next fused launch must
@@ -1858,6 +1861,8 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
             cx.first_ec = Buf<double>{nullptr, 0};
         } else {
             if (cx.first_stats) a.fstat_part = P->at<double>(lay.fstats);
+            const bool first_norm = cx.first_norm && !cx.first_zero;
+            if (first_norm) a.in_norm_part = P->at<double>(lay.normpart);
             cx.recompute = cx.first_zero && cx.allow_recompute && end_fused;
             if (cx.recompute) a.phi_out = nullptr;
             const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? (cx.recompute ? 1.0 : 2.0) : 3.0) +
@@ -1866,9 +1871,15 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
             P->tstop(ti);
             if (e == hipSuccess && cx.first_stats) {
                 e = launch_reduce4(P->at<double>(lay.fstats), nt, P->scal() + S_FSUM, s);
+                // the guess's residual norm -> history entry 0 (a guess within
+                // the tolerance sets the done flag: the rest of the cycle does nothing)
+                if (e == hipSuccess && first_norm)
+                    e = launch_cycle_end(P->at<double>(lay.normpart), nt, lay.lev[0].n, 0, P->scal() + S_F2,
+                                         P->p.rtol, P->hist(), P->scal() + S_PHIMEAN, P->done(), P->drho, s);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(cx.stats_host, P->scal(), sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
                 cx.first_stats = false;
+                cx.first_norm = false;
             }
         }
         if (e != hipSuccess) return e;
@@ -2026,10 +2037,16 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     // does not wait for the host before the first cycle (on a bad f that
     // cycle's results are dropped)
     const bool stats_late = !use_guess && !mixed && P->opt_fmg == 0 && fused_eligible(P) && P->p.max_cycles > 0;
+    // ... and from a guess (non-singular problems, no rejection bound): the
+    // first launch also takes the guess's residual norm, read with the first
+    // cycle's (the first cycle's end then waits for it on the host)
+    const bool guess_late = use_guess && !mixed && fused_eligible(P) && P->p.max_cycles > 0 && !P->singular &&
+                            !std::isfinite(guess_reject);
+    const bool late = stats_late || guess_late;
     if (e == hipSuccess && fmg_f1)
         e = launch_fstats_restrict(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM,
                                    P->at<double>(lay.lev[1].f), lay.lev[1].pitch, s);
-    else if (e == hipSuccess && !stats_late)
+    else if (e == hipSuccess && !late)
         e = launch_fstats(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM, s);
     // full multigrid start (FP64 solves without a guess, option CCMG_OPT_FMG):
     // its last launch also gives the starting residual, as a guess's would
@@ -2044,7 +2061,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     MixedState st = mixed_state(P, d_phi, pitch, !use_guess);
     if (e == hipSuccess && mixed) {
         e = enqueue_mixed_start(P, d_f, pitch, st, use_guess != 0, 0);  // r32, rho0 -> hist[0]
-    } else if (e == hipSuccess && use_guess) {
+    } else if (e == hipSuccess && use_guess && !guess_late) {
         MarchArgs<double> a{};
         level_consts(P, 0, a);
         a.f = d_f;
@@ -2058,10 +2075,10 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             e = launch_cycle_end(P->at<double>(lay.normpart), nt, n, P->singular ? 1 : 0, scal + S_F2,
                                  P->p.rtol, P->hist(), scal + S_PHIMEAN, P->done(), P->drho, s);
     }
-    if (e == hipSuccess && !stats_late)
+    if (e == hipSuccess && !late)
         e = hipMemcpyAsync(P->hpin + CCMG_HISTORY, scal, sizeof(double) * kScal, hipMemcpyDeviceToHost, s);
     Buf<double> fmg_l1{nullptr, 0};
-    if (stats_late) {
+    if (late) {
         // checked after the first cycle (below)
     } else if (fmg_fused) {
         // the full multigrid pass (workspace only) is queued before the host
@@ -2091,16 +2108,16 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         if (x == hipSuccess) x = hipStreamSynchronize(s);
         return x == hipSuccess ? st : CCMG_EHIP;
     };
-    if (!stats_late) {
+    if (!late) {
         const int st = check_f();
         if (st != kGoOn) return R->status = st;
     }
 
-    const double rho0 = fmg_fused ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
+    const double rho0 = (fmg_fused || guess_late) ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
     if (use_guess && std::isfinite(guess_reject) && !(rho0 <= guess_reject)) return R->status = kGuessRejected;
-    if (!fmg_fused && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
+    if (!fmg_fused && !guess_late && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
     int status = CCMG_NOT_CONVERGED;
     int cycles = 0;
     double rho = rho0;
@@ -2112,7 +2129,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const double keep = P->opt_fused_keep;
     FusedCtx fx{Buf<double>{d_phi, pitch}, false, !guess, 0, Buf<double>{nullptr, 0}, Buf<double>{nullptr, 0}};
     if (fmg_fused) fx.first_ec = fmg_l1;
-    fx.first_stats = stats_late;
+    fx.first_stats = late;
+    fx.first_norm = guess_late;
     fx.stats_host = P->hpin + CCMG_HISTORY;
     fx.allow_recompute = P->p.max_cycles >= 2 && (P->opt_visit == 2 || (P->opt_visit == 1 && P->fused0));
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);
@@ -2212,7 +2230,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 const bool check_first =  // queue k+1 only after reading k
                     (mixed && inner_max > 1)
                         ? (k == 1 || mixed_pred(k + 1) <= 0.5 * P->p.rtol)
-                        : (k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol);
+                        : ((guess_late && k == 1) ||  // (the guess's residual comes with cycle 1's)
+                           (k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol));
                 if (!check_first) {
                     e = enqueue(k + 1);
                     queued = k + 1;
@@ -2221,11 +2240,26 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             if (e != hipSuccess) break;
             e = hipEventSynchronize(P->ev_sync[k & 1]);
             if (e != hipSuccess) break;
-            if (stats_late && k == 1) {  // f's statistics came with the first cycle
+            if (late && k == 1) {  // f's statistics (and the guess's residual) came with the first cycle
                 const int st = check_f();
                 if (st != kGoOn) {
                     std::memset(R, 0, sizeof(*R));
                     return R->status = st;
+                }
+                if (guess_late) {
+                    const double r0 = P->hrho[0];
+                    R->rel_resid0 = r0;
+                    R->history[0] = r0;
+                    rhos[0] = r0;
+                    if (!std::isfinite(r0)) {  // (the device skipped the cycle)
+                        e = hipStreamSynchronize(s);
+                        return R->status = e == hipSuccess ? CCMG_ENONFINITE : CCMG_EHIP;
+                    }
+                    if (r0 <= P->p.rtol) {  // the guess meets the tolerance: the cycle did nothing
+                        rho = r0;
+                        status = CCMG_OK;
+                        break;
+                    }
                 }
             }
             rho = P->hrho[k];  // written by the step's last kernel (host-mapped)

@@ -213,3 +213,36 @@ def test_statistics_from_the_first_cycle(max_cycles):
     r = cc.ccmg_solve(plan, dev_field(oracle.embed(fv)), d_phi)
     assert r.status == (cc.OK if max_cycles == 100 else cc.NOT_CONVERGED) and r.cycles == min(max_cycles, r1.cycles)
     assert abs(r.history[1] - r1.history[1]) <= 1e-12 * r1.history[1]
+
+
+@pytest.mark.parametrize("bc", ["DDNN", "DNPP"])
+def test_guess_residual_from_the_first_launch(bc):
+    """Non-singular FP64 solves from a guess take the guess's residual norm
+    (and f's statistics) in the first pre-smoothing launch and read it with
+    the first cycle's: the same iterates as the unfused solve (which takes
+    them in separate passes before the first cycle), its history to rounding;
+    a guess already within the tolerance returns unchanged after 0 cycles,
+    a non-finite guess gives ENONFINITE."""
+    n = 512
+    kw = {"alpha": 1.0, "beta": 2.0 / (2.0 * n * n)}
+    fv = W.gaussian_random_field(n, seed=6)
+    guess = 0.5 * np.random.default_rng(3).standard_normal((n, n))
+    r0, p0, _ = solve(n, bc, fv, guess, options={cc.OPT_FUSED: 0}, **kw)
+    r1, p1, plan = solve(n, bc, fv, guess, **kw)
+    assert r0.status == r1.status == cc.OK and r0.cycles == r1.cycles
+    assert np.array_equal(valid(p0), valid(p1))
+    assert np.allclose(r0.history, r1.history, rtol=1e-12, atol=0)
+    assert abs(r1.rel_resid0 - r0.rel_resid0) <= 1e-12 * r0.rel_resid0
+    # the converged field as the guess: 0 cycles, the field unchanged
+    f = dev_field(oracle.embed(fv))
+    before = p1.clone()
+    r = cc.ccmg_solve(plan, f, p1, use_guess=True)
+    assert r.status == cc.OK and r.cycles == 0 and r.rel_resid0 <= 1e-10
+    assert torch.equal(p1[1:n + 1, 1:n + 1], before[1:n + 1, 1:n + 1])
+    bad = p1.clone()
+    bad[200, 300] = float("nan")
+    with pytest.raises(cc.CcmgError) as e:
+        cc.ccmg_solve(plan, f, bad, use_guess=True)
+    assert e.value.status == cc.ENONFINITE
+    r = cc.ccmg_solve(plan, f, p1, use_guess=True)  # the plan goes on as before
+    assert r.status == cc.OK and r.cycles == 0
