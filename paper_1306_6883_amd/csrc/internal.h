@@ -28,9 +28,13 @@ enum Post {
                         // from zero (recomputed: the restricting launch of the way down then
                         // stores no iterate), the prolongation of the coarse correction, the
                         // two post-smoothing iterations; stores the result
-    POST_FUSED0 = 8     // (finest level, NU = 6, from zero) the first fused launch of a solve
+    POST_FUSED0 = 8,    // (finest level, NU = 6, from zero) the first fused launch of a solve
                         // from zero: the first cycle's two pre-smoothing iterations recomputed
                         // from zero as in POST_VISIT, then everything POST_FUSED does
+    POST_CNPRE = 9      // (finest level, FP64, NU = 2, from a loaded iterate) POST_RESTRICT
+                        // whose right-hand side is the Crank-Nicolson one of the loaded
+                        // iterate, f = phi + cn_beta Lap phi, formed here and written to cn_f
+                        // (not loaded)
 };
 
 // Arguments of one row-march launch over one grid level (see march.hip).
@@ -86,6 +90,10 @@ struct MarchArgs {
     // (r^2, phi) of the residual of the loaded iterate, before any relaxation
     // (the residual norm of a solve's starting guess); no mean shift may apply
     double *in_norm_part;
+    // POST_CNPRE: the right-hand side formed from the loaded iterate goes here
+    T *cn_f;
+    int pcnf;
+    T cn_beta;
 };
 
 // One unit of work of a batched launch: tile `tile` of level descriptor `desc`.
@@ -133,6 +141,8 @@ hipError_t dispatch_fused(const MarchArgs<double> &a, MarchShape sh, hipStream_t
 hipError_t dispatch_fused(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
 // The first fused launch of a solve from zero (POST_FUSED0; march_f64_fused.hip).
 hipError_t dispatch_fused0(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
+// The first pre-smoothing of a Crank-Nicolson step (POST_CNPRE; march_f64_cn.hip).
+hipError_t dispatch_cnpre(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 // A coarse level's whole visit (POST_VISIT; march_visit.hip).
 hipError_t dispatch_visit(const MarchArgs<double> &a, MarchShape sh, hipStream_t s, int *nt);
 hipError_t dispatch_visit(const MarchArgs<float> &a, MarchShape sh, hipStream_t s, int *nt);
@@ -244,6 +254,6 @@ const ccmg_problem *plan_problem(const ccmg_plan *P);
 // ccmg_solve with a bound on the guess's relative residual (see plan.cpp).
 constexpr int kGuessRejected = 100;
 int solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess, ccmg_result *out,
-               double guess_reject);
+               double guess_reject, double *cn_f = nullptr);
 
 }  // namespace ccmg

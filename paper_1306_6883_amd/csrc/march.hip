@@ -14,6 +14,14 @@ hipError_t launch_march(const MarchArgs<T> &a, int nu, bool load_phi, bool prolo
             return dispatch_fused(a, shape, s, nt);
         return hipErrorInvalidValue;
     }
+    if (post == POST_CNPRE) {
+        if constexpr (std::is_same<T, double>::value) {
+            if (nu == 2 && load_phi && !prolong && shape.ty >= 2 && !(shape.ty & 1) && shape.wpb >= 1 &&
+                shape.wpb <= 4)
+                return dispatch_cnpre(a, shape, s, nt);
+        }
+        return hipErrorInvalidValue;
+    }
     if (post == POST_FUSED0) {
         if constexpr (std::is_same<T, double>::value) {
             if (nu == 6 && !load_phi && prolong && shape.ty >= 2 && !(shape.ty & 1) && shape.wpb >= 1 &&

@@ -153,6 +153,9 @@ template <typename T, int NU, bool LOADPHI, bool PROLONG, int POST, bool XB, boo
 __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl, const int tile) {
     using C = Cfg<NU, PROLONG, POST>;
     constexpr int W = C::W, D = C::D, WC = C::WC, DC = C::DC;
+    // POST_CNPRE: POST_RESTRICT with f formed from the loaded iterate
+    constexpr bool CNF = POST == POST_CNPRE;
+    constexpr bool RESTR = POST == POST_RESTRICT || CNF;
     const int lane = threadIdx.x & 63;
     const int nm = tl.nm, nc = tl.nc;
     const bool py = tl.py;
@@ -223,9 +226,11 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     auto load_row = [&](int y, T &p0, T &p1, T &f0, T &f1) {
         y = min(y, ye - 1);
         const int yy = py ? (y & nm) : y;
-        const T *fr = a.f + row_off(yy + 1, a.pf);
-        f0 = fr[lo];
-        f1 = fr[lo + 1];
+        if constexpr (!CNF) {  // (CNPRE forms f from phi)
+            const T *fr = a.f + row_off(yy + 1, a.pf);
+            f0 = fr[lo];
+            f1 = fr[lo + 1];
+        }
         if (LOADPHI) {
             const T *pr = a.phi_in + row_off(yy + 1, a.pin);
             p0 = pr[lo];
@@ -250,13 +255,13 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
     double acc0 = 0.0, acc1 = 0.0;
     T rprev0 = T(0), rprev1 = T(0);
     // POST_RESTRICT with fstat_part: statistics of f over the output cells
-    const bool fst = POST == POST_RESTRICT && a.fstat_part != nullptr;
+    const bool fst = RESTR && a.fstat_part != nullptr;
     double fs = 0.0, fa = 0.0, f2 = 0.0, fbad = 0.0;
     // POST_RESTRICT from a loaded iterate with in_norm_part: the residual
     // norm sums of the iterate as loaded, and the loaded values of the row
     // below the one whose residual is taken (stage 1 has already changed
     // that row in its window slot)
-    const bool innorm = POST == POST_RESTRICT && LOADPHI && a.in_norm_part != nullptr;
+    const bool innorm = RESTR && LOADPHI && a.in_norm_part != nullptr;
     double accI0 = 0.0, accI1 = 0.0;
     T SI0 = T(0), SI1 = T(0);
     // POST_FUSED (and FUSED0): norm sums after the post-smoothing, and that
@@ -354,9 +359,45 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                 P1[kq] = P1[kq] + ((c0 + T(0.25) * mx) + dy * my);
             };
             if constexpr (PROLONG && C::PRE0 == 0) prolong();
+            // 2a. CNPRE: f of row t-1 = phi + beta Lap phi of the loaded
+            // iterate (rows t and t-1 are still as loaded; row t-2 from the
+            // copy kept one step ago), Lap as differences from the centre in
+            // the order east, west, north, south; stored for the later launches
+            if constexpr (CNF) {
+                const int y = t - 1;
+                constexpr int kk = (k - 1 + W) % W;
+                const T p0 = P0[kk], p1 = P1[kk];
+                T w0 = from_left(P1[kk]);
+                T e1 = from_right(P0[kk]);
+                if constexpr (XB) {
+                    if (tl.wedge) w0 = sxl * p0;
+                    if (tl.eedge) e1 = sxh * p1;
+                }
+                T n0 = P0[k], n1 = P1[k], s0 = SI0, s1 = SI1;
+                if constexpr (YBR) {
+                    if (y == nm) {
+                        n0 = syh * p0;
+                        n1 = syh * p1;
+                    }
+                    if (y == 0) {
+                        s0 = syl * p0;
+                        s1 = syl * p1;
+                    }
+                }
+                const T ih2 = a.ih2;
+                const T lap0 = ((((p1 - p0) + (w0 - p0)) + (n0 - p0)) + (s0 - p0)) * ih2;
+                const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
+                F0[kk] = p0 + a.cn_beta * lap0;
+                F1[kk] = p1 + a.cn_beta * lap1;
+                if (inrow(y)) store_row(a.cn_f + row_off(y + 1, a.pcnf), F0[kk], F1[kk]);
+                if (!innorm) {
+                    SI0 = p0;
+                    SI1 = p1;
+                }
+            }
             // 2b. residual of row t-1 as loaded (rows t and t-1 still are;
             // row t-2 from the copy kept one step ago)
-            if constexpr (POST == POST_RESTRICT && LOADPHI) {
+            if constexpr (RESTR && LOADPHI) {
                 if (innorm) {
                     const int y = t - 1;
                     constexpr int kk = (k - 1 + W) % W;
@@ -582,7 +623,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
                     const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
                     const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
-                    if constexpr (POST == POST_RESTRICT) {
+                    if constexpr (RESTR) {
                         if (fst && tl.outl) {
                             auto add = [&](double v) {
                                 if (!isfinite(v)) {
@@ -597,7 +638,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                             add((double)F1[kk]);
                         }
                     }
-                    if constexpr (POST == POST_RESTRICT || FUSED) {
+                    if constexpr (RESTR || FUSED) {
                         if constexpr ((k - C::LAGR) & 1) {  // odd row: close the 2x2 block
                             const T v = T(0.25) * (((rprev0 + rprev1) + r0) + r1);
                             if (tl.outl) {
@@ -645,7 +686,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             static_for<0, W>([&](auto kc) { step(kc, std::true_type{}, tb); });
     }
 
-    if constexpr (POST == POST_RESTRICT || FUSED) {
+    if constexpr (RESTR || FUSED) {
         const double s = wave_sum(acc0);
         if (lane == 0) a.partial[tile] = s;
         if (innorm) {

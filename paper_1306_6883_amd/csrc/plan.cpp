@@ -1634,6 +1634,10 @@ int ccmg_cn_step(ccmg_plan *P, double *d_phi, double *d_work, ptrdiff_t pitch, c
     ccmg_result *R = out ? out : &local;
     std::memset(R, 0, sizeof(*R));
     if (!P || !d_phi || !d_work || d_phi == d_work || P->p.alpha != 1.0) return R->status = CCMG_EINVAL;
+    // FP64 solves with the fused launch form the right-hand side in their
+    // first pre-smoothing launch (which loads the old level anyway)
+    if (P->p.prec == CCMG_FP64 && fused_eligible(P) && P->p.max_cycles > 0 && !P->singular)
+        return solve_impl(P, d_work, d_phi, pitch, 1, R, INFINITY, d_work);
     const int st = ccmg_cn_rhs(P, d_phi, d_work, pitch);
     if (st != CCMG_OK) return R->status = st;
     return ccmg_solve(P, d_work, d_phi, pitch, 1, R);
@@ -1812,6 +1816,9 @@ struct FusedCtx {
     // the first pre-smoothing (from a guess) also takes the guess's residual
     // norm, filed as the history's entry 0 (the solve's separate pass skipped)
     bool first_norm = false;
+    // Crank-Nicolson step: the first pre-smoothing (from the old level) forms
+    // the right-hand side phi + beta Lap phi itself and writes it here
+    double *cn_f = nullptr;
     // a first pre-smoothing from zero may leave its iterate unstored, the
     // first fused launch recomputing it (the solve allows at least 2 cycles);
     // `recompute`: the next fused launch must
@@ -1865,9 +1872,17 @@ hipError_t enqueue_fused_cycle(ccmg_plan *P, FusedCtx &cx, const double *d_f, lo
             if (first_norm) a.in_norm_part = P->at<double>(lay.normpart);
             cx.recompute = cx.first_zero && cx.allow_recompute && end_fused;
             if (cx.recompute) a.phi_out = nullptr;
+            int post = POST_RESTRICT;
+            if (cx.cn_f && !cx.first_zero) {  // f is formed here, not read
+                a.cn_f = cx.cn_f;
+                a.pcnf = pf;
+                a.cn_beta = P->p.beta;
+                post = POST_CNPRE;
+                cx.cn_f = nullptr;
+            }
             const int ti = P->tstart(0, sizeof(double) * nn * ((cx.first_zero ? (cx.recompute ? 1.0 : 2.0) : 3.0) +
                                                                0.25));
-            e = launch_march<double>(a, 2, !cx.first_zero, false, POST_RESTRICT, P->shp_pre[0], s, &nt);
+            e = launch_march<double>(a, 2, !cx.first_zero, false, post, P->shp_pre[0], s, &nt);
             P->tstop(ti);
             if (e == hipSuccess && cx.first_stats) {
                 e = launch_reduce4(P->at<double>(lay.fstats), nt, P->scal() + S_FSUM, s);
@@ -2012,7 +2027,7 @@ size_t ccmg_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 // finite guess_reject, a guess whose relative residual is not finite or above
 // guess_reject returns kGuessRejected before any cycle runs.
 int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t pitch, int use_guess,
-                     ccmg_result *out, double guess_reject) {
+                     ccmg_result *out, double guess_reject, double *cn_f) {
     ccmg_result local;
     ccmg_result *R = out ? out : &local;
     std::memset(R, 0, sizeof(*R));
@@ -2043,6 +2058,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const bool guess_late = use_guess && !mixed && fused_eligible(P) && P->p.max_cycles > 0 && !P->singular &&
                             !std::isfinite(guess_reject);
     const bool late = stats_late || guess_late;
+    if (cn_f && !guess_late) return R->status = CCMG_EINVAL;  // (callers check first)
     if (e == hipSuccess && fmg_f1)
         e = launch_fstats_restrict(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM,
                                    P->at<double>(lay.lev[1].f), lay.lev[1].pitch, s);
@@ -2131,6 +2147,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     if (fmg_fused) fx.first_ec = fmg_l1;
     fx.first_stats = late;
     fx.first_norm = guess_late;
+    fx.cn_f = cn_f;
     fx.stats_host = P->hpin + CCMG_HISTORY;
     fx.allow_recompute = P->p.max_cycles >= 2 && (P->opt_visit == 2 || (P->opt_visit == 1 && P->fused0));
     std::vector<FusedCtx> fafter(P->p.max_cycles + 2, fx);

@@ -119,3 +119,29 @@ def test_cn_step_rejects_bad_arguments():
     plan1 = cn_plan(n, "NNNN", 1.0)
     with pytest.raises(Exception):
         cc.ccmg_cn_rhs(plan1, d_phi, d_phi)  # in place
+
+
+@pytest.mark.parametrize("bc", ["NNNN", "DDDD", "DNPP", "PPPP"])
+@pytest.mark.parametrize("n", [64, 1024])
+def test_cn_step_forms_the_rhs_in_its_first_launch(bc, n):
+    """FP64 steps with the fused launch form the right-hand side in the first
+    pre-smoothing launch (from the old level it loads anyway): d_work ends up
+    holding exactly ccmg_cn_rhs's right-hand side, and the new level is bitwise
+    that of the separate pass followed by ccmg_solve from the old level."""
+    h = 1.0 / n
+    c = 2.0
+    phi0 = oracle.embed(np.random.default_rng(n + 1).standard_normal((n, n)) + 1.0)
+    plan = cn_plan(n, bc, c, rtol=1e-10)
+    d_phi, d_work = dev_field(phi0), dev_field(np.full((n + 2, n + 2), 7.0))
+    r1 = cc.ccmg_cn_step(plan, d_phi, d_work)
+    ref = cn_plan(n, bc, c, rtol=1e-10)
+    cc.ccmg_plan_set_option(ref, cc.OPT_FUSED, 0)  # (the two-pass form)
+    e_phi, e_f = dev_field(phi0), dev_field(oracle.field_zeros(n))
+    cc.ccmg_cn_rhs(ref, e_phi, e_f)
+    plan2 = cn_plan(n, bc, c, rtol=1e-10)
+    r0 = cc.ccmg_solve(plan2, e_f, e_phi, use_guess=True)
+    torch.cuda.synchronize()
+    assert r1.status == r0.status == cc.OK and r1.cycles == r0.cycles
+    assert np.array_equal(oracle.interior(host(d_work)), oracle.interior(host(e_f)))
+    assert np.array_equal(oracle.interior(host(d_phi)), oracle.interior(host(e_phi)))
+    assert abs(r1.rel_resid0 - r0.rel_resid0) <= 1e-12 * r0.rel_resid0
