@@ -254,8 +254,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
 
     double acc0 = 0.0, acc1 = 0.0;
     T rprev0 = T(0), rprev1 = T(0);
-    // POST_RESTRICT with fstat_part: statistics of f over the output cells
-    const bool fst = RESTR && a.fstat_part != nullptr;
+    // POST_RESTRICT / POST_R32 with fstat_part: statistics of f over the output cells
+    constexpr bool FSTATS = RESTR || POST == POST_R32;
+    const bool fst = FSTATS && a.fstat_part != nullptr;
     double fs = 0.0, fa = 0.0, f2 = 0.0, fbad = 0.0;
     // POST_RESTRICT from a loaded iterate with in_norm_part: the residual
     // norm sums of the iterate as loaded, and the loaded values of the row
@@ -623,7 +624,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
                     const T lap1 = ((((e1 - p1) + (p0 - p1)) + (n1 - p1)) + (s1 - p1)) * ih2;
                     const T r0 = F0[kk] - (a.alpha * p0 - a.beta * lap0);
                     const T r1 = F1[kk] - (a.alpha * p1 - a.beta * lap1);
-                    if constexpr (RESTR) {
+                    if constexpr (FSTATS) {
                         if (fst && tl.outl) {
                             auto add = [&](double v) {
                                 if (!isfinite(v)) {
@@ -720,6 +721,17 @@ __device__ __forceinline__ void march_tile(const MarchArgs<T> &a, const Tile &tl
             a.partial[2 * tile] = s0;
             a.partial[2 * tile + 1] = s1;
             if constexpr (POST != POST_NORM) a.partial3[tile] = s2;
+        }
+        if constexpr (POST == POST_R32) {
+            if (fst) {
+                const double q0 = wave_sum(fs), q1 = wave_sum(fa), q2 = wave_sum(f2), q3 = wave_sum(fbad);
+                if (lane == 0) {
+                    a.fstat_part[4 * tile + 0] = q0;
+                    a.fstat_part[4 * tile + 1] = q1;
+                    a.fstat_part[4 * tile + 2] = q2;
+                    a.fstat_part[4 * tile + 3] = q3;
+                }
+            }
         }
     }
 }

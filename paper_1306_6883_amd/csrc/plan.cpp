@@ -763,7 +763,8 @@ struct MixedState {
 };
 
 // r32 = f - A phi64 in FP64 (and its norm -> hist[slot]); phi64 is not changed.
-hipError_t enqueue_mixed_start(ccmg_plan *P, const double *d_f, long pf, MixedState &st, bool use_guess, int slot) {
+hipError_t enqueue_mixed_start(ccmg_plan *P, const double *d_f, long pf, MixedState &st, bool use_guess, int slot,
+                               double *stats_host = nullptr) {
     MarchArgs<double> a{};
     level_consts(P, 0, a);
     a.f = d_f;
@@ -774,13 +775,19 @@ hipError_t enqueue_mixed_start(ccmg_plan *P, const double *d_f, long pf, MixedSt
     a.pr = st.pr;
     a.partial = P->at<double>(P->lay.normpart);
     a.partial3 = st.s3;
+    // stats_host: f's statistics from this launch's loads too (summed before
+    // the norm needs ||f||, then copied to the host)
+    if (stats_host) a.fstat_part = P->at<double>(P->lay.fstats);
     int nt = 0;
     hipError_t e = launch_march<double>(a, 0, use_guess, false, POST_R32, P->shp_pre[0], P->stream, &nt);
     st.r_tiles = nt;
+    if (e == hipSuccess && stats_host) e = launch_reduce4(P->at<double>(P->lay.fstats), nt, P->scal() + S_FSUM, P->stream);
     if (e == hipSuccess)
         e = launch_cycle_end(P->at<double>(P->lay.normpart), nt, P->lay.lev[0].n, P->singular ? 1 : 0,
                              P->scal() + S_F2, P->p.rtol, P->hist() + slot, P->scal() + S_PHIMEAN, P->done(),
                              P->drho + slot, P->stream);
+    if (e == hipSuccess && stats_host)
+        e = hipMemcpyAsync(stats_host, P->scal(), sizeof(double) * kScal, hipMemcpyDeviceToHost, P->stream);
     return e;
 }
 
@@ -2057,7 +2064,10 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     // cycle's (the first cycle's end then waits for it on the host)
     const bool guess_late = use_guess && !mixed && fused_eligible(P) && P->p.max_cycles > 0 && !P->singular &&
                             !std::isfinite(guess_reject);
-    const bool late = stats_late || guess_late;
+    // ... and MIXED solves: the start pass (the FP64 residual rounded to FP32)
+    // takes f's statistics too, read with the first step's residual
+    const bool mixed_late = mixed && P->p.max_cycles > 0 && !(use_guess && std::isfinite(guess_reject));
+    const bool late = stats_late || guess_late || mixed_late;
     if (cn_f && !guess_late) return R->status = CCMG_EINVAL;  // (callers check first)
     if (e == hipSuccess && fmg_f1)
         e = launch_fstats_restrict(d_f, pitch, n, P->at<double>(lay.fstats), kStatBlocks, scal + S_FSUM,
@@ -2076,7 +2086,8 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     const bool guess = use_guess || fmg;
     MixedState st = mixed_state(P, d_phi, pitch, !use_guess);
     if (e == hipSuccess && mixed) {
-        e = enqueue_mixed_start(P, d_f, pitch, st, use_guess != 0, 0);  // r32, rho0 -> hist[0]
+        e = enqueue_mixed_start(P, d_f, pitch, st, use_guess != 0, 0,  // r32, rho0 -> hist[0]
+                                mixed_late ? P->hpin + CCMG_HISTORY : nullptr);
     } else if (e == hipSuccess && use_guess && !guess_late) {
         MarchArgs<double> a{};
         level_consts(P, 0, a);
@@ -2129,11 +2140,11 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
         if (st != kGoOn) return R->status = st;
     }
 
-    const double rho0 = (fmg_fused || guess_late) ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
+    const double rho0 = (fmg_fused || guess_late || mixed_late) ? NAN : (guess || mixed) ? P->hrho[0] : 1.0;
     R->rel_resid0 = rho0;
     R->history[0] = rho0;
     if (use_guess && std::isfinite(guess_reject) && !(rho0 <= guess_reject)) return R->status = kGuessRejected;
-    if (!fmg_fused && !guess_late && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
+    if (!fmg_fused && !guess_late && !mixed_late && !std::isfinite(rho0)) return R->status = CCMG_ENONFINITE;
     int status = CCMG_NOT_CONVERGED;
     int cycles = 0;
     double rho = rho0;
@@ -2247,7 +2258,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 const bool check_first =  // queue k+1 only after reading k
                     (mixed && inner_max > 1)
                         ? (k == 1 || mixed_pred(k + 1) <= 0.5 * P->p.rtol)
-                        : ((guess_late && k == 1) ||  // (the guess's residual comes with cycle 1's)
+                        : (((guess_late || mixed_late) && k == 1) ||  // (the start's residual comes with cycle 1's)
                            (k >= 3 && rhos[k - 2] > 0.0 && rhos[k - 1] * (rhos[k - 1] / rhos[k - 2]) <= 0.5 * P->p.rtol));
                 if (!check_first) {
                     e = enqueue(k + 1);
@@ -2263,7 +2274,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                     std::memset(R, 0, sizeof(*R));
                     return R->status = st;
                 }
-                if (guess_late) {
+                if (guess_late || mixed_late) {
                     const double r0 = P->hrho[0];
                     R->rel_resid0 = r0;
                     R->history[0] = r0;
@@ -2349,7 +2360,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
     }
     if (mixed) {
         // the FP64 iterate of the last step that ran (or the guess / zero)
-        const MixedState &fin = cycles > 0 ? after[cycles] : st;
+        const MixedState &fin = cycles > 0 ? after[cycles] : after[0];
         if (fin.q_zero) e = hipMemset2DAsync(d_phi, sizeof(double) * pitch, 0, sizeof(double) * (n + 2), n + 2, s);
         else e = copy_valid(d_phi, pitch, fin.q, fin.pq, n, s);
         if (e != hipSuccess) return R->status = CCMG_EHIP;

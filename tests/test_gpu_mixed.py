@@ -213,3 +213,42 @@ def test_mixed_inner_cycles_against_one_cycle_steps(bc):
     assert np.linalg.norm(g3 - g1) / np.linalg.norm(g1) < 1e-9
     if sing:
         assert abs(g3.mean()) < 1e-13 * np.abs(g3).max()
+
+
+@pytest.mark.parametrize("max_cycles", [1, 100])
+def test_mixed_statistics_and_start_residual_from_the_start_pass(max_cycles):
+    """MIXED solves take f's statistics in the start pass (the FP64 residual
+    rounded to FP32) and check them, with the start's residual, once the
+    first step has run: zero f gives phi = 0 and OK, a non-finite f or guess
+    ENONFINITE, an incompatible singular f EINCOMPAT, a guess within the
+    tolerance returns unchanged after 0 steps, and a plan goes on solving."""
+    n = 256
+    plan = mixed_plan(n, "DDNN", rtol=1e-10, max_cycles=max_cycles)
+    phi = dev_field(np.full((n + 2, n + 2), 4.0))
+    r = cc.ccmg_solve(plan, dev_field(oracle.field_zeros(n)), phi)
+    assert r.status == cc.OK and r.cycles == 0 and torch.count_nonzero(phi[:, :n + 2]).item() == 0
+    bad = np.zeros((n, n))
+    bad[17, 3] = np.inf
+    with pytest.raises(cc.CcmgError) as e:
+        cc.ccmg_solve(plan, dev_field(oracle.embed(bad)), phi)
+    assert e.value.status == cc.ENONFINITE
+    with pytest.raises(cc.CcmgError) as e:
+        cc.ccmg_solve(mixed_plan(n, "PPPP", max_cycles=max_cycles), dev_field(oracle.embed(np.ones((n, n)))), phi)
+    assert e.value.status == cc.EINCOMPAT
+    fv = W.fourier_modes(n, seed=2, count=16, kmax=8) + 0.1
+    f = dev_field(oracle.embed(fv))
+    phi = dev_field(oracle.field_zeros(n))
+    r = cc.ccmg_solve(plan, f, phi)
+    if max_cycles == 1:
+        assert r.status == cc.NOT_CONVERGED and r.cycles == 1
+        return
+    assert r.status == cc.OK and r.rel_resid <= 1e-10 and r.rel_resid0 == 1.0
+    before = phi.clone()
+    r = cc.ccmg_solve(plan, f, phi, use_guess=True)
+    assert r.status == cc.OK and r.cycles == 0 and r.rel_resid0 <= 1e-10
+    assert torch.equal(phi[1:n + 1, 1:n + 1], before[1:n + 1, 1:n + 1])
+    nan_guess = phi.clone()
+    nan_guess[9, 9] = float("nan")
+    with pytest.raises(cc.CcmgError) as e:
+        cc.ccmg_solve(plan, f, nan_guess, use_guess=True)
+    assert e.value.status == cc.ENONFINITE
