@@ -28,6 +28,15 @@
 // write phi, plus a quarter cell of coarse rhs (restriction) or coarse
 // correction (prolongation).  Every other intermediate lives in registers.
 //
+// Variants that recompute instead of reading back (internal.h, enum Post):
+// POST_VISIT and POST_FUSED0 start with the pre-smoothing from zero (stages
+// 1-4, on f alone), then prolongate into row t-4 and go on with their other
+// stages, so the launch that ran that pre-smoothing earlier need not store
+// it; POST_CNPRE forms its right-hand side phi + beta Lap phi from the
+// loaded rows instead of loading f.  A first launch of a solve can also sum
+// f's statistics and the residual of the loaded iterate (fstat_part,
+// in_norm_part) from the loads it makes anyway.
+//
 // The output never aliases the input (phi_in != phi_out): a neighbour tile may
 // still read the old values of rows this tile has finished.
 #pragma once
