@@ -30,9 +30,11 @@ def valid(t):
     return t[1:n + 1, 1:n + 1].cpu().numpy()
 
 
-def check_against_transforms(prob, fv, bc, sol_tol=1e-9):
+def check_against_transforms(prob, fv, bc, sol_tol=1e-9, setup=None):
     n = prob.n
     plan = cc.Plan(prob)
+    if setup is not None:  # plan options, set before tuning as the benchmark does
+        setup(plan)
     f, phi = to_dev(fv), to_dev(np.zeros((n, n)))
     cc.ccmg_plan_autotune(plan, f, phi)
     r = cc.ccmg_solve(plan, f, phi)
@@ -94,6 +96,32 @@ def test_mixed_poisson_8192_dirichlet():
     print(f"mixed Poisson n={n} Dirichlet", flush=True)
     fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
     check_against_transforms(cc.Problem(n=n, bc="D", rtol=1e-10, prec=cc.MIXED), fv, "DDDD")
+
+
+@pytest.mark.parametrize("n,side,bc", [(8192, "D", "DDDD"), (4096, "P", "PPPP")])
+def test_full_multigrid_start_full_size(n, side, bc):
+    """The full multigrid start (CCMG_OPT_FMG = 1) on the benchmark's two
+    problems (64 Fourier modes |k| <= 32, seed 0), autotuned with the option
+    set, fused finest launches: the same bar as the zero start, in fewer
+    cycles."""
+    print(f"FMG start n={n} {bc}", flush=True)
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    r = check_against_transforms(cc.Problem(n=n, bc=side, rtol=1e-10), fv, bc,
+                                 setup=lambda plan: cc.ccmg_plan_set_option(plan, cc.OPT_FMG, 1))
+    assert r.cycles <= 9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nb", [4, 8])
+def test_exact_bottom_full_size(nb, prec):
+    """The exact 4^2 or 8^2 bottom solve on the benchmark's 4096^2 periodic
+    problem, FP64 and mixed, autotuned: the returned field (zero mean) against
+    the FFT solve."""
+    n = 4096
+    print(f"exact bottom {nb}^2 n={n} {prec}", flush=True)
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    prob = cc.Problem(n=n, bc="P", rtol=1e-10, prec=cc.FP64 if prec == "fp64" else cc.MIXED)
+    check_against_transforms(prob, fv, "PPPP", setup=lambda plan: cc.ccmg_plan_set_bottom(plan, nb))
 
 
 def test_batched_512_against_oracle_solves():
