@@ -98,7 +98,16 @@ def test_mixed_poisson_8192_dirichlet():
     check_against_transforms(cc.Problem(n=n, bc="D", rtol=1e-10, prec=cc.MIXED), fv, "DDDD")
 
 
-@pytest.mark.parametrize("n,side,bc", [(8192, "D", "DDDD"), (4096, "P", "PPPP")])
+def test_mixed_poisson_4096_periodic():
+    """The mixed form on the 4096^2 periodic Poisson workload (singular: the
+    returned field has zero mean), against the FFT solve."""
+    n = 4096
+    print(f"mixed Poisson n={n} periodic", flush=True)
+    fv = W.fourier_modes(n, seed=0, count=64, kmax=32)
+    check_against_transforms(cc.Problem(n=n, bc="P", rtol=1e-10, prec=cc.MIXED), fv, "PPPP")
+
+
+@pytest.mark.parametrize("n,side,bc",[(8192, "D", "DDDD"), (4096, "P", "PPPP")])
 def test_full_multigrid_start_full_size(n, side, bc):
     """The full multigrid start (CCMG_OPT_FMG = 1) on the benchmark's two
     problems (64 Fourier modes |k| <= 32, seed 0), autotuned with the option
