@@ -225,6 +225,12 @@ struct ccmg_plan {
     bool singular = false;
     double *hpin = nullptr;  // pinned host: relative residual per cycle
     hipEvent_t ev_sync[2] = {nullptr, nullptr};
+    // Events after cycles 2, 3, ... of a solve: the host then reads only the
+    // cycle's residual from hrho, which is fine-grained (coherent) host memory
+    // that the kernel writes directly, so these skip the system-scope fence
+    // (a cache write-back the device otherwise idles for after every cycle);
+    // the statistics copied to hpin are read after cycle 1's fenced event
+    hipEvent_t ev_cyc[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
 
     template <typename T>
@@ -1083,6 +1089,8 @@ int ccmg_plan_create(const ccmg_problem *p, void *d_ws, size_t ws_bytes, void *s
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&P->drho), P->hrho, 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_sync[1], hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&P->ev_cyc[i], hipEventDisableTiming | hipEventDisableSystemFence);
     if (e == hipSuccess) e = hipEventCreate(&P->ev_t0);
     if (e == hipSuccess) e = hipEventCreate(&P->ev_t1);
     if (e != hipSuccess) {
@@ -1764,8 +1772,10 @@ int ccmg_plan_destroy(ccmg_plan *P) {
         if (e) hipEventDestroy(e);
     if (P->hpin) hipHostFree(P->hpin);
     if (P->hrho) hipHostFree(P->hrho);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         if (P->ev_sync[i]) hipEventDestroy(P->ev_sync[i]);
+        if (P->ev_cyc[i]) hipEventDestroy(P->ev_cyc[i]);
+    }
     if (P->ev_t0) hipEventDestroy(P->ev_t0);
     if (P->ev_t1) hipEventDestroy(P->ev_t1);
     delete P;
@@ -2220,6 +2230,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             if (need == inner_max + 1) return need;  // one more cycle than the cap ends the solve
             return std::max(1, std::min(inner_max, need));
         };
+        auto cycle_event = [&](int k) { return k >= 2 ? P->ev_cyc[k & 1] : P->ev_sync[k & 1]; };
         auto enqueue = [&](int k) -> hipError_t {  // cycle / step k (1-based) -> hist[k]
             hipError_t x;
             P->tcycle = k;
@@ -2244,7 +2255,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
             } else {
                 x = enqueue_vcycle64(P, d_f, pitch, d_phi, pitch, k == 1 && !guess, shift, true, k);
             }
-            if (x == hipSuccess) x = hipEventRecord(P->ev_sync[k & 1], s);
+            if (x == hipSuccess) x = hipEventRecord(cycle_event(k), s);
             return x;
         };
         // Cycle k+1 is queued before cycle k's residual is read, so the GPU
@@ -2266,7 +2277,7 @@ int ccmg::solve_impl(ccmg_plan *P, const double *d_f, double *d_phi, ptrdiff_t p
                 }
             }
             if (e != hipSuccess) break;
-            e = hipEventSynchronize(P->ev_sync[k & 1]);
+            e = hipEventSynchronize(cycle_event(k));
             if (e != hipSuccess) break;
             if (late && k == 1) {  // f's statistics (and the guess's residual) came with the first cycle
                 const int st = check_f();
